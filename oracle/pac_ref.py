@@ -1,0 +1,434 @@
+"""Reference definitions of the PAC stochastic aggregates (CPU, fp64, exact ints).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``; never by the GPU library.
+
+Each function names the passage of the paper it follows.  Readings of points
+the paper leaves open are marked "reading:".
+
+Parity pins (see tests/test_oracle_*.py): splitmix64 and Philox4x32-10
+known-answer vectors, m-execution brute force == per-world definition
+(Theorem 2), all-ones / zero / single-bit masks against a plain GROUP BY,
+complement and popcount invariants, ``math.fsum`` for float sums, closed forms
+of the weighted variance and of the posterior after several releases,
+Monte-Carlo moments of the released noise and of the NULL coin.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+U64 = (1 << 64) - 1
+U32 = (1 << 32) - 1
+
+# ---------------------------------------------------------------------------
+# keyed PU hash  (Sec. 2 "SIMD-PAC-DB", Sec. 4.2 "PAC Hash")
+# ---------------------------------------------------------------------------
+# reading: the paper wraps DuckDB's hash() and re-hashes it with a per-query
+# key; here the m-bit vector of key k under query key K is the first m/64
+# outputs of the splitmix64 generator (Steele, Lea, Flood 2014) started at
+# state k XOR K.  Word w holds worlds 64w..64w+63, world j is bit j % 64
+# (least significant bit first).
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64_output(z: int) -> int:
+    """The splitmix64 output function applied to a 64-bit state value."""
+    z &= U64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & U64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & U64
+    return z ^ (z >> 31)
+
+
+def splitmix64_stream(seed: int, count: int) -> List[int]:
+    """First ``count`` outputs of splitmix64 seeded with ``seed``."""
+    state = seed & U64
+    out = []
+    for _ in range(count):
+        state = (state + GOLDEN_GAMMA) & U64
+        out.append(splitmix64_output(state))
+    return out
+
+
+def balance_word(h: int) -> int:
+    """Reading of the optional transform to exactly 32 one-bits (Sec. 2).
+
+    The paper states the property (32 zero and 32 one bits) but not the
+    transform.  Reading: rotate h left by r = output(h) mod 64, then clear the
+    highest surplus one-bits (popcount > 32) or set the highest surplus
+    zero-bits (popcount < 32), then rotate back.
+    """
+    r = splitmix64_output(h) % 64
+    x = ((h << r) | (h >> (64 - r))) & U64 if r else h
+    pc = bin(x).count("1")
+    bit = 63
+    while pc > 32:
+        if (x >> bit) & 1:
+            x &= ~(1 << bit) & U64
+            pc -= 1
+        bit -= 1
+    bit = 63
+    while pc < 32:
+        if not (x >> bit) & 1:
+            x |= 1 << bit
+            pc += 1
+        bit -= 1
+    return ((x >> r) | (x << (64 - r))) & U64 if r else x
+
+
+def pac_hash(key: int, query_key: int, m: int = 64, balanced: bool = False) -> List[int]:
+    """pac_hash_K(pk): list of m/64 words, word w bit b = membership in world 64w+b."""
+    if m not in (64, 128):
+        raise ValueError("m must be 64 or 128")
+    words = splitmix64_stream((key ^ query_key) & U64, m // 64)
+    if balanced:
+        words = [balance_word(w) for w in words]
+    return words
+
+
+def pac_hash_np(keys: np.ndarray, query_key: int, m: int = 64, balanced: bool = False) -> np.ndarray:
+    """Vectorised pac_hash over an int64 key array -> uint64 [n, m/64]."""
+    W = m // 64
+    k = keys.astype(np.int64).view(np.uint64) ^ np.uint64(query_key & U64)
+    out = np.empty((k.shape[0], W), dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        for w in range(W):
+            z = k + np.uint64(((w + 1) * GOLDEN_GAMMA) & U64)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            out[:, w] = z ^ (z >> np.uint64(31))
+    if balanced:
+        for i in range(out.shape[0]):
+            for w in range(W):
+                out[i, w] = np.uint64(balance_word(int(out[i, w])))
+    return out
+
+
+def world_bit(words: Sequence[int], j: int) -> int:
+    return (int(words[j // 64]) >> (j % 64)) & 1
+
+
+# ---------------------------------------------------------------------------
+# the PU column of a scanned relation  (Sec. 2 "Relational Privacy Unit")
+# ---------------------------------------------------------------------------
+def pu_of_rows_star(pu_key: np.ndarray, o_pu: np.ndarray, f_order: np.ndarray, query_key: int,
+                    m: int = 64, balanced: bool = False) -> np.ndarray:
+    """pu = pac_hash(pk reached by fact -> orders -> PU).  Returns uint64 [n, m/64]."""
+    pk = pu_key[o_pu[f_order]]
+    return pac_hash_np(pk, query_key, m, balanced)
+
+
+def pu_of_rows_flat(pu_key: np.ndarray, query_key: int, m: int = 64, balanced: bool = False) -> np.ndarray:
+    return pac_hash_np(pu_key, query_key, m, balanced)
+
+
+def dense_group(gcols: Sequence[np.ndarray], gcards: Sequence[int]) -> np.ndarray:
+    """Mixed-radix dense group id: ((g0 * card1 + g1) * card2 + g2) ..."""
+    n = gcols[0].shape[0] if gcols else 0
+    g = np.zeros(n, dtype=np.int64)
+    for col, card in zip(gcols, gcards):
+        g = g * int(card) + col.astype(np.int64)
+    return g
+
+
+# ---------------------------------------------------------------------------
+# per-world aggregate definition  (Sec. 4.2 "PAC Aggregation", Sec. 1 count loop)
+# ---------------------------------------------------------------------------
+def _exact_group_sum(group: np.ndarray, values: np.ndarray, sel: np.ndarray, G: int) -> np.ndarray:
+    """Exact int64 (mod 2^64) per-group sum of values[sel]: sum of three 22-bit limbs.
+
+    Each limb sum is below 2^53 for fewer than 2^31 rows, so numpy's float64
+    bincount adds it exactly.
+    """
+    u = values.astype(np.int64).view(np.uint64)[sel]
+    g = group[sel]
+    total = np.zeros(G, dtype=np.uint64)
+    for k in range(3):
+        limb = ((u >> np.uint64(22 * k)) & np.uint64((1 << 22) - 1)).astype(np.float64)
+        s = np.bincount(g, weights=limb, minlength=G).astype(np.uint64)
+        with np.errstate(over="ignore"):
+            total += s << np.uint64(22 * k)
+    return total.view(np.int64)
+
+
+def pac_agg_counters(pu: np.ndarray, group: np.ndarray, G: int, int_cols: Sequence[np.ndarray] = (),
+                     float_cols: Sequence[np.ndarray] = (), exact_float: bool = False) -> Dict[str, np.ndarray]:
+    """Per-group, per-world counters of the stochastic aggregates.
+
+    For group g and world j (pac_agg's definition, r_j = agg over the rows
+    whose pu[j] = 1):
+        count[g][j]   = |{t in g : pu[j] = 1}|
+        isum[g][c][j] = sum of int column c over those rows (exact, mod 2^64)
+        fsum[g][c][j] = sum of float column c over those rows
+        nrows[g]      = |{t in g}|  (rows reaching the aggregate)
+    Rows with group < 0 are filtered out.  ``exact_float`` uses math.fsum
+    (correctly rounded) instead of a plain float64 accumulation.
+    """
+    W = pu.shape[1]
+    m = 64 * W
+    valid = group >= 0
+    gv = np.where(valid, group, 0)
+    count = np.zeros((G, m), dtype=np.int64)
+    isum = np.zeros((G, len(int_cols), m), dtype=np.int64)
+    fsum = np.zeros((G, len(float_cols), m), dtype=np.float64)
+    for j in range(m):
+        bit = ((pu[:, j // 64] >> np.uint64(j % 64)) & np.uint64(1)).astype(bool)
+        sel = bit & valid
+        count[:, j] = np.bincount(gv[sel], minlength=G)
+        for c, col in enumerate(int_cols):
+            isum[:, c, j] = _exact_group_sum(gv, col, sel, G)
+        for c, col in enumerate(float_cols):
+            if exact_float:
+                for g in range(G):
+                    fsum[g, c, j] = math.fsum(col[sel & (gv == g)].tolist())
+            else:
+                fsum[:, c, j] = np.bincount(gv[sel], weights=col[sel].astype(np.float64), minlength=G)
+    nrows = np.bincount(gv[valid], minlength=G).astype(np.int64)
+    return {"count": count, "isum": isum, "fsum": fsum, "nrows": nrows}
+
+
+def or_accumulator(pu: np.ndarray, group: np.ndarray, G: int) -> np.ndarray:
+    """K_g = OR of the pu words of the rows of group g (Sec. 3.2 NULLs)."""
+    W = pu.shape[1]
+    acc = np.zeros((G, W), dtype=np.uint64)
+    for r in range(pu.shape[0]):
+        g = int(group[r])
+        if g >= 0:
+            acc[g] |= pu[r]
+    return acc
+
+
+# ---------------------------------------------------------------------------
+# brute force: m executions on m sampled databases  (Sec. 4.1 compile procedure)
+# ---------------------------------------------------------------------------
+def brute_force_star(pu_key: np.ndarray, o_pu: np.ndarray, f_order: np.ndarray, group: np.ndarray,
+                     G: int, int_cols: Sequence[np.ndarray], float_cols: Sequence[np.ndarray],
+                     query_key: int, m: int = 64, balanced: bool = False,
+                     row_filter: Optional[np.ndarray] = None) -> Dict[str, list]:
+    """Execute the plain grouped query once per sampled database instance.
+
+    Step (1): S_j = sigma_{pac_hash_K(pk)[j] = 1}(PU); every relation with a
+    foreign-key path to the PU table is joined with S_j along that path
+    (orders^(j) = orders join S_j, fact^(j) = fact join orders^(j)).
+    Step (2): evaluate the ordinary GROUP BY on each instance, take the
+    multiset union and list the m results per group.  A group that has no row
+    in instance j lists 0 (count) / 0 (sum) there.
+
+    Written with Python sets, dicts and ints so that it can be read against
+    the definition; use on small inputs only.
+    """
+    n_pu = pu_key.shape[0]
+    hashes = [pac_hash(int(pu_key[u]), query_key, m, balanced) for u in range(n_pu)]
+    out_count = [[0] * m for _ in range(G)]
+    out_isum = [[[0] * m for _ in int_cols] for _ in range(G)]
+    out_fsum = [[[0.0] * m for _ in float_cols] for _ in range(G)]
+    for j in range(m):
+        S_j = {u for u in range(n_pu) if world_bit(hashes[u], j)}            # sampled PU instance
+        orders_j = {o for o in range(o_pu.shape[0]) if int(o_pu[o]) in S_j}   # orders join S_j
+        rows_j = [r for r in range(f_order.shape[0])                         # fact join orders_j
+                  if int(f_order[r]) in orders_j
+                  and (row_filter is None or bool(row_filter[r]))]
+        groups: Dict[int, List[int]] = {}
+        for r in rows_j:                                                      # GROUP BY
+            g = int(group[r])
+            if g >= 0:
+                groups.setdefault(g, []).append(r)
+        for g, rs in groups.items():
+            out_count[g][j] = len(rs)
+            for c, col in enumerate(int_cols):
+                s = sum(int(col[r]) for r in rs)
+                out_isum[g][c][j] = ((s + (1 << 63)) % (1 << 64)) - (1 << 63)   # int64 wrap
+            for c, col in enumerate(float_cols):
+                out_fsum[g][c][j] = math.fsum(float(col[r]) for r in rs)
+    return {"count": out_count, "isum": out_isum, "fsum": out_fsum}
+
+
+def brute_force_flat(pu_key_rows: np.ndarray, group: np.ndarray, G: int, int_cols: Sequence[np.ndarray],
+                     float_cols: Sequence[np.ndarray], query_key: int, m: int = 64,
+                     balanced: bool = False) -> Dict[str, list]:
+    """As ``brute_force_star`` for a fact table that carries the PU key itself."""
+    keys = sorted({int(k) for k in pu_key_rows})
+    hashes = {k: pac_hash(k, query_key, m, balanced) for k in keys}
+    out_count = [[0] * m for _ in range(G)]
+    out_isum = [[[0] * m for _ in int_cols] for _ in range(G)]
+    out_fsum = [[[0.0] * m for _ in float_cols] for _ in range(G)]
+    for j in range(m):
+        S_j = {k for k in keys if world_bit(hashes[k], j)}
+        groups: Dict[int, List[int]] = {}
+        for r in range(pu_key_rows.shape[0]):
+            if int(pu_key_rows[r]) in S_j and int(group[r]) >= 0:
+                groups.setdefault(int(group[r]), []).append(r)
+        for g, rs in groups.items():
+            out_count[g][j] = len(rs)
+            for c, col in enumerate(int_cols):
+                s = sum(int(col[r]) for r in rs)
+                out_isum[g][c][j] = ((s + (1 << 63)) % (1 << 64)) - (1 << 63)
+            for c, col in enumerate(float_cols):
+                out_fsum[g][c][j] = math.fsum(float(col[r]) for r in rs)
+    return {"count": out_count, "isum": out_isum, "fsum": out_fsum}
+
+
+# ---------------------------------------------------------------------------
+# counter-based randomness  (reading: the paper does not name its RNG)
+# ---------------------------------------------------------------------------
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> Tuple[int, int, int, int]:
+    """Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11)."""
+    c0, c1, c2, c3 = (int(x) & U32 for x in ctr)
+    k0, k1 = (int(x) & U32 for x in key)
+    for _ in range(10):
+        p0 = PHILOX_M0 * c0
+        p1 = PHILOX_M1 * c2
+        c0, c1, c2, c3 = ((p1 >> 32) ^ c1 ^ k0) & U32, p1 & U32, ((p0 >> 32) ^ c3 ^ k1) & U32, p0 & U32
+        k0 = (k0 + PHILOX_W0) & U32
+        k1 = (k1 + PHILOX_W1) & U32
+    return c0, c1, c2, c3
+
+
+PURPOSE_JSTAR, PURPOSE_NOISE, PURPOSE_NULL = 0, 1, 2
+
+
+def draw64(seed: int, index: int, purpose: int) -> Tuple[int, int]:
+    """Two 64-bit words from Philox keyed by ``seed``, counter (index, purpose, 0)."""
+    x0, x1, x2, x3 = philox4x32_10((index & U32, (index >> 32) & U32, purpose, 0),
+                                   (seed & U32, (seed >> 32) & U32))
+    return x0 | (x1 << 32), x2 | (x3 << 32)
+
+
+def unit_uniform(x: int) -> float:
+    """53 high bits of a 64-bit word as a double in [0, 1)."""
+    return (x >> 11) * (1.0 / 9007199254740992.0)
+
+
+def secret_world(seed: int, m: int) -> int:
+    """j* drawn uniformly from the m worlds (Sec. 4.1 step (2))."""
+    a, _ = draw64(seed, 0, PURPOSE_JSTAR)
+    return a % m
+
+
+def standard_normal(seed: int, cell: int) -> float:
+    """Box-Muller: sqrt(-2 ln(1 - u1)) cos(2 pi u2)."""
+    a, b = draw64(seed, cell, PURPOSE_NOISE)
+    u1, u2 = unit_uniform(a), unit_uniform(b)
+    return math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2.0 * math.pi * u2)
+
+
+def null_uniform(seed: int, cell: int) -> float:
+    a, _ = draw64(seed, cell, PURPOSE_NULL)
+    return unit_uniform(a)
+
+
+# ---------------------------------------------------------------------------
+# release: cell vectors, NULL coin, pac_noised, posterior  (Sec. 4.1, Sec. 3.2, Sec. 5)
+# ---------------------------------------------------------------------------
+KIND_COUNT, KIND_SUM_I, KIND_SUM_F, KIND_AVG_I, KIND_AVG_F = 0, 1, 2, 3, 4
+FLAG_SCALE2 = 1           # release count/sum times 2 (Sec. 2: each world sees about half the rows)
+FLAG_AVG_TOTALCOUNT = 2   # AVG_j = 2 * S_j / n_g instead of S_j / CNT_j
+FLAG_STRICT_DIVERSITY = 4
+FLAG_FIXED_PRIOR = 8      # no posterior update between cells
+CELL_NULL, CELL_DIVERSITY, CELL_ZERO_VARIANCE = 1, 2, 4
+
+
+def cell_vector(counters: Dict[str, np.ndarray], group: int, kind: int, col: int, flags: int) -> np.ndarray:
+    """y_j for one released cell, from the per-world counters (List of m results)."""
+    cnt = counters["count"][group].astype(np.float64)
+    if kind == KIND_COUNT:
+        y = cnt.copy()
+    elif kind in (KIND_SUM_I, KIND_AVG_I):
+        y = counters["isum"][group][col].astype(np.float64)
+    else:
+        y = counters["fsum"][group][col].astype(np.float64)
+    if kind in (KIND_AVG_I, KIND_AVG_F):
+        if flags & FLAG_AVG_TOTALCOUNT:
+            n = float(counters["nrows"][group])
+            y = (2.0 * y) / n if n > 0 else np.zeros_like(y)
+        else:
+            # reading: worlds with no update count as 0 (Sec. 3.2 NULLs)
+            y = np.where(cnt > 0, y / np.where(cnt > 0, cnt, 1.0), 0.0)
+    elif flags & FLAG_SCALE2:
+        y = 2.0 * y
+    return y
+
+
+def popcount_words(words: Sequence[int]) -> int:
+    return sum(bin(int(w)).count("1") for w in words)
+
+
+def diversity_flag(nrows: int, or_pop: int, m: int) -> bool:
+    """Reading of Sec. 5's check: many updates yet about half of the worlds never updated."""
+    return nrows >= 16 and or_pop <= (40 if m == 64 else 80)
+
+
+def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows: Sequence[int], m: int,
+                        budget: float, seed: int, j_star: Optional[int] = None, flags: int = FLAG_SCALE2,
+                        prior: Optional[np.ndarray] = None):
+    """Release the cells in order, each with pac_noised under the running posterior.
+
+    For cell c with world values y (Sec. 4.1, noise function):
+      0. NULL with probability (m - popcount(K))/m (Sec. 3.2); a NULL cell
+         releases nothing and leaves P unchanged (reading).
+      1. s^2 = Var_{j ~ P}[y_j]  (weighted population variance).
+      2. Delta = s^2 / (2B).
+      3. y~ = y_{j*} + N(0, Delta).
+      4. P <- P * W / sum(P * W),  W_j = exp(-(y~ - y_j)^2 / (2 Delta)).
+    Reading: Delta = 0 releases y_{j*} exactly and skips step 4.
+    Returns (values, is_null, cell_flags, final P).
+    """
+    if j_star is None:
+        j_star = secret_world(seed, m)
+    P = np.full(m, 1.0 / m) if prior is None else np.array(prior, dtype=np.float64)
+    vals, nulls, cflags = [], [], []
+    for c, y in enumerate(ys):
+        f = 0
+        if diversity_flag(int(nrows[c]), int(or_pops[c]), m):
+            f |= CELL_DIVERSITY
+            if flags & FLAG_STRICT_DIVERSITY:
+                raise ValueError(f"diversity check failed on cell {c}")
+        p_null = (m - int(or_pops[c])) / m
+        if null_uniform(seed, c) < p_null:
+            vals.append(0.0)
+            nulls.append(1)
+            cflags.append(f | CELL_NULL)
+            continue
+        y = np.asarray(y, dtype=np.float64)
+        mu = float(np.sum(P * y))
+        s2 = float(np.sum(P * (y - mu) ** 2))
+        delta = s2 / (2.0 * budget)
+        if not delta > 0.0:
+            vals.append(float(y[j_star]))
+            nulls.append(0)
+            cflags.append(f | CELL_ZERO_VARIANCE)
+            continue
+        y_rel = float(y[j_star]) + math.sqrt(delta) * standard_normal(seed, c)
+        vals.append(y_rel)
+        nulls.append(0)
+        cflags.append(f)
+        if not flags & FLAG_FIXED_PRIOR:
+            with np.errstate(divide="ignore"):
+                logw = np.log(P) - (y_rel - y) ** 2 / (2.0 * delta)
+            mx = float(np.max(logw))
+            e = np.exp(logw - mx)
+            P = e / float(np.sum(e))
+    return np.array(vals), np.array(nulls, dtype=np.uint8), np.array(cflags, dtype=np.uint32), P
+
+
+def release(counters: Dict[str, np.ndarray], cells: Sequence[Tuple[int, int, int]], m: int, budget: float,
+            seed: int, j_star: Optional[int] = None, flags: int = FLAG_SCALE2,
+            prior: Optional[np.ndarray] = None):
+    """Finalize a list of cells (group, kind, col) against per-world counters.
+
+    K_g is read off the counters: world j received an update of group g iff
+    count[g][j] > 0, which is the OR of the pu words of g's rows.
+    """
+    ys, pops, ns = [], [], []
+    for (g, kind, col) in cells:
+        ys.append(cell_vector(counters, g, kind, col, flags))
+        pops.append(int(np.count_nonzero(counters["count"][g])))
+        ns.append(int(counters["nrows"][g]))
+    vals, nulls, cflags, P = pac_noised_sequence(ys, pops, ns, m, budget, seed, j_star, flags, prior)
+    return vals, nulls, cflags, P, np.array(ys)

@@ -1,0 +1,264 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+* published known-answer vectors of splitmix64 and Philox4x32-10;
+* three independent hash implementations agree (Python ints, numpy, C);
+* the one-pass per-world counters equal the m-execution brute force over the
+  m sampled databases (Theorem 2 / Eq. agg_equiv of the paper);
+* special masks reduce to a plain GROUP BY (textbook aggregate);
+* invariants: popcount totals, complement masks, chunked combine;
+* float sums against math.fsum.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pac_ref as R
+from workloads import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_lines(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [l.split() for l in f if l.strip() and not l.startswith("#")]
+
+
+# ----------------------------------------------------------------------------- hash
+def test_splitmix64_known_answer():
+    want = [int(l[0]) for l in _golden_lines("splitmix64_seed1234567.txt")]
+    assert R.splitmix64_stream(1234567, 5) == want
+
+
+def test_philox_known_answer():
+    for row in _golden_lines("philox4x32_10_kat.txt"):
+        v = [int(x, 16) for x in row]
+        assert R.philox4x32_10(v[0:4], v[4:6]) == tuple(v[6:10])
+
+
+def test_pac_hash_words_are_splitmix_stream():
+    # word w of pac_hash_K(k) is output w+1 of splitmix64 seeded with k ^ K
+    k, K = 987654321, 0x0123456789ABCDEF
+    assert R.pac_hash(k, K, 128) == R.splitmix64_stream(k ^ K, 2)
+
+
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("balanced", [False, True])
+def test_hash_three_implementations_agree(oracle_native, m, balanced):
+    g = np.random.default_rng(5)
+    keys = g.integers(-(1 << 63), (1 << 63) - 1, size=300, dtype=np.int64)
+    keys[:4] = [0, -1, 1, np.iinfo(np.int64).min]
+    K = 0xDEADBEEFCAFEF00D
+    a = R.pac_hash_np(keys, K, m, balanced)
+    b = oracle_native.hash_keys(keys, K, m, balanced)
+    c = np.array([R.pac_hash(int(k), K, m, balanced) for k in keys], dtype=np.uint64)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_mix_is_bijective_on_sample():
+    xs = list(range(0, 200000, 7)) + [(1 << 64) - 1 - i for i in range(1000)]
+    outs = {R.splitmix64_output(x) for x in xs}
+    assert len(outs) == len(set(xs))
+
+
+def test_raw_hash_bits_are_fair():
+    # each bit is 1 with probability 1/2 and the popcount is Binomial(64, 1/2)
+    keys = np.arange(1, 200001, dtype=np.int64)
+    h = R.pac_hash_np(keys, 0x0123456789ABCDEF, 64)[:, 0]
+    bits = ((h[:, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)).astype(np.float64)
+    p = bits.mean(axis=0)
+    n = keys.shape[0]
+    assert np.all(np.abs(p - 0.5) < 5 * math.sqrt(0.25 / n))
+    pc = bits.sum(axis=1)
+    assert abs(pc.mean() - 32.0) < 0.05 and abs(pc.var() - 16.0) < 0.3
+
+
+def test_balanced_hash_has_exactly_32_ones_and_fair_bits():
+    keys = np.arange(1, 20001, dtype=np.int64)
+    h = R.pac_hash_np(keys, 77, 128, balanced=True)
+    bits = ((h[:, :, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)).astype(np.int64)
+    assert np.all(bits.sum(axis=2) == 32)
+    p = bits.reshape(keys.shape[0], 128).mean(axis=0)
+    assert np.all(np.abs(p - 0.5) < 5 * math.sqrt(0.25 / keys.shape[0]))
+
+
+def test_query_key_reshuffles_worlds():
+    # a new per-query key re-creates the worlds: masks of the same keys are unrelated
+    keys = np.arange(1, 5001, dtype=np.int64)
+    a = R.pac_hash_np(keys, 1, 64)[:, 0]
+    b = R.pac_hash_np(keys, 2, 64)[:, 0]
+    same = np.unpackbits((~(a ^ b)).view(np.uint8)).mean()
+    assert abs(same - 0.5) < 0.01
+
+
+# ----------------------------------------------------------------------------- counters
+def _star_inputs(t, K, m, balanced=False, filter_lt=None):
+    pu = R.pu_of_rows_star(t.pu_key, t.o_pu, t.f_order, K, m, balanced)
+    group = R.dense_group(t.gcols, t.gcards)
+    if filter_lt is not None:
+        group = np.where(t.sel < filter_lt, group, -1)
+    G = int(np.prod(t.gcards))
+    return pu, group, G
+
+
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_onepass_equals_m_executions_star(m, seed):
+    t = gen.tiny_star(seed, n_pu=25, n_orders=60, n_rows=220, n_cols=2, float_cols=1, with_sel=True)
+    K = 0x1234 + seed
+    lt = 3 << 30
+    pu, group, G = _star_inputs(t, K, m, filter_lt=lt)
+    ints = [t.cols["v0"], t.cols["v1"]]
+    flts = [t.cols["f0"]]
+    one = R.pac_agg_counters(pu, group, G, ints, flts, exact_float=True)
+    bf = R.brute_force_star(t.pu_key, t.o_pu, t.f_order, R.dense_group(t.gcols, t.gcards), G, ints, flts, K, m,
+                            row_filter=t.sel < lt)
+    assert np.array_equal(one["count"], np.array(bf["count"]))
+    assert np.array_equal(one["isum"], np.array(bf["isum"], dtype=np.int64))
+    assert np.array_equal(one["fsum"], np.array(bf["fsum"]))
+
+
+def test_onepass_equals_m_executions_flat_balanced():
+    t = gen.tiny_flat(3, n_rows=300, n_keys=20, n_groups=3)
+    K = 99
+    pu = R.pu_of_rows_flat(t.pu_key, K, 64, balanced=True)
+    group = R.dense_group(t.gcols, t.gcards)
+    one = R.pac_agg_counters(pu, group, 3, [t.cols["v"]])
+    bf = R.brute_force_flat(t.pu_key, group, 3, [t.cols["v"]], [], K, 64, balanced=True)
+    assert np.array_equal(one["count"], np.array(bf["count"]))
+    assert np.array_equal(one["isum"], np.array(bf["isum"], dtype=np.int64))
+    # balanced hash: every row is in exactly half of the worlds
+    assert np.array_equal(one["count"].sum(axis=1), 32 * one["nrows"])
+
+
+def test_c_oracle_equals_definition_star(oracle_native):
+    t = gen.tiny_star(11, n_pu=300, n_orders=2000, n_rows=20000, gcards=(3, 2), n_cols=3, float_cols=1,
+                      with_sel=True, value_range=(-(1 << 40), 1 << 40))
+    K = 0xABCDEF
+    lt = 1 << 31
+    for m in (64, 128):
+        pu, group, G = _star_inputs(t, K, m, filter_lt=lt)
+        ints = [t.cols[f"v{i}"] for i in range(3)]
+        want = R.pac_agg_counters(pu, group, G, ints, [t.cols["f0"]], exact_float=True)
+        pumask = R.pac_hash_np(t.pu_key, K, m)
+        got = oracle_native.onepass(t.n_rows, m, masks=pumask, links=[t.f_order, t.o_pu], gcols=t.gcols,
+                                    gcards=t.gcards, n_groups=G, filter_col=t.sel, filter_lt=lt,
+                                    int_cols=ints, float_cols=[t.cols["f0"]], threads=4)
+        assert np.array_equal(got["count"], want["count"])
+        assert np.array_equal(got["isum"], want["isum"])
+        assert np.array_equal(got["nrows"], want["nrows"])
+        # compensated sums are within a couple of ulps of the correctly rounded sum
+        np.testing.assert_allclose(got["fsum"], want["fsum"], rtol=1e-15, atol=1e-9)
+        # fused hashing of the PU key gives the same counters as the mask table
+        got2 = oracle_native.onepass(t.n_rows, m, pu_keys=t.pu_key, query_key=K, links=[t.f_order, t.o_pu],
+                                     gcols=t.gcols, gcards=t.gcards, n_groups=G, filter_col=t.sel, filter_lt=lt,
+                                     int_cols=ints, threads=3)
+        assert np.array_equal(got2["count"], want["count"]) and np.array_equal(got2["isum"], want["isum"])
+
+
+def test_c_oracle_sparse_keys(oracle_native):
+    t = gen.tiny_flat(4, n_rows=5000, n_keys=200, n_groups=37, sparse_groups=True)
+    K = 5
+    got = oracle_native.onepass(t.n_rows, 64, pu_keys=t.pu_key, query_key=K, group_keys=t.group_keys,
+                                n_groups=100, int_cols=[t.cols["v"]], threads=4)
+    keys = np.unique(t.group_keys)
+    assert np.array_equal(got["keys"], keys)
+    group = np.searchsorted(keys, t.group_keys)
+    pu = R.pac_hash_np(t.pu_key, K, 64)
+    want = R.pac_agg_counters(pu, group, keys.shape[0], [t.cols["v"]])
+    assert np.array_equal(got["count"], want["count"]) and np.array_equal(got["isum"], want["isum"])
+
+
+def test_c_oracle_group_split_mode_matches(oracle_native):
+    # many groups force the group-sliced threading path
+    g = np.random.default_rng(8)
+    n, G = 30000, 200000
+    keys = g.integers(0, 1 << 40, size=n, dtype=np.int64)
+    gid = g.integers(0, G, size=n, dtype=np.uint32)
+    v = g.integers(-50, 50, size=n, dtype=np.int64)
+    a = oracle_native.onepass(n, 64, pu_keys=keys, query_key=3, gcols=[gid], gcards=[G], n_groups=G,
+                              int_cols=[v], threads=1)
+    b = oracle_native.onepass(n, 64, pu_keys=keys, query_key=3, gcols=[gid], gcards=[G], n_groups=G,
+                              int_cols=[v], threads=8)
+    assert np.array_equal(a["count"], b["count"]) and np.array_equal(a["isum"], b["isum"])
+
+
+def test_special_masks_reduce_to_plain_group_by():
+    g = np.random.default_rng(0)
+    n, G = 400, 5
+    group = g.integers(0, G, size=n)
+    v = g.integers(-(1 << 50), 1 << 50, size=n, dtype=np.int64)
+    plain_cnt = np.bincount(group, minlength=G)
+    plain_sum = np.array([sum(int(x) for x in v[group == k]) for k in range(G)], dtype=np.int64)
+    ones = np.full((n, 1), np.uint64((1 << 64) - 1))
+    c = R.pac_agg_counters(ones, group, G, [v])
+    assert np.all(c["count"] == plain_cnt[:, None]) and np.all(c["isum"][:, 0, :] == plain_sum[:, None])
+    zeros = np.zeros((n, 1), dtype=np.uint64)
+    c0 = R.pac_agg_counters(zeros, group, G, [v])
+    assert not c0["count"].any() and not c0["isum"].any()
+    for j in (0, 17, 63):
+        one = np.full((n, 1), np.uint64(1 << j))
+        cj = R.pac_agg_counters(one, group, G, [v])
+        assert np.all(cj["count"][:, j] == plain_cnt) and np.all(cj["isum"][:, 0, j] == plain_sum)
+        others = np.delete(cj["count"], j, axis=1)
+        assert not others.any()
+
+
+def test_invariants_popcount_complement_combine():
+    t = gen.tiny_flat(9, n_rows=3000, n_keys=100, n_groups=4)
+    pu = R.pac_hash_np(t.pu_key, 42, 64)
+    group = R.dense_group(t.gcols, t.gcards)
+    v = t.cols["v"]
+    c = R.pac_agg_counters(pu, group, 4, [v])
+    pops = np.array([bin(int(x)).count("1") for x in pu[:, 0]])
+    for k in range(4):
+        sel = group == k
+        assert c["count"][k].sum() == pops[sel].sum()
+        assert c["isum"][k, 0].sum() == int((pops[sel] * v[sel]).sum())
+    cc = R.pac_agg_counters(~pu, group, 4, [v])
+    plain_sum = np.array([v[group == k].sum() for k in range(4)])
+    assert np.all(c["count"] + cc["count"] == c["nrows"][:, None])
+    assert np.all(c["isum"][:, 0] + cc["isum"][:, 0] == plain_sum[:, None])
+    # combine: aggregating two row chunks and adding the states gives the same counters
+    a = R.pac_agg_counters(pu[:1234], group[:1234], 4, [v[:1234]])
+    b = R.pac_agg_counters(pu[1234:], group[1234:], 4, [v[1234:]])
+    assert np.array_equal(a["count"] + b["count"], c["count"])
+    assert np.array_equal(a["isum"] + b["isum"], c["isum"])
+    # the OR accumulator K_g is exactly the set of worlds with a non-zero count
+    acc = R.or_accumulator(pu, group, 4)
+    for k in range(4):
+        bits = np.array([(int(acc[k, 0]) >> j) & 1 for j in range(64)])
+        assert np.array_equal(bits, (c["count"][k] > 0).astype(int))
+
+
+def test_int64_wraparound_is_modular():
+    # counters are exact modulo 2^64 (what the GPU recombination also computes)
+    n = 10
+    v = np.full(n, np.iinfo(np.int64).max, dtype=np.int64)
+    pu = np.full((n, 1), np.uint64((1 << 64) - 1))
+    c = R.pac_agg_counters(pu, np.zeros(n, dtype=np.int64), 1, [v])
+    want = ((n * ((1 << 63) - 1) + (1 << 63)) % (1 << 64)) - (1 << 63)
+    assert int(c["isum"][0, 0, 0]) == want
+
+
+def test_float_sums_against_fsum():
+    g = np.random.default_rng(3)
+    n = 2000
+    f = g.lognormal(0, 2, size=n)
+    pu = R.pac_hash_np(np.arange(n, dtype=np.int64), 7, 64)
+    group = np.zeros(n, dtype=np.int64)
+    c = R.pac_agg_counters(pu, group, 1, [], [f], exact_float=True)
+    for j in (0, 31, 63):
+        sel = ((pu[:, 0] >> np.uint64(j)) & np.uint64(1)).astype(bool)
+        assert c["fsum"][0, 0, j] == math.fsum(f[sel].tolist())
+
+
+def test_workload_generators_are_deterministic():
+    a = gen.config2_star(scale=1e-4)
+    b = gen.config2_star(scale=1e-4)
+    assert np.array_equal(a.f_order, b.f_order) and np.array_equal(a.cols["v1"], b.cols["v1"])
+    assert np.all(np.diff(a.f_order) >= 0)
+    assert a.cols["v1"].min() >= 100 and a.cols["v1"].max() <= 10_000_000
+    c = gen.config1_flat(n=1000)
+    assert c.cols["value"].min() >= 1 and c.cols["value"].max() <= 50
