@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the PAC stochastic-aggregation hot path on one MI355X.
+
+Workload: a synthetic 3-level star schema -- 1.5M PU keys, 15M orders
+(FK -> PU uniform), 60M fact rows clustered by order (FK -> orders), grouped
+by two low-cardinality columns (6 groups), COUNT + SUM/AVG of three int64
+decimal-cents columns uniform in [1e2, 1e7], m = 64 worlds.
+
+One step = the whole path for one query: keyed hash of the PU keys (a1),
+FK-chain gather + world-bit expansion + int8 matrix-core contraction + group
+counters (a2-a6), release of the 42 result cells with noise and posterior
+(a7).  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: this build runs
+on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto"])
+    ap.add_argument("--compare-steps", type=int, default=5, help="steps timed for the other GPU forms")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shuffled", action="store_true", help="fact rows in random order instead of by order")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2603_15023_amd as P
+    from workloads import gen
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ctx = P.Context(0)
+    K = gen.query_key(1)
+    seed = gen.noise_seed(1)
+
+    t0 = time.time()
+    t = gen.config2_star(shuffled=args.shuffled)
+    log(f"generated star schema in {time.time() - t0:.1f}s: {t.n_rows} rows")
+    n, n_orders, n_pu = t.n_rows, t.o_pu.shape[0], t.pu_key.shape[0]
+
+    pu_key = torch.from_numpy(t.pu_key).to(dev)
+    links = [torch.from_numpy(t.f_order).to(dev), torch.from_numpy(t.o_pu).to(dev)]
+    gcols = [torch.from_numpy(g).to(dev) for g in t.gcols]
+    names = ["v1", "v2", "v3"]
+    cols = [torch.from_numpy(t.cols[c]).to(dev) for c in names]
+    stats = [(100, 10_000_000)] * 3  # domain of the decimal-cents columns
+    masks = torch.empty((n_pu, 1), dtype=torch.int64, device=dev)
+    spec = P.AggSpec(n_rows=n, masks=masks, links=links, gcols=gcols, gcards=t.gcards, n_groups=6, cols=cols,
+                     stats=stats)
+    state = P.new_state(spec, 64)
+    cells = []
+    for g in range(6):
+        cells.append((g, P._abi.PAC_CELL_COUNT, 0))
+        for c in range(3):
+            cells.append((g, P._abi.PAC_CELL_SUM_I, c))
+        for c in range(3):
+            cells.append((g, P._abi.PAC_CELL_AVG_I, c))
+    cells_t = P.cells_tensor(cells)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step(algo, ev=None):
+        P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+        if ev is not None:
+            ev[0].record(stream)
+        P.pac_group_aggregate(ctx, spec, state, m=64, query_key=K, algo=algo)
+        if ev is not None:
+            ev[1].record(stream)
+        return P.pac_finalize(ctx, state, cells_t, len(cells), m=64, mi_budget=1.0 / 128, noise_seed=seed)
+
+    def run(algo, steps, warmup):
+        for _ in range(warmup):
+            step(algo)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        step_ms = []
+        t_start = time.perf_counter()
+        for i in range(steps):
+            s0 = time.perf_counter()
+            step(algo, evs[i])
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - s0) * 1e3)
+        total = time.perf_counter() - t_start
+        agg_ms = [a.elapsed_time(b) for a, b in evs]
+        return total * 1e3 / steps, float(np.mean(agg_ms)), step_ms
+
+    ms_step, agg_ms, step_ms = run(args.algo, args.steps, args.warmup)
+    ctx.check()
+    log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
+
+    # the other GPU forms on the same inputs (same counters; checked in the tests)
+    forms = {}
+    ref_state = {k: v.clone() for k, v in state.items()}
+    for algo in ("plain", "mfma"):
+        if algo == args.algo:
+            forms[algo] = {"ms_per_step": ms_step, "aggregate_ms": agg_ms}
+            continue
+        ms2, agg2, _ = run(algo, args.compare_steps, 1)
+        same = all(torch.equal(state[k], ref_state[k]) for k in ("count", "isum", "nrows"))
+        forms[algo] = {"ms_per_step": ms2, "aggregate_ms": agg2, "same_counters": bool(same)}
+        log(f"{algo}: {ms2:.3f} ms/step, aggregate {agg2:.3f} ms, same counters {same}")
+    ctx.check()
+
+    alg_bytes = 30 * n + 4 * n_orders + 8 * n_pu  # fact columns + o_pu + the PU word table, each once
+    achieved = alg_bytes / (agg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"agg_mfma ({args.algo})", "alg_bytes_per_launch": alg_bytes}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(t, K, args.cpu_seconds)
+
+    rows_per_s = n / (ms_step * 1e-3)
+    out = {
+        "metric": "PAC rows/s into 64 worlds (% HBM roofline), MFMA vs plain; p99 query latency",
+        "value": rows_per_s,
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {"workload": "star schema: 1.5M PU keys, 15M orders, 60M fact rows "
+                               f"({'shuffled' if args.shuffled else 'clustered by order'}), "
+                               "6 groups, COUNT + SUM/AVG of 3 int64 cents columns, m=64, 42 released cells",
+                   "algo": args.algo},
+        "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                            "max": float(np.max(step_ms))},
+        "aggregate_rows_per_s": n / (agg_ms * 1e-3),
+        "forms": {k: dict(v, aggregate_rows_per_s=n / (v["aggregate_ms"] * 1e-3)) for k, v in forms.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(t, K, target_s):
+    """The CPU oracle (hash + one-pass counters) on a prefix of the fact rows, all host cores."""
+    from oracle import native as ON
+    from oracle import pac_ref as R
+
+    threads = ON.default_threads()
+    rows = min(t.n_rows, 2_000_000)
+    while True:
+        t0 = time.perf_counter()
+        masks = R.pac_hash_np(t.pu_key, K, 64)
+        ON.onepass(rows, 64, masks=masks, links=[t.f_order[:rows], t.o_pu], gcols=[g[:rows] for g in t.gcols],
+                   gcards=t.gcards, n_groups=6, int_cols=[t.cols[c][:rows] for c in ("v1", "v2", "v3")],
+                   threads=threads)
+        el = time.perf_counter() - t0
+        if el >= target_s * 0.5 or rows >= t.n_rows:
+            break
+        rows = min(t.n_rows, int(rows * min(8.0, target_s / max(el, 1e-3))))
+    log(f"cpu oracle: {rows} rows in {el:.2f}s on {threads} threads")
+    return {"value": rows / el, "unit": "rows/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {rows} of {t.n_rows} fact rows (hash of all 1.5M PU keys + C one-pass counters), "
+                      f"{el:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

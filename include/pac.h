@@ -1,0 +1,203 @@
+/*
+ * pac.h -- C ABI of the MI355X (gfx950) PAC stochastic-aggregation library.
+ *
+ * The library computes, in one scan of HBM-resident columns, the m per-world
+ * aggregates of SIMD-PAC-DB's stochastic aggregation functions and then the
+ * PAC-noised release of each result cell.  Paper: "SIMD-PAC-DB: Pretty
+ * Performant PAC Privacy" (arXiv 2603.15023).
+ *
+ * Conventions (all entry points)
+ *  - Every call returns an int status: PAC_OK (0) or a negative PAC_ERR_*.
+ *    Nothing aborts or throws across the ABI; pac_last_error() gives the
+ *    message of the last failing call on the calling host thread.
+ *  - "device" pointers are HIP device allocations owned by the caller; the
+ *    library never frees or keeps them beyond the work it enqueues.  The
+ *    caller keeps them alive until the stream has finished that work.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls only enqueue work; they do not synchronise.
+ *  - Errors that only the device can see (a group value or a foreign-key
+ *    index out of range, a full hash table, a failed diversity check in
+ *    strict mode) set bits of a per-context device status word;
+ *    pac_check() synchronises the stream and reports and clears them.
+ *  - Arrays are dense, row-major, naturally aligned; value and group columns
+ *    must be 16-byte aligned (any torch / hipMalloc allocation is).
+ */
+#ifndef PAC_H
+#define PAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PAC_OK 0
+#define PAC_ERR_INVALID (-1)       /* bad argument: null pointer, size, m, type mix */
+#define PAC_ERR_OOM (-2)           /* device scratch allocation failed */
+#define PAC_ERR_HIP (-3)           /* a HIP runtime call failed */
+#define PAC_ERR_OVERFLOW (-4)      /* column statistics say an int64 counter could overflow */
+#define PAC_ERR_DIVERSITY (-5)     /* strict diversity check failed (Sec. 5, Diversity Check) */
+#define PAC_ERR_UNSUPPORTED (-6)   /* algorithm / input combination not implemented */
+#define PAC_ERR_DEVICE_STATUS (-7) /* pac_check found device status bits set */
+
+/* device status bits reported by pac_check */
+#define PAC_STATUS_BAD_GROUP 1u    /* group column value >= its cardinality: row skipped */
+#define PAC_STATUS_BAD_LINK 2u     /* foreign-key index out of range: row skipped */
+#define PAC_STATUS_TABLE_FULL 4u   /* sparse group hash table out of slots: rows skipped */
+#define PAC_STATUS_DIVERSITY 8u    /* strict diversity check failed in pac_finalize */
+
+typedef struct pac_ctx pac_ctx;
+
+/* One context per (device, host thread).  Creates the device status word and
+ * a scratch pool on device `hip_device`.  Not thread-safe. */
+int pac_ctx_create(int hip_device, pac_ctx **out);
+int pac_ctx_destroy(pac_ctx *ctx);
+const char *pac_last_error(void);
+/* Synchronises `stream`, returns the device status bits in *status (may be
+ * NULL) and clears them.  Returns PAC_ERR_DEVICE_STATUS if any bit was set. */
+int pac_check(pac_ctx *ctx, void *stream, uint32_t *status);
+int pac_version(void); /* library ABI version (this header: 1) */
+
+/* ---- a1: keyed PU hash (Sec. 2 "SIMD-PAC-DB"; Sec. 4.2 "PAC Hash") --------
+ * out_masks[i*W + w] = word w of pac_hash_K(keys[i]), W = m/64, m in {64,128}.
+ * World j is bit (j % 64) of word j/64.  Word w is the (w+1)-th output of
+ * splitmix64 started at state keys[i] XOR query_key; the query key re-creates
+ * all worlds for every query.  PAC_HASH_BALANCED transforms each word to
+ * exactly 32 one-bits (the paper's "guaranteed 32 0- and 32 1-bits").
+ * keys: device int64[n]; out_masks: device uint64[n*W].  n = 0 is a no-op. */
+#define PAC_HASH_BALANCED 1u
+int pac_hash_mask(pac_ctx *ctx, void *stream, const int64_t *keys, int64_t n, uint64_t query_key, int m,
+                  uint32_t flags, uint64_t *out_masks);
+
+/* ---- a2-a6: per-group, per-world aggregation (Sec. 4.2 "PAC Aggregation",
+ * Sec. 5; Theorem 2 makes one scan equal to m executions) ------------------ */
+enum pac_type { PAC_U8 = 1, PAC_U16 = 2, PAC_U32 = 3, PAC_I32 = 4, PAC_I64 = 5, PAC_F32 = 6, PAC_F64 = 7 };
+
+#define PAC_MAX_LINKS 4
+#define PAC_MAX_GCOLS 4
+#define PAC_MAX_COLS 8
+#define PAC_EMPTY_KEY ((int64_t)0x8000000000000000ull) /* unused sparse slot; not a valid group key */
+
+/* Host struct holding device pointers.
+ * PU vector of row r (Sec. 2 "Relational Privacy Unit": a fact row reaches its
+ * PU through a foreign-key chain):  idx = r; idx = links[k][idx] for
+ * k = 0..n_links-1; then masks[idx*W .. idx*W+W-1] if masks != NULL, else
+ * pac_hash of pu_keys[idx] with the call's query key (fused a1).
+ * Group of row r: dense composite key ((g0*card1 + g1)*card2 + ...) of the
+ * unsigned group columns, reduced mod group_mod if group_mod > 0, and must be
+ * < n_groups; or, with group_keys != NULL, a sparse int64 key placed in an
+ * open-addressing hash table of n_groups slots kept in the state.  No group
+ * columns and no keys: one group (ungrouped aggregate).
+ * Filter (a3): with filter_col != NULL only rows with filter_col[r] < filter_lt
+ * reach the aggregate (an ordinary selection below the aggregate).
+ * Value columns: PAC_I32 / PAC_I64 sums are exact modulo 2^64 (exact whenever
+ * the true sum fits int64); PAC_F32 / PAC_F64 sums accumulate in fp64.
+ * has_stats != 0 promises col_min[c] <= value <= col_max[c] for every int
+ * column c (host values); it lets the int8 matrix-core path drop zero bytes. */
+typedef struct {
+  int64_t n_rows;
+  const uint64_t *masks;   /* device [n_masks][W] or NULL */
+  int64_t n_masks;
+  const int64_t *pu_keys;  /* device [n_pu_keys] (used when masks == NULL) */
+  int64_t n_pu_keys;
+  uint32_t hash_flags;     /* PAC_HASH_BALANCED for the fused hash */
+  int32_t n_links;
+  const int32_t *links[PAC_MAX_LINKS]; /* device int32 index arrays */
+  int64_t link_len[PAC_MAX_LINKS];
+  int32_t n_gcols;
+  const void *gcols[PAC_MAX_GCOLS];    /* device, PAC_U8 / PAC_U16 / PAC_U32 */
+  int32_t gcol_type[PAC_MAX_GCOLS];
+  int64_t gcards[PAC_MAX_GCOLS];
+  int64_t group_mod;
+  const int64_t *group_keys;           /* device [n_rows] sparse keys or NULL */
+  int64_t n_groups;                    /* dense: G;  sparse: slot capacity */
+  const uint32_t *filter_col;          /* device [n_rows] or NULL */
+  uint32_t filter_lt;
+  int32_t n_cols;
+  const void *cols[PAC_MAX_COLS];      /* device [n_rows] */
+  int32_t col_type[PAC_MAX_COLS];
+  int32_t has_stats;
+  int64_t col_min[PAC_MAX_COLS];
+  int64_t col_max[PAC_MAX_COLS];
+} pac_agg_input;
+
+/* Device output arrays (caller allocated).  Accumulate semantics: a call adds
+ * into them, so chunked scans and the combine of partial states (DuckDB's
+ * state.combine) are plain repeated calls.  PAC_AGG_INIT clears them first.
+ * Raw, unscaled per-world aggregates; world j of group g at [g][...][j]. */
+typedef struct {
+  int64_t *count;       /* [G][m]            rows of g in world j            */
+  int64_t *isum;        /* [G][n_int][m]     int columns, in input order      */
+  double *fsum;         /* [G][n_float][m]   float columns, in input order    */
+  int64_t *nrows;       /* [G]               rows of g reaching the aggregate */
+  int64_t *slot_keys;   /* sparse: [n_groups] key of each slot or PAC_EMPTY_KEY */
+  int64_t *n_used;      /* sparse: [1] number of occupied slots                */
+} pac_agg_state;
+
+#define PAC_ALGO_AUTO 0u
+#define PAC_ALGO_PLAIN 1u   /* lane = world, rows broadcast, predicated adds (the paper's update loop) */
+#define PAC_ALGO_BALLOT 2u  /* ballot transpose of world bits, popcounts of bit-sliced values (ints) */
+#define PAC_ALGO_MFMA_I8 3u /* int8 matrix cores on byte digits, exact int32 -> int64 recombination */
+#define PAC_AGG_INIT 1u     /* clear the state (and the sparse table) before aggregating */
+
+/* m in {64, 128}; query_key is used by the fused hash.  Returns
+ * PAC_ERR_UNSUPPORTED if `algo` cannot run this input (AUTO never does).
+ * PAC_ERR_OVERFLOW if has_stats shows n_rows*max|v| could exceed int64. */
+int pac_group_aggregate(pac_ctx *ctx, void *stream, const pac_agg_input *in, int m, uint64_t query_key,
+                        uint32_t algo, uint32_t flags, pac_agg_state *inout);
+
+/* Several independent queries in one call: query q reads in[q] with
+ * query_keys[q] and accumulates into states[q].  Work of all queries is
+ * enqueued back to back on one stream with no host synchronisation. */
+int pac_group_aggregate_batch(pac_ctx *ctx, void *stream, const pac_agg_input *in, const uint64_t *query_keys,
+                              int n_queries, int m, uint32_t algo, uint32_t flags, pac_agg_state *states);
+
+/* ---- a7: release (Sec. 4.1 noise function pac_noised; Sec. 3.2 NULLs;
+ * Sec. 5 Diversity Check; Sec. 2 adaptive composition) -------------------- */
+enum pac_cell_kind { PAC_CELL_COUNT = 0, PAC_CELL_SUM_I = 1, PAC_CELL_SUM_F = 2, PAC_CELL_AVG_I = 3,
+                     PAC_CELL_AVG_F = 4 };
+typedef struct {
+  int64_t group;  /* group index (dense id or sparse slot) */
+  int32_t kind;   /* pac_cell_kind */
+  int32_t col;    /* index among the int (SUM_I/AVG_I) or float (SUM_F/AVG_F) columns */
+} pac_cell;
+
+#define PAC_FIN_SCALE2 1u            /* release count/sum times 2 (each world sees about half of the rows) */
+#define PAC_FIN_AVG_TOTALCOUNT 2u    /* AVG_j = 2 S_j / nrows instead of S_j / count_j */
+#define PAC_FIN_STRICT_DIVERSITY 4u  /* a flagged cell sets PAC_STATUS_DIVERSITY */
+#define PAC_FIN_FIXED_PRIOR 8u       /* no posterior update between cells */
+#define PAC_FIN_PRIOR_IN 16u         /* posterior holds the prior on entry (else uniform) */
+typedef struct {
+  double mi_budget;     /* B > 0 (nats), per released cell; +inf releases y_{j*} */
+  uint64_t noise_seed;  /* Philox4x32-10 key of every draw of this query */
+  int32_t j_star;       /* secret world, or -1 to draw it from noise_seed */
+  uint32_t flags;       /* PAC_FIN_* */
+} pac_finalize_params;
+
+/* Per-cell output flags */
+#define PAC_CELL_NULL 1u
+#define PAC_CELL_DIVERSITY 2u
+#define PAC_CELL_ZERO_VARIANCE 4u
+
+/* Releases cells[0..n_cells-1] in array order, all with the same secret world
+ * j*, each with pac_noised under the running posterior P over the m worlds:
+ *   NULL with probability (m - popcount K_g)/m (K_g: worlds with count > 0);
+ *   s^2 = Var_{j~P}[y_j]; Delta = s^2/(2B); y~ = y_{j*} + N(0, Delta);
+ *   P <- P*W/sum(P*W), W_j = exp(-(y~ - y_j)^2 / (2 Delta)).
+ * Runs in fp64 on the device, one wavefront for the whole (sequential) chain.
+ * state / cells / out_* / posterior / out_y: device pointers.  params: host.
+ * n_groups / n_int / n_float: sizes of the state's arrays; a cell whose group,
+ * kind or column is out of range sets PAC_STATUS_BAD_GROUP and is released as
+ * NULL with flag PAC_CELL_NULL.
+ * out_val[c] (0 for NULL cells), out_is_null[c], out_flags[c];
+ * posterior: [m] prior on entry with PAC_FIN_PRIOR_IN, final posterior on exit;
+ * out_y: [n_cells][m] released world vectors, or NULL. */
+int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
+                 int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
+                 uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAC_H */

@@ -1,0 +1,18 @@
+"""MI355X-native PAC stochastic aggregation (SIMD-PAC-DB's hot path on gfx950).
+
+The work runs in libpac.so (hand-written HIP kernels behind the C ABI of
+include/pac.h); this package only marshals arguments.  Importing it does not
+load the library; the first call does, and raises ImportError if it has not
+been built (``python -m paper_2603_15023_amd.build``).
+"""
+from ._abi import PacError  # noqa: F401
+from .api import (  # noqa: F401
+    AggSpec,
+    Context,
+    cells_tensor,
+    new_state,
+    pac_finalize,
+    pac_group_aggregate,
+    pac_group_aggregate_batch,
+    pac_hash_mask,
+)

@@ -1,0 +1,239 @@
+"""Python binding of the C ABI (argument marshalling only; all work runs in libpac.so).
+
+Tensors are torch CUDA (HIP) tensors; 64-bit PU words travel as int64
+tensors holding the same bits.  Every call is asynchronous on the given
+torch stream (default: the current stream); ``Context.check`` synchronises
+and raises on device status bits.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+_GTYPES = {torch.uint8: A.PAC_U8, torch.int16: A.PAC_U16, torch.int32: A.PAC_U32}
+_VTYPES = {torch.int32: A.PAC_I32, torch.int64: A.PAC_I64, torch.float32: A.PAC_F32, torch.float64: A.PAC_F64}
+for _name, _code in (("uint16", A.PAC_U16), ("uint32", A.PAC_U32)):
+    if hasattr(torch, _name):
+        _GTYPES[getattr(torch, _name)] = _code
+
+
+def _stream_handle(stream) -> Optional[int]:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors passed to the PAC library must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the PAC library must be contiguous")
+    return t.data_ptr()
+
+
+class Context:
+    """A pac_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        lib = A.load()
+        h = C.c_void_p()
+        A.check(lib.pac_ctx_create(int(device), C.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, stream=None) -> int:
+        """Synchronise the stream; raise PacError if device status bits were set."""
+        st = C.c_uint32(0)
+        A.check(A.load().pac_check(self._h, _stream_handle(stream), C.byref(st)))
+        return st.value
+
+    def status(self, stream=None) -> int:
+        """Synchronise the stream and return (and clear) the device status bits without raising."""
+        st = C.c_uint32(0)
+        rc = A.load().pac_check(self._h, _stream_handle(stream), C.byref(st))
+        if rc not in (A.PAC_OK, -7):
+            A.check(rc)
+        return st.value
+
+    def close(self):
+        if self._h:
+            A.load().pac_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pac_hash_mask(ctx: Context, keys: torch.Tensor, query_key: int, m: int = 64, balanced: bool = False,
+                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """a1: [n] int64 keys -> [n, m/64] int64 words of pac_hash_K."""
+    if keys.dtype != torch.int64:
+        raise TypeError("keys must be int64")
+    n = keys.numel()
+    if out is None:
+        out = torch.empty((n, m // 64), dtype=torch.int64, device=keys.device)
+    A.check(A.load().pac_hash_mask(ctx.handle, _stream_handle(stream), _ptr(keys), n, query_key & ((1 << 64) - 1),
+                                   m, A.PAC_HASH_BALANCED if balanced else 0, _ptr(out)))
+    return out
+
+
+@dataclasses.dataclass
+class AggSpec:
+    """One aggregation's inputs (device tensors) -- mirrors pac_agg_input."""
+
+    n_rows: int
+    masks: Optional[torch.Tensor] = None           # int64 [n_masks, W]
+    pu_keys: Optional[torch.Tensor] = None         # int64 (fused hash)
+    balanced: bool = False
+    links: Sequence[torch.Tensor] = ()             # int32 FK index arrays
+    gcols: Sequence[torch.Tensor] = ()             # uint8 / int16 / int32 (unsigned values)
+    gcards: Sequence[int] = ()
+    group_mod: int = 0
+    group_keys: Optional[torch.Tensor] = None      # int64 sparse keys
+    n_groups: int = 1
+    filter_col: Optional[torch.Tensor] = None      # int32 holding uint32 bits
+    filter_lt: int = 0
+    cols: Sequence[torch.Tensor] = ()              # int32 / int64 / float32 / float64
+    stats: Optional[Sequence[Tuple[int, int]]] = None  # (min, max) per column (ints only used)
+
+    @property
+    def n_int(self) -> int:
+        return sum(1 for c in self.cols if c.dtype in (torch.int32, torch.int64))
+
+    @property
+    def n_float(self) -> int:
+        return sum(1 for c in self.cols if c.dtype in (torch.float32, torch.float64))
+
+    def to_c(self) -> A.AggInput:
+        s = A.AggInput()
+        s.n_rows = int(self.n_rows)
+        if self.masks is not None:
+            s.masks, s.n_masks = _ptr(self.masks), int(self.masks.shape[0])
+        if self.pu_keys is not None:
+            s.pu_keys, s.n_pu_keys = _ptr(self.pu_keys), int(self.pu_keys.numel())
+        s.hash_flags = A.PAC_HASH_BALANCED if self.balanced else 0
+        if len(self.links) > A.MAX_LINKS or len(self.gcols) > A.MAX_GCOLS or len(self.cols) > A.MAX_COLS:
+            raise ValueError("too many links / group columns / value columns")
+        s.n_links = len(self.links)
+        for i, l in enumerate(self.links):
+            if l.dtype != torch.int32:
+                raise TypeError("links must be int32")
+            s.links[i], s.link_len[i] = _ptr(l), l.numel()
+        s.n_gcols = len(self.gcols)
+        for i, (g, card) in enumerate(zip(self.gcols, self.gcards)):
+            s.gcols[i], s.gcol_type[i], s.gcards[i] = _ptr(g), _GTYPES[g.dtype], int(card)
+        s.group_mod = int(self.group_mod)
+        if self.group_keys is not None:
+            s.group_keys = _ptr(self.group_keys)
+        s.n_groups = int(self.n_groups)
+        if self.filter_col is not None:
+            s.filter_col, s.filter_lt = _ptr(self.filter_col), int(self.filter_lt)
+        s.n_cols = len(self.cols)
+        for i, c in enumerate(self.cols):
+            s.cols[i], s.col_type[i] = _ptr(c), _VTYPES[c.dtype]
+        if self.stats is not None:
+            s.has_stats = 1
+            for i, (lo, hi) in enumerate(self.stats):
+                s.col_min[i], s.col_max[i] = int(lo), int(hi)
+        return s
+
+
+def new_state(spec: AggSpec, m: int = 64, device=None) -> Dict[str, torch.Tensor]:
+    """Allocates (uninitialised) device counters for ``spec``; pass PAC_AGG_INIT on first use."""
+    dev = device if device is not None else torch.device("cuda")
+    G = int(spec.n_groups)
+    st = {
+        "count": torch.empty((G, m), dtype=torch.int64, device=dev),
+        "isum": torch.empty((G, max(spec.n_int, 0), m), dtype=torch.int64, device=dev),
+        "fsum": torch.empty((G, max(spec.n_float, 0), m), dtype=torch.float64, device=dev),
+        "nrows": torch.empty((G,), dtype=torch.int64, device=dev),
+    }
+    if spec.group_keys is not None:
+        st["slot_keys"] = torch.empty((G,), dtype=torch.int64, device=dev)
+        st["n_used"] = torch.empty((1,), dtype=torch.int64, device=dev)
+    return st
+
+
+def _state_c(st: Dict[str, torch.Tensor]) -> A.AggState:
+    s = A.AggState()
+    s.count = _ptr(st["count"])
+    s.nrows = _ptr(st["nrows"])
+    s.isum = _ptr(st["isum"]) if st["isum"].numel() else None
+    s.fsum = _ptr(st["fsum"]) if st["fsum"].numel() else None
+    s.slot_keys = _ptr(st.get("slot_keys"))
+    s.n_used = _ptr(st.get("n_used"))
+    return s
+
+
+def pac_group_aggregate(ctx: Context, spec: AggSpec, state: Dict[str, torch.Tensor], m: int = 64,
+                        query_key: int = 0, algo: str = "auto", init: bool = True, stream=None):
+    """a2-a6: accumulate the per-world counters of ``spec`` into ``state``."""
+    cin = spec.to_c()
+    cst = _state_c(state)
+    A.check(A.load().pac_group_aggregate(ctx.handle, _stream_handle(stream), C.byref(cin), m,
+                                         query_key & ((1 << 64) - 1), A.ALGOS[algo],
+                                         A.PAC_AGG_INIT if init else 0, C.byref(cst)))
+    return state
+
+
+def pac_group_aggregate_batch(ctx: Context, specs: Sequence[AggSpec], states: Sequence[Dict[str, torch.Tensor]],
+                              query_keys: Sequence[int], m: int = 64, algo: str = "auto", init: bool = True,
+                              stream=None):
+    n = len(specs)
+    cins = (A.AggInput * n)(*[s.to_c() for s in specs])
+    csts = (A.AggState * n)(*[_state_c(s) for s in states])
+    qks = (C.c_uint64 * n)(*[q & ((1 << 64) - 1) for q in query_keys])
+    A.check(A.load().pac_group_aggregate_batch(ctx.handle, _stream_handle(stream), cins, qks, n, m, A.ALGOS[algo],
+                                               A.PAC_AGG_INIT if init else 0, csts))
+    return states
+
+
+CELL_KINDS = {"count": A.PAC_CELL_COUNT, "sum_i": A.PAC_CELL_SUM_I, "sum_f": A.PAC_CELL_SUM_F,
+              "avg_i": A.PAC_CELL_AVG_I, "avg_f": A.PAC_CELL_AVG_F}
+
+
+def cells_tensor(cells: Sequence[Tuple[int, int, int]], device=None) -> torch.Tensor:
+    """(group, kind, col) triples -> device array of pac_cell (16 bytes each)."""
+    dt = np.dtype([("group", "<i8"), ("kind", "<i4"), ("col", "<i4")])
+    arr = np.zeros(len(cells), dtype=dt)
+    for i, (g, k, c) in enumerate(cells):
+        arr[i] = (g, k, c)
+    t = torch.from_numpy(arr.view(np.uint8).copy())
+    return t.to(device if device is not None else torch.device("cuda"))
+
+
+def pac_finalize(ctx: Context, state: Dict[str, torch.Tensor], cells: torch.Tensor, n_cells: int, m: int = 64,
+                 mi_budget: float = 1.0 / 128, noise_seed: int = 0, j_star: int = -1,
+                 flags: int = A.PAC_FIN_SCALE2, prior: Optional[torch.Tensor] = None, want_y: bool = False,
+                 stream=None):
+    """a7: release ``n_cells`` cells; returns (values, is_null, cell_flags, posterior, y or None)."""
+    dev = state["count"].device
+    vals = torch.empty(n_cells, dtype=torch.float64, device=dev)
+    nulls = torch.empty(n_cells, dtype=torch.uint8, device=dev)
+    cflags = torch.empty(n_cells, dtype=torch.int32, device=dev)
+    post = torch.empty(m, dtype=torch.float64, device=dev)
+    if prior is not None:
+        post.copy_(prior)
+        flags |= A.PAC_FIN_PRIOR_IN
+    ys = torch.empty((n_cells, m), dtype=torch.float64, device=dev) if want_y else None
+    params = A.FinalizeParams(float(mi_budget), noise_seed & ((1 << 64) - 1), int(j_star), int(flags))
+    cst = _state_c(state)
+    G = int(state["count"].shape[0])
+    A.check(A.load().pac_finalize(ctx.handle, _stream_handle(stream), C.byref(cst), m, G,
+                                  int(state["isum"].shape[1]), int(state["fsum"].shape[1]), _ptr(cells), n_cells,
+                                  C.byref(params), _ptr(vals), _ptr(nulls), _ptr(cflags), _ptr(post), _ptr(ys)))
+    return vals, nulls, cflags, post, ys

@@ -1,0 +1,50 @@
+// a1: keyed PU hash (Sec. 2 "SIMD-PAC-DB", Sec. 4.2 "PAC Hash") and small fill kernels.
+//
+// One thread per key; word w of key k is the (w+1)-th splitmix64 output from
+// state k ^ K.  Reads 8 B and writes 8*W B per key: HBM-bound, coalesced.
+#include "pac_internal.h"
+
+namespace pac {
+
+template <int W>
+__global__ __launch_bounds__(256) void hash_kernel(const int64_t *__restrict__ keys, int64_t n, uint64_t qk,
+                                                   uint32_t balanced, uint64_t *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t k = __builtin_nontemporal_load(&keys[i]);
+#pragma unroll
+    for (int w = 0; w < W; ++w) out[i * W + w] = pu_word(k, qk, w, balanced != 0);
+  }
+}
+
+hipError_t launch_hash(const LaunchEnv &env, const int64_t *keys, int64_t n, uint64_t qk, int m, bool balanced,
+                       uint64_t *out) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks_needed = (n + 255) / 256;
+  const int blocks = (int)(blocks_needed < (int64_t)env.n_cu * 16 ? blocks_needed : (int64_t)env.n_cu * 16);
+  if (m == 64)
+    hipLaunchKernelGGL(hash_kernel<1>, dim3(blocks), dim3(256), 0, env.stream, keys, n, qk, balanced ? 1u : 0u, out);
+  else
+    hipLaunchKernelGGL(hash_kernel<2>, dim3(blocks), dim3(256), 0, env.stream, keys, n, qk, balanced ? 1u : 0u, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_kernel(T *p, int64_t n, T v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+template <typename T>
+static hipError_t launch_fill(const LaunchEnv &env, T *p, int64_t n, T v) {
+  if (n <= 0 || !p) return hipSuccess;
+  const int64_t need = (n + 255) / 256;
+  const int blocks = (int)(need < (int64_t)env.n_cu * 8 ? need : (int64_t)env.n_cu * 8);
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks), dim3(256), 0, env.stream, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(const LaunchEnv &env, int64_t *p, int64_t n, int64_t v) { return launch_fill(env, p, n, v); }
+hipError_t launch_fill_f64(const LaunchEnv &env, double *p, int64_t n, double v) { return launch_fill(env, p, n, v); }
+
+}  // namespace pac

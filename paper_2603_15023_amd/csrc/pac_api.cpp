@@ -1,0 +1,376 @@
+// Host side of the C ABI: argument checks, input planning, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "pac_internal.h"
+
+struct pac_ctx {
+  int device;
+  int n_cu;
+  uint32_t *d_status;
+  void *scratch;
+  size_t scratch_bytes;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(PAC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Runs the body with the context's device current, restoring the caller's device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int ensure_scratch(pac_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->scratch_bytes) return PAC_OK;
+  if (ctx->scratch) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, (size_t)1 << 20);
+  if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
+    ctx->scratch = nullptr;
+    return fail(PAC_ERR_OOM, "scratch allocation of %zu bytes failed", want);
+  }
+  ctx->scratch_bytes = want;
+  return PAC_OK;
+}
+
+bool is_int(int t) { return t == PAC_I32 || t == PAC_I64; }
+bool is_float(int t) { return t == PAC_F32 || t == PAC_F64; }
+bool is_gtype(int t) { return t == PAC_U8 || t == PAC_U16 || t == PAC_U32; }
+
+int bit_length(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+// Validates one input and builds the kernel view.  Returns PAC_OK or an error.
+int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state *st, pac::DevInput *d,
+               pac::DevState *ds) {
+  if (!in || !st) return fail(PAC_ERR_INVALID, "null input or state");
+  if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
+  if (in->n_rows < 0) return fail(PAC_ERR_INVALID, "n_rows < 0");
+  if (in->n_links < 0 || in->n_links > PAC_MAX_LINKS) return fail(PAC_ERR_INVALID, "n_links out of range");
+  if (in->n_gcols < 0 || in->n_gcols > PAC_MAX_GCOLS) return fail(PAC_ERR_INVALID, "n_gcols out of range");
+  if (in->n_cols < 0 || in->n_cols > PAC_MAX_COLS) return fail(PAC_ERR_INVALID, "n_cols out of range");
+  if (in->n_rows > 0 && !in->masks && !in->pu_keys) return fail(PAC_ERR_INVALID, "need masks or pu_keys");
+  if (in->masks && in->n_masks < 0) return fail(PAC_ERR_INVALID, "n_masks < 0");
+  if (!in->masks && in->pu_keys && in->n_pu_keys < 0) return fail(PAC_ERR_INVALID, "n_pu_keys < 0");
+  for (int k = 0; k < in->n_links; ++k)
+    if (!in->links[k] || in->link_len[k] < 0) return fail(PAC_ERR_INVALID, "link %d missing", k);
+  if (in->n_groups < 1) return fail(PAC_ERR_INVALID, "n_groups must be >= 1");
+  if (in->group_keys) {
+    if (in->n_gcols > 0 || in->group_mod > 0) return fail(PAC_ERR_INVALID, "sparse keys exclude group columns");
+    if (in->n_groups & (in->n_groups - 1)) return fail(PAC_ERR_INVALID, "sparse capacity must be a power of two");
+    if (!st->slot_keys || !st->n_used) return fail(PAC_ERR_INVALID, "sparse mode needs slot_keys and n_used");
+  } else {
+    if (in->n_gcols == 0 && in->group_mod == 0 && in->n_groups != 1)
+      return fail(PAC_ERR_INVALID, "ungrouped aggregate needs n_groups == 1");
+    if (in->group_mod < 0) return fail(PAC_ERR_INVALID, "group_mod < 0");
+    double prod = 1.0;
+    for (int k = 0; k < in->n_gcols; ++k) {
+      if (!in->gcols[k] || !is_gtype(in->gcol_type[k]) || in->gcards[k] < 1)
+        return fail(PAC_ERR_INVALID, "bad group column %d", k);
+      prod *= (double)in->gcards[k];
+    }
+    if (prod > 4.0e9) return fail(PAC_ERR_UNSUPPORTED, "composite group key space above 2^32");
+  }
+  if (!st->count || !st->nrows) return fail(PAC_ERR_INVALID, "state.count and state.nrows are required");
+  const int64_t G = in->n_groups;
+  if ((double)G * m * (1 + in->n_cols) > 4.0e12) return fail(PAC_ERR_INVALID, "state too large");
+
+  std::memset(d, 0, sizeof(*d));
+  d->n_rows = in->n_rows;
+  d->masks = in->masks;
+  d->n_masks = in->n_masks;
+  d->pu_keys = in->pu_keys;
+  d->n_pu_keys = in->n_pu_keys;
+  d->query_key = qk;
+  d->balanced = (in->hash_flags & PAC_HASH_BALANCED) ? 1u : 0u;
+  d->m = m;
+  d->W = m / 64;
+  d->n_links = in->n_links;
+  for (int k = 0; k < in->n_links; ++k) {
+    d->links[k] = in->links[k];
+    d->link_len[k] = in->link_len[k];
+  }
+  d->n_gcols = in->n_gcols;
+  for (int k = 0; k < in->n_gcols; ++k) {
+    d->gcols[k] = in->gcols[k];
+    d->gcol_type[k] = in->gcol_type[k];
+    d->gcards[k] = in->gcards[k];
+  }
+  d->group_mod = in->group_mod;
+  d->group_keys = in->group_keys;
+  d->n_groups = G;
+  d->filter_col = in->filter_col;
+  d->filter_lt = in->filter_lt;
+  for (int c = 0; c < in->n_cols; ++c) {
+    const int t = in->col_type[c];
+    if (!in->cols[c] && in->n_rows > 0) return fail(PAC_ERR_INVALID, "value column %d missing", c);
+    if (is_int(t)) {
+      const int i = d->n_icols++;
+      d->icols[i] = in->cols[c];
+      d->icol_type[i] = t;
+      int64_t lo, hi;
+      if (in->has_stats) {
+        lo = in->col_min[c];
+        hi = in->col_max[c];
+        if (lo > hi) return fail(PAC_ERR_INVALID, "column %d: min > max", c);
+        const __int128 amax = std::max<__int128>(-(__int128)lo, (__int128)hi);
+        if (amax * (__int128)in->n_rows >= ((__int128)1 << 63))
+          return fail(PAC_ERR_OVERFLOW, "column %d: n_rows * max|v| may exceed int64", c);
+      } else if (t == PAC_I32) {
+        lo = INT32_MIN;
+        hi = INT32_MAX;
+      } else {
+        lo = INT64_MIN;
+        hi = INT64_MAX;
+      }
+      const uint64_t range = (uint64_t)hi - (uint64_t)lo;
+      d->icol_lo[i] = lo;
+      d->icol_bits[i] = bit_length(range);
+      d->icol_digits[i] = (bit_length(range) + 7) / 8;
+    } else if (is_float(t)) {
+      const int f = d->n_fcols++;
+      d->fcols[f] = in->cols[c];
+      d->fcol_type[f] = t;
+    } else {
+      return fail(PAC_ERR_INVALID, "value column %d: bad type %d", c, t);
+    }
+  }
+  // the scan kernels use 16-byte vector loads of 4 consecutive rows
+  auto misaligned = [](const void *p) { return ((uintptr_t)p & 15u) != 0; };
+  for (int c = 0; c < in->n_cols; ++c)
+    if (misaligned(in->cols[c])) return fail(PAC_ERR_INVALID, "value column %d is not 16-byte aligned", c);
+  for (int k = 0; k < in->n_gcols; ++k)
+    if (misaligned(in->gcols[k])) return fail(PAC_ERR_INVALID, "group column %d is not 16-byte aligned", k);
+  if (misaligned(in->filter_col)) return fail(PAC_ERR_INVALID, "filter column is not 16-byte aligned");
+  if (d->n_icols > 0 && !st->isum) return fail(PAC_ERR_INVALID, "state.isum required for int columns");
+  if (d->n_fcols > 0 && !st->fsum) return fail(PAC_ERR_INVALID, "state.fsum required for float columns");
+  ds->count = st->count;
+  ds->isum = st->isum;
+  ds->fsum = st->fsum;
+  ds->nrows = st->nrows;
+  ds->slot_keys = st->slot_keys;
+  ds->n_used = st->n_used;
+  return PAC_OK;
+}
+
+uint32_t choose_algo(const pac::DevInput &d) {
+  if (d.group_keys || d.n_fcols > 0) return PAC_ALGO_PLAIN;
+  int64_t bits = 1;
+  for (int c = 0; c < d.n_icols; ++c) bits += d.icol_bits[c];
+  const int64_t ballot_cost = d.n_groups * bits;  // popcounts per 64 rows
+  if (pac::ballot_supported(d) && ballot_cost <= 24) return PAC_ALGO_BALLOT;
+  if (pac::mfma_supported(d)) return PAC_ALGO_MFMA_I8;
+  if (pac::ballot_supported(d) && ballot_cost <= 160) return PAC_ALGO_BALLOT;
+  return PAC_ALGO_PLAIN;
+}
+
+int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, uint64_t qk, uint32_t algo,
+            uint32_t flags, pac_agg_state *st) {
+  pac::DevInput d;
+  pac::DevState ds;
+  int rc = plan_input(in, m, qk, st, &d, &ds);
+  if (rc != PAC_OK) return rc;
+  pac::LaunchEnv env{stream, ctx->n_cu, ctx->d_status};
+  const int64_t G = d.n_groups;
+  if (flags & PAC_AGG_INIT) {
+    hipError_t e = pac::launch_fill_i64(env, ds.count, G * m, 0);
+    if (e == hipSuccess && ds.isum) e = pac::launch_fill_i64(env, ds.isum, G * d.n_icols * m, 0);
+    if (e == hipSuccess && ds.fsum) e = pac::launch_fill_f64(env, ds.fsum, G * d.n_fcols * m, 0.0);
+    if (e == hipSuccess) e = pac::launch_fill_i64(env, ds.nrows, G, 0);
+    if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.slot_keys, G, PAC_EMPTY_KEY);
+    if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.n_used, 1, 0);
+    if (e != hipSuccess) return hip_fail(e, "state init");
+  }
+  if (d.n_rows == 0) return PAC_OK;
+  if (algo == PAC_ALGO_AUTO) algo = choose_algo(d);
+  hipError_t e = hipSuccess;
+  switch (algo) {
+    case PAC_ALGO_PLAIN: {
+      const size_t need = pac::plain_scratch_bytes(env, d);
+      if (need) {
+        rc = ensure_scratch(ctx, need);
+        if (rc != PAC_OK) return rc;
+      }
+      e = pac::launch_agg_plain(env, d, ds, ctx->scratch, ctx->scratch_bytes);
+      break;
+    }
+    case PAC_ALGO_BALLOT:
+      if (!pac::ballot_supported(d))
+        return fail(PAC_ERR_UNSUPPORTED, "ballot form needs int columns, dense groups and LDS-sized counters");
+      e = pac::launch_agg_ballot(env, d, ds);
+      break;
+    case PAC_ALGO_MFMA_I8:
+      if (!pac::mfma_supported(d))
+        return fail(PAC_ERR_UNSUPPORTED, "int8 matrix-core form needs int columns, <= 254 dense groups and "
+                                         "groups x (digits+1) within the tile");
+      e = pac::launch_agg_mfma(env, d, ds);
+      break;
+    default:
+      return fail(PAC_ERR_INVALID, "unknown algorithm %u", algo);
+  }
+  if (e != hipSuccess) return hip_fail(e, "aggregate launch");
+  return PAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pac_last_error(void) { return g_err.c_str(); }
+
+int pac_version(void) { return 1; }
+
+int pac_ctx_create(int hip_device, pac_ctx **out) {
+  if (!out) return fail(PAC_ERR_INVALID, "out is null");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= n) return fail(PAC_ERR_INVALID, "device %d out of range (%d)", hip_device, n);
+  DeviceGuard guard(hip_device);
+  if (!guard.ok) return fail(PAC_ERR_HIP, "hipSetDevice(%d) failed", hip_device);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, hip_device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  pac_ctx *ctx = new pac_ctx();
+  ctx->device = hip_device;
+  ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  e = hipMalloc((void **)&ctx->d_status, sizeof(uint32_t));
+  if (e != hipSuccess) {
+    delete ctx;
+    return hip_fail(e, "status word allocation");
+  }
+  const uint32_t zero = 0;
+  e = hipMemcpy(ctx->d_status, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(ctx->d_status);
+    delete ctx;
+    return hip_fail(e, "status word init");
+  }
+  *out = ctx;
+  return PAC_OK;
+}
+
+int pac_ctx_destroy(pac_ctx *ctx) {
+  if (!ctx) return PAC_OK;
+  DeviceGuard guard(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->d_status) (void)hipFree(ctx->d_status);
+  delete ctx;
+  return PAC_OK;
+}
+
+int pac_check(pac_ctx *ctx, void *stream, uint32_t *status) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  uint32_t s = 0;
+  e = hipMemcpy(&s, ctx->d_status, sizeof(s), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "status read");
+  const uint32_t zero = 0;
+  e = hipMemcpy(ctx->d_status, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "status clear");
+  if (status) *status = s;
+  if (s) return fail(PAC_ERR_DEVICE_STATUS, "device status bits 0x%x", s);
+  return PAC_OK;
+}
+
+int pac_hash_mask(pac_ctx *ctx, void *stream, const int64_t *keys, int64_t n, uint64_t query_key, int m,
+                  uint32_t flags, uint64_t *out_masks) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
+  if (n < 0) return fail(PAC_ERR_INVALID, "n < 0");
+  if (n == 0) return PAC_OK;
+  if (!keys || !out_masks) return fail(PAC_ERR_INVALID, "null keys or out_masks");
+  if (flags & ~PAC_HASH_BALANCED) return fail(PAC_ERR_INVALID, "unknown hash flags 0x%x", flags);
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  hipError_t e = pac::launch_hash(env, keys, n, query_key, m, (flags & PAC_HASH_BALANCED) != 0, out_masks);
+  if (e != hipSuccess) return hip_fail(e, "hash launch");
+  return PAC_OK;
+}
+
+int pac_group_aggregate(pac_ctx *ctx, void *stream, const pac_agg_input *in, int m, uint64_t query_key,
+                        uint32_t algo, uint32_t flags, pac_agg_state *inout) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  if (flags & ~PAC_AGG_INIT) return fail(PAC_ERR_INVALID, "unknown aggregate flags 0x%x", flags);
+  DeviceGuard guard(ctx->device);
+  return run_one(ctx, (hipStream_t)stream, in, m, query_key, algo, flags, inout);
+}
+
+int pac_group_aggregate_batch(pac_ctx *ctx, void *stream, const pac_agg_input *in, const uint64_t *query_keys,
+                              int n_queries, int m, uint32_t algo, uint32_t flags, pac_agg_state *states) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  if (n_queries < 0) return fail(PAC_ERR_INVALID, "n_queries < 0");
+  if (n_queries > 0 && (!in || !query_keys || !states)) return fail(PAC_ERR_INVALID, "null batch arrays");
+  if (flags & ~PAC_AGG_INIT) return fail(PAC_ERR_INVALID, "unknown aggregate flags 0x%x", flags);
+  DeviceGuard guard(ctx->device);
+  for (int q = 0; q < n_queries; ++q) {
+    const int rc = run_one(ctx, (hipStream_t)stream, &in[q], m, query_keys[q], algo, flags, &states[q]);
+    if (rc != PAC_OK) {
+      std::string msg = g_err;
+      return fail(rc, "query %d: %s", q, msg.c_str());
+    }
+  }
+  return PAC_OK;
+}
+
+int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
+                 int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
+                 uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y) {
+  if (!ctx || !state || !params) return fail(PAC_ERR_INVALID, "null context, state or params");
+  if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
+  if (n_cells < 0 || n_int < 0 || n_float < 0 || n_groups < 1) return fail(PAC_ERR_INVALID, "bad sizes");
+  if (!posterior) return fail(PAC_ERR_INVALID, "posterior buffer is required");
+  if (!(params->mi_budget > 0.0)) return fail(PAC_ERR_INVALID, "mi_budget must be > 0");
+  if (params->j_star >= m) return fail(PAC_ERR_INVALID, "j_star out of range");
+  if (params->flags & ~31u) return fail(PAC_ERR_INVALID, "unknown finalize flags 0x%x", params->flags);
+  if (n_cells > 0 && (!cells || !out_val || !out_is_null || !out_flags || !state->count || !state->nrows))
+    return fail(PAC_ERR_INVALID, "null cell or output arrays");
+  if (n_int > 0 && !state->isum) return fail(PAC_ERR_INVALID, "state.isum missing");
+  if (n_float > 0 && !state->fsum) return fail(PAC_ERR_INVALID, "state.fsum missing");
+  DeviceGuard guard(ctx->device);
+  pac::DevState ds{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used};
+  pac::FinParams fp{params->mi_budget, params->noise_seed, params->j_star, params->flags, m, n_int, n_float, n_cells, n_groups};
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  hipError_t e = pac::launch_finalize(env, ds, cells, fp, out_val, out_is_null, out_flags, posterior, out_y);
+  if (e != hipSuccess) return hip_fail(e, "finalize launch");
+  return PAC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer counters must match bit for bit; fp64 sums within 1e-12 relative
+(positive data) or 1e-12 of the sum of magnitudes (signed data).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import native as ON
+from oracle import pac_ref as R
+from workloads import gen
+
+from cases import compare_counters, gpu_star, star_definition, star_oracle
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = ["plain", "ballot", "mfma"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2603_15023_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+# ----------------------------------------------------------------------------- a1 hash
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("balanced", [False, True])
+def test_hash_matches_oracle(ctx, torch_mod, m, balanced):
+    import paper_2603_15023_amd as P
+    g = np.random.default_rng(11)
+    n = 100_003
+    keys = g.integers(-(1 << 63), (1 << 63) - 1, size=n, dtype=np.int64)
+    keys[:3] = [0, -1, np.iinfo(np.int64).min]
+    K = 0x0123456789ABCDEF
+    _say("hash", m, balanced, n)
+    out = P.pac_hash_mask(ctx, torch_mod.from_numpy(keys).cuda(), K, m, balanced=balanced)
+    got = out.cpu().numpy().view(np.uint64)
+    want = R.pac_hash_np(keys, K, m, balanced) if not balanced else ON.hash_keys(keys, K, m, True)
+    assert np.array_equal(got, want)
+    assert ctx.check() == 0
+
+
+def test_hash_empty(ctx, torch_mod):
+    import paper_2603_15023_amd as P
+    out = P.pac_hash_mask(ctx, torch_mod.empty(0, dtype=torch_mod.int64, device="cuda"), 1, 64)
+    assert out.shape == (0, 1)
+
+
+# ----------------------------------------------------------------------------- a2-a6 small
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("m", [64, 128])
+def test_star_small_vs_definition(ctx, algo, m):
+    # 5000 rows: 19 full 256-row tiles and a ragged 136-row tail; 6 groups; filter on
+    t = gen.tiny_star(21, n_pu=300, n_orders=1200, n_rows=5000, gcards=(3, 2), n_cols=3,
+                      value_range=(-100_000, 9_000_000), with_sel=True)
+    K, lt = 0xBEEF, 3 << 30
+    ints = ["v0", "v1", "v2"]
+    _say("star small", algo, m)
+    got = gpu_star(ctx, t, K, m, filter_lt=lt, int_cols=ints, algo=algo)
+    want = star_definition(t, K, m, filter_lt=lt, int_cols=ints)
+    assert got["status"] == 0
+    compare_counters(got, want)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_star_no_stats_full_int64_range(ctx, algo):
+    # no column statistics: 8 byte digits (64 bits) per value, sums modulo 2^64
+    t = gen.tiny_star(22, n_pu=50, n_orders=200, n_rows=1500, gcards=(2,), n_cols=1,
+                      value_range=(-(1 << 62), (1 << 62)))
+    t.cols["v0"][:5] = [np.iinfo(np.int64).max, np.iinfo(np.int64).min, -1, 0, 1]
+    K = 77
+    _say("no stats", algo)
+    got = gpu_star(ctx, t, K, 64, int_cols=["v0"], algo=algo, stats=False)
+    want = star_definition(t, K, 64, int_cols=["v0"])
+    compare_counters(got, want)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_int32_column_and_balanced_fused_hash(ctx, algo):
+    t = gen.tiny_star(23, n_pu=80, n_orders=400, n_rows=3001, gcards=(4,), n_cols=2, value_range=(-50, 50))
+    t.cols["v1"] = t.cols["v1"].astype(np.int32)
+    K = 5
+    _say("int32 balanced fused", algo)
+    got = gpu_star(ctx, t, K, 64, int_cols=["v0", "v1"], algo=algo, balanced=True, fused=True)
+    want = star_definition(t, K, 64, int_cols=["v0", "v1"], balanced=True)
+    compare_counters(got, want)
+    assert np.array_equal(got["count"].sum(axis=1), 32 * got["nrows"])
+
+
+@pytest.mark.parametrize("m", [64, 128])
+def test_float_columns_plain(ctx, m):
+    t = gen.tiny_star(24, n_pu=100, n_orders=500, n_rows=4000, gcards=(3,), n_cols=1, float_cols=0)
+    g = np.random.default_rng(3)
+    t.cols["f0"] = g.lognormal(0.0, 2.0, size=t.n_rows)
+    t.cols["f1"] = g.lognormal(0.0, 2.0, size=t.n_rows).astype(np.float32)
+    K = 99
+    _say("float plain", m)
+    got = gpu_star(ctx, t, K, m, int_cols=["v0"], float_cols=["f0", "f1"], algo="plain")
+    want = star_definition(t, K, m, int_cols=["v0"], float_cols=["f0", "f1"])
+    compare_counters(got, want)
+
+
+def test_float_signed_against_magnitude_bound(ctx):
+    t = gen.tiny_star(25, n_pu=100, n_orders=500, n_rows=4000, gcards=(2,), n_cols=0, float_cols=1)
+    K = 3
+    got = gpu_star(ctx, t, K, 64, float_cols=["f0"], algo="plain")
+    want = star_definition(t, K, 64, float_cols=["f0"])
+    t.cols["f0"] = np.abs(t.cols["f0"])
+    mag = star_definition(t, K, 64, float_cols=["f0"])
+    assert np.all(np.abs(got["fsum"] - want["fsum"]) <= 1e-12 * mag["fsum"] + 1e-300)
+
+
+def test_empty_and_fully_filtered(ctx):
+    t = gen.tiny_star(26, n_pu=10, n_orders=20, n_rows=0, gcards=(2,), n_cols=1, with_sel=True)
+    for algo in ALGOS:
+        got = gpu_star(ctx, t, 1, 64, int_cols=["v0"], algo=algo, stats=False)
+        assert not got["count"].any() and not got["nrows"].any()
+    t = gen.tiny_star(27, n_pu=10, n_orders=20, n_rows=700, gcards=(2,), n_cols=1, with_sel=True)
+    for algo in ALGOS:
+        got = gpu_star(ctx, t, 1, 64, filter_lt=0, int_cols=["v0"], algo=algo)
+        assert not got["count"].any() and not got["isum"].any() and not got["nrows"].any()
+
+
+def test_bad_group_value_sets_status(ctx):
+    t = gen.tiny_star(28, n_pu=10, n_orders=20, n_rows=600, gcards=(3,), n_cols=1)
+    t.gcols[0][100] = 7  # outside its declared cardinality
+    for algo in ALGOS:
+        got = gpu_star(ctx, t, 1, 64, int_cols=["v0"], algo=algo)
+        assert got["status"] & 1, algo
+        keep = np.ones(t.n_rows, dtype=bool)
+        keep[100] = False
+        assert got["nrows"].sum() == keep.sum()
+
+
+def test_bad_link_sets_status(ctx):
+    t = gen.tiny_star(29, n_pu=10, n_orders=20, n_rows=300, gcards=(2,), n_cols=1)
+    t.f_order = t.f_order.copy()
+    t.f_order[5] = 10_000
+    got = gpu_star(ctx, t, 1, 64, int_cols=["v0"], algo="plain")
+    assert got["status"] & 2
+
+
+# ----------------------------------------------------------------------------- full-size workloads
+@pytest.mark.parametrize("algo", ALGOS)
+def test_config1_full_size(ctx, torch_mod, algo):
+    import paper_2603_15023_amd as P
+    t = gen.config1_flat()
+    K = gen.query_key(0)
+    _say("config1", algo)
+    dev = torch_mod.device("cuda")
+    keys = torch_mod.from_numpy(t.pu_key).to(dev)
+    val = torch_mod.from_numpy(t.cols["value"]).to(dev)
+    masks = P.pac_hash_mask(ctx, keys, K, 64)
+    spec = P.AggSpec(n_rows=t.n_rows, masks=masks, cols=[val], stats=[(1, 50)])
+    st = P.new_state(spec, 64)
+    P.pac_group_aggregate(ctx, spec, st, m=64, query_key=K, algo=algo)
+    assert ctx.check() == 0
+    want = ON.onepass(t.n_rows, 64, pu_keys=t.pu_key, query_key=K, int_cols=[t.cols["value"]])
+    compare_counters({k: v.cpu().numpy() for k, v in st.items()}, want)
+
+
+@pytest.mark.parametrize("algo", ["mfma", "plain"])
+def test_config2_full_size(ctx, algo):
+    t = _config2()
+    K = gen.query_key(1)
+    ints = ["v1", "v2", "v3"]
+    _say("config2", algo)
+    got = gpu_star(ctx, t, K, 64, int_cols=ints, algo=algo)
+    assert got["status"] == 0
+    compare_counters(got, _config2_oracle())
+
+
+_C2 = {}
+
+
+def _config2():
+    if "t" not in _C2:
+        _C2["t"] = gen.config2_star()
+    return _C2["t"]
+
+
+def _config2_oracle():
+    if "want" not in _C2:
+        _C2["want"] = star_oracle(_config2(), gen.query_key(1), 64, int_cols=["v1", "v2", "v3"])
+    return _C2["want"]
+
+
+def test_sparse_group_keys(ctx, torch_mod):
+    import paper_2603_15023_amd as P
+    t = gen.tiny_flat(30, n_rows=200_000, n_keys=5000, n_groups=3000, sparse_groups=True,
+                      value_range=(-10**9, 10**9))
+    K = 17
+    dev = torch_mod.device("cuda")
+    spec = P.AggSpec(n_rows=t.n_rows, pu_keys=torch_mod.from_numpy(t.pu_key).to(dev),
+                     group_keys=torch_mod.from_numpy(t.group_keys).to(dev), n_groups=8192,
+                     cols=[torch_mod.from_numpy(t.cols["v"]).to(dev)])
+    st = P.new_state(spec, 64)
+    P.pac_group_aggregate(ctx, spec, st, m=64, query_key=K, algo="auto")
+    assert ctx.check() == 0
+    slot_keys = st["slot_keys"].cpu().numpy()
+    used = slot_keys != np.iinfo(np.int64).min
+    assert int(st["n_used"].cpu()[0]) == used.sum() == 3000
+    order = np.argsort(slot_keys[used])
+    got = {k: st[k].cpu().numpy()[used][order] for k in ("count", "isum", "nrows")}
+    got["fsum"] = np.zeros((3000, 0, 64))
+    want = ON.onepass(t.n_rows, 64, pu_keys=t.pu_key, query_key=K, group_keys=t.group_keys, n_groups=4000,
+                      int_cols=[t.cols["v"]])
+    assert np.array_equal(slot_keys[used][order], want["keys"])
+    compare_counters(got, want)
+
+
+def test_repeat_runs_are_identical(ctx):
+    t = gen.tiny_star(31, n_pu=300, n_orders=3000, n_rows=50_000, gcards=(3, 2), n_cols=1, float_cols=0)
+    t.cols["f0"] = np.random.default_rng(1).lognormal(0, 2, size=t.n_rows)
+    a = gpu_star(ctx, t, 9, 64, int_cols=["v0"], float_cols=["f0"], algo="plain")
+    b = gpu_star(ctx, t, 9, 64, int_cols=["v0"], float_cols=["f0"], algo="plain")
+    assert np.array_equal(a["fsum"], b["fsum"]) and np.array_equal(a["isum"], b["isum"])
+    c = gpu_star(ctx, t, 9, 64, int_cols=["v0"], algo="mfma")
+    d = gpu_star(ctx, t, 9, 64, int_cols=["v0"], algo="mfma")
+    assert np.array_equal(c["isum"], d["isum"]) and np.array_equal(c["isum"], a["isum"])
+
+
+# ----------------------------------------------------------------------------- a7 release
+@pytest.mark.parametrize("m", [64, 128])
+def test_finalize_matches_oracle(ctx, torch_mod, m):
+    import paper_2603_15023_amd as P
+    t = gen.tiny_star(32, n_pu=40, n_orders=400, n_rows=6000, gcards=(3, 2), n_cols=2, value_range=(1, 10**6))
+    t.cols["f0"] = np.random.default_rng(2).lognormal(0, 2, size=t.n_rows)
+    K = 1234
+    ints, flts = ["v0", "v1"], ["f0"]
+    got = gpu_star(ctx, t, K, m, int_cols=ints, float_cols=flts, algo="plain")
+    counters = {k: got[k] for k in ("count", "isum", "fsum", "nrows")}
+    cells = []
+    for g in range(6):
+        cells += [(g, R.KIND_COUNT, 0), (g, R.KIND_SUM_I, 0), (g, R.KIND_AVG_I, 1), (g, R.KIND_SUM_F, 0),
+                  (g, R.KIND_AVG_F, 0)]
+    seed, B = 0xC0FFEE01, 1.0 / 128
+    dev = torch_mod.device("cuda")
+    state = {k: torch_mod.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in counters.items()}
+    ct = P.cells_tensor(cells)
+    vals, nulls, flags, post, ys = P.pac_finalize(ctx, state, ct, len(cells), m=m, mi_budget=B, noise_seed=seed,
+                                                 want_y=True)
+    assert ctx.check() == 0
+    wv, wn, wf, wP, wy = R.release(counters, cells, m, B, seed)
+    assert np.array_equal(ys.cpu().numpy(), wy)
+    assert np.array_equal(nulls.cpu().numpy(), wn)
+    assert np.array_equal(flags.cpu().numpy().astype(np.uint32), wf)
+    np.testing.assert_allclose(vals.cpu().numpy(), wv, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(post.cpu().numpy(), wP, rtol=1e-9, atol=1e-300)
