@@ -35,8 +35,14 @@ namespace pac {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned long long v2u64 __attribute__((ext_vector_type(2)));
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
 constexpr int kTileRows = 256;
+// Byte planes hold 256 rows; consecutive planes are 272 bytes apart so that
+// the 16 lanes of a group reading 16 bytes from 16 different planes hit
+// different LDS banks.
+constexpr int kPlaneStride = 272;
 constexpr int kMaxNT = 8;
 
 struct MfmaPlan {
@@ -47,7 +53,8 @@ struct MfmaPlan {
   int32_t dig[kMaxCols];
   int32_t doff[kMaxCols];
   int64_t lo[kMaxCols];
-  int32_t wave_bytes;   // per-wave LDS: planes, reused as the flush buffer
+  int32_t wave_bytes;   // per-wave LDS: planes (reused as the flush buffer), then the staging area
+  int32_t stage_off;
   int32_t blk_off;      // block-shared int64 counters [G][1+ni][m] + nrows[G]
   int32_t blk_words;
   int32_t flush_tiles;  // tiles between accumulator flushes (int32 headroom)
@@ -59,28 +66,55 @@ __device__ __forceinline__ uint32_t dpp_xor1(uint32_t x) {
 __device__ __forceinline__ uint32_t dpp_xor2(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
 }
-__device__ __forceinline__ uint32_t swz_xor4(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x101F);  // bit mode: lane ^ 4
+// lane ^ 4 inside a row of 16: banks 0 and 2 (lanes 0-3, 8-11) read lane + 4
+// (row_ror:12), banks 1 and 3 read lane - 4 (row_ror:4).
+__device__ __forceinline__ uint32_t dpp_xor4(uint32_t x) {
+  const int t = __builtin_amdgcn_update_dpp((int)x, (int)x, 0x12C, 0xF, 0x5, false);
+  return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)x, 0x124, 0xF, 0xA, false);
 }
 __device__ __forceinline__ uint32_t dpp_xor8(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);  // row_ror:8 == lane ^ 8 in a row
 }
 
 // One exchange stage of the 16x16 bit transposes held in the two 16-bit
-// halves of x: swap bit b of the lane index with bit b of the bit position.
-template <int B>
-__device__ __forceinline__ uint32_t tstage(uint32_t x, uint32_t partner, bool lower) {
-  constexpr uint32_t lo_mask = B == 8 ? 0x00FF00FFu : B == 4 ? 0x0F0F0F0Fu : B == 2 ? 0x33333333u : 0x55555555u;
-  const uint32_t keep = lower ? lo_mask : ~lo_mask;
-  const uint32_t rot = __builtin_amdgcn_alignbit(partner, partner, lower ? 32 - B : B);
-  return (keep & x) | (~keep & rot);
+// halves of x: swap bit B of the lane index with bit B of the bit position.
+// The lower lane of a pair keeps its bits whose position has bit B clear and
+// takes the partner's such bits rotated up by B; the upper lane keeps the
+// others and takes the partner's bits rotated down by B.  Per-lane constants:
+// keep mask and rotation amount of each stage.
+struct TransposeConsts {
+  uint32_t keep[4];
+  uint32_t rot[4];
+};
+
+__device__ __forceinline__ TransposeConsts transpose_consts(int lane) {
+  TransposeConsts t;
+  const uint32_t lo_masks[4] = {0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int b = 8 >> s;
+    const bool lower = (lane & b) == 0;
+    t.keep[s] = lower ? lo_masks[s] : ~lo_masks[s];
+    t.rot[s] = lower ? 32 - b : b;
+  }
+  return t;
 }
 
-__device__ __forceinline__ uint32_t transpose16x2(uint32_t x, int lane) {
-  x = tstage<8>(x, dpp_xor8(x), (lane & 8) == 0);
-  x = tstage<4>(x, swz_xor4(x), (lane & 4) == 0);
-  x = tstage<2>(x, dpp_xor2(x), (lane & 2) == 0);
-  x = tstage<1>(x, dpp_xor1(x), (lane & 1) == 0);
+__device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm volatile("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(mask), "v"(a), "v"(b));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t transpose16x2(uint32_t x, const TransposeConsts &tc) {
+  uint32_t p = dpp_xor8(x);
+  x = bfi(tc.keep[0], x, __builtin_amdgcn_alignbit(p, p, tc.rot[0]));
+  p = dpp_xor4(x);
+  x = bfi(tc.keep[1], x, __builtin_amdgcn_alignbit(p, p, tc.rot[1]));
+  p = dpp_xor2(x);
+  x = bfi(tc.keep[2], x, __builtin_amdgcn_alignbit(p, p, tc.rot[2]));
+  p = dpp_xor1(x);
+  x = bfi(tc.keep[3], x, __builtin_amdgcn_alignbit(p, p, tc.rot[3]));
   return x;
 }
 
@@ -104,39 +138,327 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Loads 4 consecutive unsigned group values starting at row r0 (guarded tail).
-__device__ __forceinline__ void load4_gcol(const void *p, int type, int64_t r0, int64_t n, uint32_t (&v)[4]) {
-  if (r0 + 3 < n) {
-    if (type == PAC_U8) {
-      const uint32_t w = *(const uint32_t *)((const uint8_t *)p + r0);
-      v[0] = w & 0xFF; v[1] = (w >> 8) & 0xFF; v[2] = (w >> 16) & 0xFF; v[3] = w >> 24;
-    } else if (type == PAC_U16) {
-      const uint2 w = *(const uint2 *)((const uint16_t *)p + r0);
-      v[0] = w.x & 0xFFFF; v[1] = w.x >> 16; v[2] = w.y & 0xFFFF; v[3] = w.y >> 16;
-    } else {
-      const uint4 w = *(const uint4 *)((const uint32_t *)p + r0);
-      v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
-    }
-  } else {
+constexpr int kMC = 4;  // int columns / links handled by this path
+constexpr int kMG = 2;  // group columns handled by this path
+
+// Compact kernel arguments of the matrix-core path.  Row-indexed pointers
+// (columns, first link, or the mask table when there is no link) are offset
+// to the first row of the launch, so rows and table indices are 32-bit.
+struct MfmaArgs {
+  int32_t n_links;
+  const int32_t *links[kMC];
+  uint32_t link_len[kMC];
+  const uint64_t *masks;
+  const int64_t *pu_keys;
+  uint32_t n_idx;  // rows of the mask table (or of pu_keys); >= 1
+  uint64_t qk;
+  uint32_t balanced;
+  int32_t n_gcols;
+  const uint8_t *gcols[kMG];
+  int32_t gcol_bytes[kMG];  // 1, 2 or 4
+  uint32_t gcards[kMG];
+  uint32_t group_mod;
+  const uint32_t *filter_col;
+  uint32_t filter_lt;
+  const uint8_t *icols[kMC];
+  int32_t icol_bytes[kMC];  // 4 or 8
+  uint32_t n_rows;          // rows of this launch
+};
+
+// ---------------------------------------------------------------- FK chain
+// Indices of the four K-chunk rows (64u + lane) of a tile after some chain
+// levels, with their validity.  Every load below is unconditional: invalid
+// lanes read index 0 of a non-empty table and are masked when the words are
+// staged, so the compiler never has to wait for a load before it is used.
+struct Chain {
+  uint32_t idx[4];
+  bool ok[4];
+};
+
+__device__ __forceinline__ void chain_rows(const MfmaArgs &a, uint32_t row0, int lane, Chain &c) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = r0 + i < n ? load_gcol(p, type, r0 + i) : 0u;
+  for (int u = 0; u < 4; ++u) {
+    const uint32_t r = row0 + 64u * u + lane;
+    c.ok[u] = r < a.n_rows;
+    c.idx[u] = r;
   }
 }
 
-__device__ __forceinline__ void load4_icol(const void *p, int type, int64_t r0, int64_t n, uint64_t (&v)[4]) {
-  if (r0 + 3 < n) {
-    if (type == PAC_I32) {
-      const v4i w = __builtin_nontemporal_load((const v4i *)((const int32_t *)p + r0));
-      v[0] = (uint64_t)(int64_t)w[0]; v[1] = (uint64_t)(int64_t)w[1];
-      v[2] = (uint64_t)(int64_t)w[2]; v[3] = (uint64_t)(int64_t)w[3];
-    } else {
-      const v2u64 a = __builtin_nontemporal_load((const v2u64 *)((const int64_t *)p + r0));
-      const v2u64 b = __builtin_nontemporal_load((const v2u64 *)((const int64_t *)p + r0 + 2));
-      v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
-    }
-  } else {
+__device__ __forceinline__ void chain_level(const MfmaArgs &a, int k, Chain &c) {
+  const int32_t *lk = a.links[k];
+  const uint32_t len = a.link_len[k];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = r0 + i < n ? (uint64_t)load_icol(p, type, r0 + i) : 0ull;
+  for (int u = 0; u < 4; ++u) {
+    c.ok[u] = c.ok[u] && c.idx[u] < len;
+    c.idx[u] = (uint32_t)lk[c.ok[u] ? c.idx[u] : 0u];
+  }
+}
+
+// Raw words of one tile in flight: PU words of rows 64u + lane and column
+// words of rows 4*lane .. 4*lane + 3, exactly as loaded.
+template <int W, int NI>
+struct Raw {
+  uint64_t mk[4][W];
+  bool ok[4];
+  uint32_t g[kMG][4];
+  uint32_t f[4];
+  uint32_t v[NI > 0 ? NI : 1][8];
+};
+
+template <int W, int NI>
+__device__ __forceinline__ void issue_words(const MfmaArgs &a, Chain c, Raw<W, NI> &r) {
+  for (int k = 2; k < a.n_links; ++k) chain_level(a, k, c);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    r.ok[u] = c.ok[u] && c.idx[u] < a.n_idx;
+    const uint32_t si = r.ok[u] ? c.idx[u] : 0u;
+    if (a.masks) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) r.mk[u][w] = a.masks[(size_t)si * W + w];
+    } else {
+      r.mk[u][0] = (uint64_t)a.pu_keys[si];  // hashed when staged
+    }
+  }
+}
+
+// Column words of the full tile starting at row0 (no bounds checks).
+template <int W, int NI>
+__device__ __forceinline__ void issue_cols(const MfmaArgs &a, uint32_t row0, int lane, Raw<W, NI> &r) {
+  const uint32_t r4 = row0 + 4 * lane;
+#pragma unroll
+  for (int k = 0; k < kMG; ++k) {
+    if (k < a.n_gcols) {
+      const int gb = a.gcol_bytes[k];
+      const uint8_t *base = a.gcols[k] + (size_t)r4 * gb;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) r.g[k][j] = *(const uint32_t *)(base + 4 * min(j, gb - 1));
+    }
+  }
+  if (a.filter_col) {
+    const v4u32 w = __builtin_nontemporal_load((const v4u32 *)(a.filter_col + r4));
+    r.f[0] = w[0]; r.f[1] = w[1]; r.f[2] = w[2]; r.f[3] = w[3];
+  }
+#pragma unroll
+  for (int c = 0; c < NI; ++c) {
+    const int eb = a.icol_bytes[c];
+    const uint8_t *base = a.icols[c] + (size_t)r4 * eb;
+    const v4u32 x = __builtin_nontemporal_load((const v4u32 *)base);
+    const v4u32 y = __builtin_nontemporal_load((const v4u32 *)(base + (eb == 8 ? 16 : 0)));
+    r.v[c][0] = x[0]; r.v[c][1] = x[1]; r.v[c][2] = x[2]; r.v[c][3] = x[3];
+    r.v[c][4] = y[0]; r.v[c][5] = y[1]; r.v[c][6] = y[2]; r.v[c][7] = y[3];
+  }
+}
+
+// Column words of a partial tile (bounds-checked element loads).
+template <int W, int NI>
+__device__ __forceinline__ void issue_cols_tail(const MfmaArgs &a, uint32_t row0, int lane, Raw<W, NI> &r) {
+  const uint32_t r4 = row0 + 4 * lane, n = a.n_rows;
+#pragma unroll
+  for (int k = 0; k < kMG; ++k) {
+    if (k < a.n_gcols) {
+      const int gb = a.gcol_bytes[k];
+      uint32_t v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t row = r4 + i;
+        v[i] = row < n ? (gb == 1 ? a.gcols[k][row] : gb == 2 ? ((const uint16_t *)a.gcols[k])[row]
+                                                              : ((const uint32_t *)a.gcols[k])[row])
+                       : 0u;
+      }
+      if (gb == 1) {
+        r.g[k][0] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+      } else if (gb == 2) {
+        r.g[k][0] = v[0] | (v[1] << 16);
+        r.g[k][1] = v[2] | (v[3] << 16);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r.g[k][i] = v[i];
+      }
+    }
+  }
+  if (a.filter_col) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.f[i] = r4 + i < n ? a.filter_col[r4 + i] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int c = 0; c < NI; ++c) {
+    const int eb = a.icol_bytes[c];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t row = r4 + i;
+      if (eb == 8) {
+        const uint64_t x = row < n ? ((const uint64_t *)a.icols[c])[row] : 0ull;
+        r.v[c][2 * i] = (uint32_t)x;
+        r.v[c][2 * i + 1] = (uint32_t)(x >> 32);
+      } else {
+        r.v[c][i] = row < n ? ((const uint32_t *)a.icols[c])[row] : 0u;
+      }
+    }
+  }
+}
+
+// Wave-private LDS staging of one tile's words, field-major ([field][lane])
+// so that a wave's accesses hit consecutive banks.  Lane l stores and reads
+// back only its own words: no cross-lane ordering is needed.
+template <int W, int NI>
+struct Stage {
+  uint64_t mk[4][W][64];
+  uint32_t g[kMG][4][64];
+  uint32_t f[4][64];
+  uint32_t v[NI > 0 ? NI : 1][8][64];
+};
+
+template <int W, int NI>
+__device__ __forceinline__ void stage_store(Stage<W, NI> *sg, int lane, const MfmaArgs &a, const Raw<W, NI> &r) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (a.masks) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) sg->mk[u][w][lane] = r.ok[u] ? r.mk[u][w] : 0ull;
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        sg->mk[u][w][lane] = r.ok[u] ? pu_word((int64_t)r.mk[u][0], a.qk, w, a.balanced != 0) : 0ull;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMG; ++k)
+    if (k < a.n_gcols)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sg->g[k][j][lane] = r.g[k][j];
+  if (a.filter_col)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sg->f[j][lane] = r.f[j];
+#pragma unroll
+  for (int c = 0; c < NI; ++c)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sg->v[c][j][lane] = r.v[c][j];
+}
+
+// ---------------------------------------------------------------- planes (B side)
+// Group byte planes, row counts and digit planes of the staged tile.
+template <int W, int NI>
+__device__ __forceinline__ void build_planes(const MfmaArgs &a, const MfmaPlan &pl, const Stage<W, NI> *sg,
+                                             uint32_t r4, uint8_t *planes, int64_t *blk, int nrows_off, int lane,
+                                             uint32_t *status) {
+  const uint32_t n = a.n_rows;
+  const int G = pl.G, gplane0 = pl.D + 2;
+  uint32_t gv[4] = {0, 0, 0, 0};
+  bool ok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ok[i] = r4 + i < n;
+#pragma unroll
+  for (int k = 0; k < kMG; ++k) {
+    if (k < a.n_gcols) {
+      const int gb = a.gcol_bytes[k];
+      uint32_t x[4];
+      if (gb == 1) {
+        const uint32_t w = sg->g[k][0][lane];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = (w >> (8 * i)) & 0xFFu;
+      } else if (gb == 2) {
+        const uint32_t w0 = sg->g[k][0][lane], w1 = sg->g[k][1][lane];
+        x[0] = w0 & 0xFFFFu; x[1] = w0 >> 16; x[2] = w1 & 0xFFFFu; x[3] = w1 >> 16;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = sg->g[k][i][lane];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ok[i] = ok[i] && x[i] < a.gcards[k];
+        gv[i] = __umul24(gv[i], a.gcards[k]) + x[i];
+      }
+    }
+  }
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bad = bad || (r4 + i < n && !ok[i]);
+  if (a.group_mod > 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gv[i] = gv[i] % a.group_mod;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ok[i] = ok[i] && gv[i] < (uint32_t)G;
+  if (a.filter_col) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ok[i] = ok[i] && sg->f[i][lane] < a.filter_lt;
+  }
+  if (bad) atomicOr(status, PAC_STATUS_BAD_GROUP);
+  uint32_t gid4 = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) gid4 |= (ok[i] ? gv[i] : 0xFFu) << (8 * i);
+  for (int g = 0; g < G; ++g) {
+    const uint32_t x = gid4 ^ ((uint32_t)g * 0x01010101u);
+    const uint32_t nz = (x | ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu)) & 0x80808080u;
+    const uint32_t z = nz ^ 0x80808080u;
+    const uint32_t gm = z | (z - (z >> 7));
+    ((uint32_t *)(planes + (gplane0 + g) * kPlaneStride))[lane] = gm;
+    const unsigned cnt = __popcll(__ballot(gm & 0xFF)) + __popcll(__ballot(gm & 0xFF00)) +
+                         __popcll(__ballot(gm & 0xFF0000)) + __popcll(__ballot(gm & 0xFF000000u));
+    if (lane == 0 && cnt) atomicAdd((unsigned long long *)&blk[nrows_off + g], (unsigned long long)cnt);
+  }
+#pragma unroll
+  for (int c = 0; c < NI; ++c) {
+    const bool wide = a.icol_bytes[c] == 8;
+    uint32_t lo32[4], hi32[4];
+    if (pl.dig[c] <= 4) {  // (v - lo) mod 2^32 already holds every non-zero byte
+#pragma unroll
+      for (int i = 0; i < 4; ++i) lo32[i] = sg->v[c][wide ? 2 * i : i][lane] - (uint32_t)pl.lo[c];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        uint64_t x;
+        if (wide)
+          x = ((uint64_t)sg->v[c][2 * i + 1][lane] << 32) | sg->v[c][2 * i][lane];
+        else
+          x = (uint64_t)(int64_t)(int32_t)sg->v[c][i][lane];
+        x -= (uint64_t)pl.lo[c];
+        lo32[i] = (uint32_t)x;
+        hi32[i] = (uint32_t)(x >> 32);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (s < pl.dig[c]) {
+        const uint32_t word = s < 4 ? pack_byte(lo32[0], lo32[1], lo32[2], lo32[3], s)
+                                    : pack_byte(hi32[0], hi32[1], hi32[2], hi32[3], s - 4);
+        ((uint32_t *)(planes + (pl.doff[c] + s) * kPlaneStride))[lane] = word ^ 0x80808080u;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- matrix work (A side + mfma)
+template <int W, int NT, int NI>
+__device__ __forceinline__ void mfma_tile(const Stage<W, NI> *sg, int lane, const uint8_t *planes,
+                                          const int (&boff_d)[NT], const int (&boff_g)[NT],
+                                          const TransposeConsts &tcs, int q, v4i (&acc)[4 * W][NT]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    v4i av[4 * W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t word = sg->mk[u][w][lane];
+      const uint32_t lo = transpose16x2((uint32_t)word, tcs);
+      const uint32_t hi = transpose16x2((uint32_t)(word >> 32), tcs);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const uint32_t x = h < 2 ? lo : hi;
+        const int sh = (h & 1) * 16;
+        av[4 * w + h] = v4i{expand_nibble(x, sh), expand_nibble(x, sh + 4), expand_nibble(x, sh + 8),
+                            expand_nibble(x, sh + 12)};
+      }
+    }
+    const int roff = 64 * u + 16 * q;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const v4i dgt = *(const v4i *)(planes + boff_d[nt] + roff);
+      const v4i gmk = *(const v4i *)(planes + boff_g[nt] + roff);
+      const v4i b = dgt & gmk;
+#pragma unroll
+      for (int mt = 0; mt < 4 * W; ++mt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[mt], b, acc[mt][nt], 0, 0, 0);
+    }
   }
 }
 
@@ -157,7 +479,7 @@ __device__ __forceinline__ void flush_acc(v4i (&acc)[4 * W][NT], uint8_t *buf, i
 #pragma unroll
       for (int r = 0; r < 4; ++r) R[(4 * q + r) * ncp + nt * 16 + p] = acc[mt][nt][r];
     wave_lds_fence();
-    const int wl = p;                 // world within this M-tile
+    const int wl = p;  // world within this M-tile
     const int world = 16 * mt + wl;
     for (int gc = q; gc < GA; gc += 4) {
       const int g = gc / A, c = gc - g * A;
@@ -174,10 +496,7 @@ __device__ __forceinline__ void flush_acc(v4i (&acc)[4 * W][NT], uint8_t *buf, i
         }
         val = (int64_t)s;
       }
-      if (val) {
-        // blk layout: [g][c][m] with c = ni meaning COUNT
-        atomicAdd((unsigned long long *)&blk[((int64_t)g * A + c) * m + world], (unsigned long long)val);
-      }
+      if (val) atomicAdd((unsigned long long *)&blk[((int64_t)g * A + c) * m + world], (unsigned long long)val);
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
@@ -185,22 +504,25 @@ __device__ __forceinline__ void flush_acc(v4i (&acc)[4 * W][NT], uint8_t *buf, i
   wave_lds_fence();
 }
 
-template <int W, int NT>
-__global__ __launch_bounds__(256) void agg_mfma(DevInput in, DevState st, uint32_t *status, MfmaPlan pl) {
+template <int W, int NT, int NI>
+__global__ __launch_bounds__(256, (16 * W * NT > 64) ? 1 : 2) void agg_mfma(MfmaArgs a, MfmaPlan pl, DevState st,
+                                                                          uint32_t *status) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   constexpr int m = 64 * W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, p = lane & 15;
   const int waves = blockDim.x >> 6;
-  uint8_t *planes = smem + wave * pl.wave_bytes;
+  uint8_t *wbase = smem + wave * pl.wave_bytes;
+  uint8_t *planes = wbase;
+  Stage<W, NI> *stage = (Stage<W, NI> *)(wbase + pl.stage_off);
   int64_t *blk = (int64_t *)(smem + pl.blk_off);
   const int D = pl.D, G = pl.G;
   const int ones_plane = D, zero_plane = D + 1, gplane0 = D + 2;
+  const int nrows_off = G * (1 + NI) * m;
 
   for (int i = threadIdx.x; i < pl.blk_words; i += blockDim.x) blk[i] = 0;
-  // constant planes
-  ((uint32_t *)(planes + ones_plane * 256))[lane] = 0x01010101u;
-  ((uint32_t *)(planes + zero_plane * 256))[lane] = 0u;
+  ((uint32_t *)(planes + ones_plane * kPlaneStride))[lane] = 0x01010101u;
+  ((uint32_t *)(planes + zero_plane * kPlaneStride))[lane] = 0u;
   __syncthreads();
 
   int boff_d[NT], boff_g[NT];
@@ -209,13 +531,14 @@ __global__ __launch_bounds__(256) void agg_mfma(DevInput in, DevState st, uint32
     const int n = nt * 16 + p;
     if (n < pl.ncols) {
       const int g = n / (D + 1), t = n - g * (D + 1);
-      boff_d[nt] = (t < D ? t : ones_plane) * 256;
-      boff_g[nt] = (gplane0 + g) * 256;
+      boff_d[nt] = (t < D ? t : ones_plane) * kPlaneStride;
+      boff_g[nt] = (gplane0 + g) * kPlaneStride;
     } else {
-      boff_d[nt] = ones_plane * 256;
-      boff_g[nt] = zero_plane * 256;
+      boff_d[nt] = ones_plane * kPlaneStride;
+      boff_g[nt] = zero_plane * kPlaneStride;
     }
   }
+  const TransposeConsts tcs = transpose_consts(lane);
 
   v4i acc[4 * W][NT];
 #pragma unroll
@@ -223,139 +546,91 @@ __global__ __launch_bounds__(256) void agg_mfma(DevInput in, DevState st, uint32
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
 
-  const int64_t n = in.n_rows;
-  const int64_t n_tiles = (n + kTileRows - 1) / kTileRows;
-  const int64_t total_waves = (int64_t)gridDim.x * waves;
-  int since_flush = 0;
-  for (int64_t tile = (int64_t)blockIdx.x * waves + wave; tile < n_tiles; tile += total_waves) {
-    const int64_t row0 = tile * kTileRows;
-    // ---- PU words of rows row0 + 64u + lane (A side)
-    uint64_t mk[4][W];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t r = row0 + 64 * u + lane;
-#pragma unroll
-      for (int w = 0; w < W; ++w) mk[u][w] = 0;
-      int64_t idx;
-      if (r < n && chain_index(in, r, &idx, status)) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) mk[u][w] = pu_of_index(in, idx, w);
-      }
+  const uint32_t n_full = a.n_rows / kTileRows;  // full tiles: pipelined, unchecked loads
+  const uint32_t stride = gridDim.x * waves;
+  const uint32_t first = blockIdx.x * waves + wave;
+  const int pre = a.n_links < 2 ? a.n_links : 2;  // chain levels gathered ahead
+  if (first < n_full) {
+    const uint32_t last = n_full - 1;
+    auto clampt = [&](uint32_t t) { return t < n_full ? t : last; };
+    uint32_t tile = first;
+    {  // prologue: stage tile `first`
+      Raw<W, NI> r;
+      Chain c;
+      chain_rows(a, tile * kTileRows, lane, c);
+      for (int k = 0; k < pre; ++k) chain_level(a, k, c);
+      issue_words<W, NI>(a, c, r);
+      issue_cols<W, NI>(a, tile * kTileRows, lane, r);
+      stage_store<W, NI>(stage, lane, a, r);
     }
-    // ---- group ids of rows row0 + 4*lane + i (B side), 0xFF = no group
-    const int64_t r4 = row0 + 4 * lane;
-    uint32_t gv[4] = {0, 0, 0, 0};
-    bool ok[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ok[i] = r4 + i < n;
-    for (int k = 0; k < in.n_gcols; ++k) {
-      uint32_t v[4];
-      load4_gcol(in.gcols[k], in.gcol_type[k], r4, n, v);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ok[i] = ok[i] && (int64_t)v[i] < in.gcards[k];
-        gv[i] = gv[i] * (uint32_t)in.gcards[k] + v[i];
-      }
+    Chain l1, l0;  // tile + stride after `pre` links, tile + 2 stride after one link
+    chain_rows(a, clampt(tile + stride) * kTileRows, lane, l1);
+    for (int k = 0; k < pre; ++k) chain_level(a, k, l1);
+    chain_rows(a, clampt(tile + 2 * stride) * kTileRows, lane, l0);
+    if (a.n_links > 0) chain_level(a, 0, l0);
+    for (; tile < n_full; tile += stride) {
+      // ---- issue the next tile's words and the chain two and three tiles ahead
+      Raw<W, NI> r;
+      issue_words<W, NI>(a, l1, r);
+      issue_cols<W, NI>(a, clampt(tile + stride) * kTileRows, lane, r);
+      Chain n1 = l0;
+      if (a.n_links > 1) chain_level(a, 1, n1);
+      chain_rows(a, clampt(tile + 3 * stride) * kTileRows, lane, l0);
+      if (a.n_links > 0) chain_level(a, 0, l0);
+      // ---- tile t from the stage (its words were loaded during the previous tile)
+      build_planes<W, NI>(a, pl, stage, tile * kTileRows + 4 * lane, planes, blk, nrows_off, lane, status);
+      wave_lds_fence();
+      mfma_tile<W, NT, NI>(stage, lane, planes, boff_d, boff_g, tcs, q, acc);
+      wave_lds_fence();
+      stage_store<W, NI>(stage, lane, a, r);
+      l1 = n1;
     }
-    if (in.group_mod > 0) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) gv[i] = (uint32_t)((uint64_t)gv[i] % (uint64_t)in.group_mod);
-    }
-    bool bad = false;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const bool inrange = r4 + i < n;
-      if (inrange && !ok[i]) bad = true;
-      ok[i] = ok[i] && (int64_t)gv[i] < G;
-    }
-    if (in.filter_col) {
-      uint32_t fv[4];
-      load4_gcol(in.filter_col, PAC_U32, r4, n, fv);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) ok[i] = ok[i] && fv[i] < in.filter_lt;
-    }
-    if (bad) atomicOr(status, PAC_STATUS_BAD_GROUP);
-    uint32_t gid4 = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) gid4 |= (ok[i] ? gv[i] : 0xFFu) << (8 * i);
-    // group planes (0xFF where the row belongs to group g) and row counts
-    for (int g = 0; g < G; ++g) {
-      const uint32_t x = gid4 ^ ((uint32_t)g * 0x01010101u);
-      const uint32_t nz = (x | ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu)) & 0x80808080u;
-      const uint32_t z = nz ^ 0x80808080u;
-      ((uint32_t *)(planes + (gplane0 + g) * 256))[lane] = z | (z - (z >> 7));
-      unsigned cnt = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) cnt += __popcll(__ballot(ok[i] && gv[i] == (uint32_t)g));
-      if (lane == 0 && cnt) atomicAdd((unsigned long long *)&blk[(int64_t)G * (1 + pl.ni) * m + g], (unsigned long long)cnt);
-    }
-    // digit planes: byte s of (v - lo), offset to int8 by xor 0x80
-    for (int c = 0; c < pl.ni; ++c) {
-      uint64_t v[4];
-      load4_icol(in.icols[c], in.icol_type[c], r4, n, v);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] -= (uint64_t)pl.lo[c];
-      for (int s = 0; s < pl.dig[c]; ++s) {
-        const int sh = s >= 4 ? 32 : 0;
-        const uint32_t word = pack_byte((uint32_t)(v[0] >> sh), (uint32_t)(v[1] >> sh), (uint32_t)(v[2] >> sh),
-                                        (uint32_t)(v[3] >> sh), s & 3);
-        ((uint32_t *)(planes + (pl.doff[c] + s) * 256))[lane] = word ^ 0x80808080u;
-      }
-    }
+  }
+  // ---- the partial last tile, if any, goes to the wave next in the tile order
+  const uint32_t n_tiles = (a.n_rows + kTileRows - 1) / kTileRows;
+  if (n_full < n_tiles && n_full % stride == first) {
+    const uint32_t row0 = n_full * kTileRows;
+    Raw<W, NI> r;
+    Chain c;
+    chain_rows(a, row0, lane, c);
+    for (int k = 0; k < pre; ++k) chain_level(a, k, c);
+    issue_words<W, NI>(a, c, r);
+    issue_cols_tail<W, NI>(a, row0, lane, r);
+    stage_store<W, NI>(stage, lane, a, r);
+    build_planes<W, NI>(a, pl, stage, row0 + 4 * lane, planes, blk, nrows_off, lane, status);
     wave_lds_fence();
-    // ---- four K-chunks of 64 rows
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      v4i a[4 * W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const uint32_t lo = transpose16x2((uint32_t)mk[u][w], lane);
-        const uint32_t hi = transpose16x2((uint32_t)(mk[u][w] >> 32), lane);
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const uint32_t x = h < 2 ? lo : hi;
-          const int sh = (h & 1) * 16;
-          a[4 * w + h] = v4i{expand_nibble(x, sh), expand_nibble(x, sh + 4), expand_nibble(x, sh + 8),
-                             expand_nibble(x, sh + 12)};
-        }
-      }
-      const int roff = 64 * u + 16 * q;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const v4i dgt = *(const v4i *)(planes + boff_d[nt] + roff);
-        const v4i gm = *(const v4i *)(planes + boff_g[nt] + roff);
-        const v4i b = dgt & gm;
-#pragma unroll
-        for (int mt = 0; mt < 4 * W; ++mt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[mt], b, acc[mt][nt], 0, 0, 0);
-      }
-    }
+    mfma_tile<W, NT, NI>(stage, lane, planes, boff_d, boff_g, tcs, q, acc);
     wave_lds_fence();
-    if (++since_flush >= pl.flush_tiles) {
-      flush_acc<W, NT>(acc, planes, blk, pl, lane);
-      since_flush = 0;
-    }
   }
   flush_acc<W, NT>(acc, planes, blk, pl, lane);
   __syncthreads();
   // block counters -> global state
-  const int A = 1 + pl.ni;
+  const int A = 1 + NI;
   for (int i = threadIdx.x; i < pl.blk_words; i += blockDim.x) {
     const int64_t v = blk[i];
     if (!v) continue;
-    if (i >= G * A * m) {
-      atomicAdd((unsigned long long *)&st.nrows[i - G * A * m], (unsigned long long)v);
+    if (i >= nrows_off) {
+      atomicAdd((unsigned long long *)&st.nrows[i - nrows_off], (unsigned long long)v);
       continue;
     }
     const int g = i / (A * m), rem = i - g * A * m, c = rem / m, j = rem - c * m;
-    unsigned long long *dst = c == pl.ni ? (unsigned long long *)&st.count[(int64_t)g * m + j]
-                                         : (unsigned long long *)&st.isum[((int64_t)g * pl.ni + c) * m + j];
+    unsigned long long *dst = c == NI ? (unsigned long long *)&st.count[(int64_t)g * m + j]
+                                      : (unsigned long long *)&st.isum[((int64_t)g * NI + c) * m + j];
     atomicAdd(dst, (unsigned long long)v);
   }
 }
 
 static bool mfma_plan(const DevInput &in, MfmaPlan *pl, int *nt_out) {
   if (in.group_keys || in.n_fcols > 0) return false;
+  if (in.n_icols > kMC || in.n_gcols > kMG || in.n_links > kMC) return false;
+  // 32-bit row and table indices; every table non-empty (invalid lanes read index 0)
+  const int64_t lim = (int64_t)1 << 31;
+  for (int k = 0; k < in.n_links; ++k)
+    if (in.link_len[k] >= lim || in.link_len[k] < 1) return false;
+  const int64_t n_idx = in.masks ? in.n_masks : in.n_pu_keys;
+  if (n_idx >= lim || n_idx < 1) return false;
+  for (int k = 0; k < in.n_gcols; ++k)
+    if (in.gcards[k] >= (1 << 24)) return false;
   int64_t G = 1;
   if (in.n_gcols > 0 || in.group_mod > 0) G = in.n_groups;
   if (G < 1 || G > 254 || in.n_groups != G) return false;
@@ -371,16 +646,19 @@ static bool mfma_plan(const DevInput &in, MfmaPlan *pl, int *nt_out) {
   }
   p.D = D;
   p.ncols = p.G * (D + 1);
-  const int NT = (p.ncols + 15) / 16;
+  int NT = (p.ncols + 15) / 16;  // rounded up to an instantiated tile count
+  if (NT == 5 || NT == 7) ++NT;
+  if (in.W == 2 && NT == 3) NT = 4;
   const int max_nt = in.W == 1 ? kMaxNT : kMaxNT / 2;
   if (NT > max_nt) return false;
-  const int planes_bytes = (D + 2 + p.G) * 256;
+  const int planes_bytes = (D + 2 + p.G) * kPlaneStride;
   const int flush_bytes = 16 * NT * 16 * 4;
-  p.wave_bytes = (std::max(planes_bytes, flush_bytes) + 15) & ~15;
+  p.stage_off = (std::max(planes_bytes, flush_bytes) + 15) & ~15;
+  const int stage_bytes = 64 * (8 * 4 * in.W + 4 * (4 * kMG + 4 + 8 * std::max(p.ni, 1)));  // sizeof(Stage<W, NI>)
+  p.wave_bytes = (p.stage_off + stage_bytes + 15) & ~15;
   p.blk_off = 4 * p.wave_bytes;
   p.blk_words = p.G * (1 + p.ni) * in.m + p.G;
-  // int32 headroom: each row adds at most 128 in magnitude to an accumulator
-  p.flush_tiles = (1 << 24) / kTileRows;
+  p.flush_tiles = (1 << 23) / kTileRows;  // |accumulator| <= 128 * rows < 2^31
   *pl = p;
   *nt_out = NT;
   return p.blk_off + p.blk_words * 8 <= 160 * 1024;
@@ -392,17 +670,85 @@ bool mfma_supported(const DevInput &in) {
   return mfma_plan(in, &p, &nt);
 }
 
-template <int W, int NT>
+// Arguments of the launch covering rows [r0, r0 + n).
+static MfmaArgs mfma_args(const DevInput &in, int64_t r0, int64_t n) {
+  MfmaArgs a{};
+  a.n_rows = (uint32_t)n;
+  a.n_links = in.n_links;
+  for (int k = 0; k < in.n_links; ++k) {
+    a.links[k] = in.links[k];
+    a.link_len[k] = (uint32_t)in.link_len[k];
+  }
+  a.masks = in.masks;
+  a.pu_keys = in.pu_keys;
+  a.n_idx = (uint32_t)(in.masks ? in.n_masks : in.n_pu_keys);
+  if (in.n_links > 0) {  // the first link is indexed by row
+    a.links[0] = in.links[0] + r0;
+    a.link_len[0] = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(in.link_len[0] - r0, n));
+  } else if (in.masks) {  // the mask table is indexed by row
+    a.masks = in.masks + r0 * in.W;
+    a.n_idx = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(in.n_masks - r0, n));
+  } else {
+    a.pu_keys = in.pu_keys + r0;
+    a.n_idx = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(in.n_pu_keys - r0, n));
+  }
+  a.qk = in.query_key;
+  a.balanced = in.balanced;
+  a.n_gcols = in.n_gcols;
+  for (int k = 0; k < in.n_gcols; ++k) {
+    const int bytes = in.gcol_type[k] == PAC_U8 ? 1 : in.gcol_type[k] == PAC_U16 ? 2 : 4;
+    a.gcols[k] = (const uint8_t *)in.gcols[k] + r0 * bytes;
+    a.gcol_bytes[k] = bytes;
+    a.gcards[k] = (uint32_t)in.gcards[k];
+  }
+  a.group_mod = (uint32_t)in.group_mod;
+  a.filter_col = in.filter_col ? in.filter_col + r0 : nullptr;
+  a.filter_lt = in.filter_lt;
+  for (int c = 0; c < in.n_icols; ++c) {
+    const int bytes = in.icol_type[c] == PAC_I32 ? 4 : 8;
+    a.icols[c] = (const uint8_t *)in.icols[c] + r0 * bytes;
+    a.icol_bytes[c] = bytes;
+  }
+  return a;
+}
+
+template <int W, int NT, int NI>
 static hipError_t launch_mfma_t(const LaunchEnv &env, const DevInput &in, const DevState &st, const MfmaPlan &pl) {
+  static_assert(sizeof(Stage<W, NI>) == 64 * (8 * 4 * W + 4 * (4 * kMG + 4 + 8 * (NI > 0 ? NI : 1))), "stage");
   const int lds = pl.blk_off + pl.blk_words * 8;
-  hipError_t e = hipFuncSetAttribute((const void *)agg_mfma<W, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const void *fn = (const void *)agg_mfma<W, NT, NI>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+  if (e != hipSuccess) return e;
+  per_cu = std::max(1, per_cu);
   const int64_t n_tiles = (in.n_rows + kTileRows - 1) / kTileRows;
-  const int per_cu = std::max(1, std::min(4, (160 * 1024) / lds));
   const int64_t want = (n_tiles + 3) / 4;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)env.n_cu * per_cu));
-  hipLaunchKernelGGL((agg_mfma<W, NT>), dim3(blocks), dim3(256), (size_t)lds, env.stream, in, st, env.status, pl);
-  return hipGetLastError();
+  // each wave keeps int32 accumulators and 32-bit row indices: bound the rows of one launch
+  const int64_t rows_per_launch =
+      std::min<int64_t>((int64_t)blocks * 4 * pl.flush_tiles * kTileRows, (int64_t)1 << 30);
+  for (int64_t r0 = 0; r0 < in.n_rows; r0 += rows_per_launch) {
+    const int64_t nr = std::min<int64_t>(in.n_rows - r0, rows_per_launch);
+    hipLaunchKernelGGL((agg_mfma<W, NT, NI>), dim3(blocks), dim3(256), (size_t)lds, env.stream,
+                       mfma_args(in, r0, nr), pl, st, env.status);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int W, int NT>
+static hipError_t launch_mfma_ni(const LaunchEnv &env, const DevInput &in, const DevState &st, const MfmaPlan &pl) {
+  switch (pl.ni) {
+    case 0: return launch_mfma_t<W, NT, 0>(env, in, st, pl);
+    case 1: return launch_mfma_t<W, NT, 1>(env, in, st, pl);
+    case 2: return launch_mfma_t<W, NT, 2>(env, in, st, pl);
+    case 3: return launch_mfma_t<W, NT, 3>(env, in, st, pl);
+    default: return launch_mfma_t<W, NT, 4>(env, in, st, pl);
+  }
 }
 
 hipError_t launch_agg_mfma(const LaunchEnv &env, const DevInput &in, const DevState &st) {
@@ -412,21 +758,18 @@ hipError_t launch_agg_mfma(const LaunchEnv &env, const DevInput &in, const DevSt
   if (!mfma_plan(in, &pl, &nt)) return hipErrorInvalidValue;
   if (in.W == 1) {
     switch (nt) {
-      case 1: return launch_mfma_t<1, 1>(env, in, st, pl);
-      case 2: return launch_mfma_t<1, 2>(env, in, st, pl);
-      case 3: return launch_mfma_t<1, 3>(env, in, st, pl);
-      case 4: return launch_mfma_t<1, 4>(env, in, st, pl);
-      case 5: return launch_mfma_t<1, 5>(env, in, st, pl);
-      case 6: return launch_mfma_t<1, 6>(env, in, st, pl);
-      case 7: return launch_mfma_t<1, 7>(env, in, st, pl);
-      default: return launch_mfma_t<1, 8>(env, in, st, pl);
+      case 1: return launch_mfma_ni<1, 1>(env, in, st, pl);
+      case 2: return launch_mfma_ni<1, 2>(env, in, st, pl);
+      case 3: return launch_mfma_ni<1, 3>(env, in, st, pl);
+      case 4: return launch_mfma_ni<1, 4>(env, in, st, pl);
+      case 6: return launch_mfma_ni<1, 6>(env, in, st, pl);
+      default: return launch_mfma_ni<1, 8>(env, in, st, pl);
     }
   }
   switch (nt) {
-    case 1: return launch_mfma_t<2, 1>(env, in, st, pl);
-    case 2: return launch_mfma_t<2, 2>(env, in, st, pl);
-    case 3: return launch_mfma_t<2, 3>(env, in, st, pl);
-    default: return launch_mfma_t<2, 4>(env, in, st, pl);
+    case 1: return launch_mfma_ni<2, 1>(env, in, st, pl);
+    case 2: return launch_mfma_ni<2, 2>(env, in, st, pl);
+    default: return launch_mfma_ni<2, 4>(env, in, st, pl);
   }
 }
 

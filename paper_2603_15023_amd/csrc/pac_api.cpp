@@ -86,7 +86,8 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
   if (in->masks && in->n_masks < 0) return fail(PAC_ERR_INVALID, "n_masks < 0");
   if (!in->masks && in->pu_keys && in->n_pu_keys < 0) return fail(PAC_ERR_INVALID, "n_pu_keys < 0");
   for (int k = 0; k < in->n_links; ++k)
-    if (!in->links[k] || in->link_len[k] < 0) return fail(PAC_ERR_INVALID, "link %d missing", k);
+    if (in->link_len[k] < 0 || (!in->links[k] && in->link_len[k] > 0))
+      return fail(PAC_ERR_INVALID, "link %d missing", k);
   if (in->n_groups < 1) return fail(PAC_ERR_INVALID, "n_groups must be >= 1");
   if (in->group_keys) {
     if (in->n_gcols > 0 || in->group_mod > 0) return fail(PAC_ERR_INVALID, "sparse keys exclude group columns");
@@ -98,7 +99,7 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
     if (in->group_mod < 0) return fail(PAC_ERR_INVALID, "group_mod < 0");
     double prod = 1.0;
     for (int k = 0; k < in->n_gcols; ++k) {
-      if (!in->gcols[k] || !is_gtype(in->gcol_type[k]) || in->gcards[k] < 1)
+      if ((!in->gcols[k] && in->n_rows > 0) || !is_gtype(in->gcol_type[k]) || in->gcards[k] < 1)
         return fail(PAC_ERR_INVALID, "bad group column %d", k);
       prod *= (double)in->gcards[k];
     }
