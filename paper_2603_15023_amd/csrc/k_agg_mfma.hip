@@ -76,12 +76,18 @@ __device__ __forceinline__ uint32_t dpp_xor8(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);  // row_ror:8 == lane ^ 8 in a row
 }
 
-// One exchange stage of the 16x16 bit transposes held in the two 16-bit
-// halves of x: swap bit B of the lane index with bit B of the bit position.
-// The lower lane of a pair keeps its bits whose position has bit B clear and
-// takes the partner's such bits rotated up by B; the upper lane keeps the
-// others and takes the partner's bits rotated down by B.  Per-lane constants:
-// keep mask and rotation amount of each stage.
+// Bit transpose of the PU words inside each 16-lane group.  Lane i of group
+// q holds the 64 PU bits of row 16q + i; four exchange stages each swap one
+// lane-index bit with one bit-position bit of a 32-bit word:
+//   lane bit 2 <-> position bit 0,  lane bit 3 <-> position bit 1,
+//   lane bit 0 <-> position bit 3,  lane bit 1 <-> position bit 4.
+// Afterwards bit position  k + 4h + 8j  (k, j in 0..3, h in 0..1) of lane i
+// holds row 4k + j of world  world_of(i, h)  (see below) -- i.e. the rows of
+// one world are spread one per byte, so the int8 A operand for rows
+// 4k..4k+3 is just (T >> (k + 4h)) & 0x01010101.
+// In a stage the lower lane of a pair keeps its bits whose position bit is
+// clear and takes the partner's such bits rotated up; the upper lane keeps
+// the others and takes the partner's bits rotated down.
 struct TransposeConsts {
   uint32_t keep[4];
   uint32_t rot[4];
@@ -89,13 +95,14 @@ struct TransposeConsts {
 
 __device__ __forceinline__ TransposeConsts transpose_consts(int lane) {
   TransposeConsts t;
-  const uint32_t lo_masks[4] = {0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+  const int lane_bit[4] = {4, 8, 1, 2};
+  const uint32_t clear_mask[4] = {0x55555555u, 0x33333333u, 0x00FF00FFu, 0x0000FFFFu};
+  const uint32_t shift[4] = {1, 2, 8, 16};
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const int b = 8 >> s;
-    const bool lower = (lane & b) == 0;
-    t.keep[s] = lower ? lo_masks[s] : ~lo_masks[s];
-    t.rot[s] = lower ? 32 - b : b;
+    const bool lower = (lane & lane_bit[s]) == 0;
+    t.keep[s] = lower ? clear_mask[s] : ~clear_mask[s];
+    t.rot[s] = lower ? 32 - shift[s] : shift[s];
   }
   return t;
 }
@@ -106,22 +113,22 @@ __device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t a, uint32_t b) {
   return r;
 }
 
-__device__ __forceinline__ uint32_t transpose16x2(uint32_t x, const TransposeConsts &tc) {
-  uint32_t p = dpp_xor8(x);
+__device__ __forceinline__ uint32_t transpose_word(uint32_t x, const TransposeConsts &tc) {
+  uint32_t p = dpp_xor4(x);
   x = bfi(tc.keep[0], x, __builtin_amdgcn_alignbit(p, p, tc.rot[0]));
-  p = dpp_xor4(x);
+  p = dpp_xor8(x);
   x = bfi(tc.keep[1], x, __builtin_amdgcn_alignbit(p, p, tc.rot[1]));
-  p = dpp_xor2(x);
-  x = bfi(tc.keep[2], x, __builtin_amdgcn_alignbit(p, p, tc.rot[2]));
   p = dpp_xor1(x);
+  x = bfi(tc.keep[2], x, __builtin_amdgcn_alignbit(p, p, tc.rot[2]));
+  p = dpp_xor2(x);
   x = bfi(tc.keep[3], x, __builtin_amdgcn_alignbit(p, p, tc.rot[3]));
   return x;
 }
 
-// 4 bits (positions sh..sh+3 of x) -> 4 bytes of 0/1
-__device__ __forceinline__ int expand_nibble(uint32_t x, int sh) {
-  const uint32_t nib = (x >> sh) & 0xFu;
-  return (int)((__umul24(nib, 0x204081u)) & 0x01010101u);
+// World (0..31 within the 32-bit word) held by lane i of a group at bit-4 value h
+// after transpose_word: lane bits (0,1,2,3) carry world bits (3,4,0,1), h world bit 2.
+__device__ __forceinline__ int world_of(int i, int h) {
+  return ((i >> 2) & 1) | (((i >> 3) & 1) << 1) | (h << 2) | ((i & 1) << 3) | (((i >> 1) & 1) << 4);
 }
 
 // byte b of four 32-bit words, packed into one word (word i -> byte i)
@@ -165,6 +172,17 @@ struct MfmaArgs {
   uint32_t n_rows;          // rows of this launch
 };
 
+// Input shape: SH = 0 reads everything from the arguments; SH = 1 is the
+// star-schema scan (two FK links into a PU-word table, up to two group
+// columns, no filter, no group modulus) with those facts known at compile time.
+template <int SH>
+struct Shape {
+  static __device__ __forceinline__ int n_links(const MfmaArgs &a) { return SH == 1 ? 2 : a.n_links; }
+  static __device__ __forceinline__ bool masks(const MfmaArgs &a) { return SH == 1 ? true : a.masks != nullptr; }
+  static __device__ __forceinline__ bool filter(const MfmaArgs &a) { return SH == 1 ? false : a.filter_col != nullptr; }
+  static __device__ __forceinline__ bool modulo(const MfmaArgs &a) { return SH == 1 ? false : a.group_mod > 0; }
+};
+
 // ---------------------------------------------------------------- FK chain
 // Indices of the four K-chunk rows (64u + lane) of a tile after some chain
 // levels, with their validity.  Every load below is unconditional: invalid
@@ -172,7 +190,7 @@ struct MfmaArgs {
 // staged, so the compiler never has to wait for a load before it is used.
 struct Chain {
   uint32_t idx[4];
-  bool ok[4];
+  uint32_t ok[4];  // 0/1, kept as integers (vector registers) rather than lane masks
 };
 
 __device__ __forceinline__ void chain_rows(const MfmaArgs &a, uint32_t row0, int lane, Chain &c) {
@@ -189,8 +207,9 @@ __device__ __forceinline__ void chain_level(const MfmaArgs &a, int k, Chain &c) 
   const uint32_t len = a.link_len[k];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    c.ok[u] = c.ok[u] && c.idx[u] < len;
-    c.idx[u] = (uint32_t)lk[c.ok[u] ? c.idx[u] : 0u];
+    const bool v = c.ok[u] && c.idx[u] < len;
+    c.ok[u] = v;
+    c.idx[u] = (uint32_t)lk[v ? c.idx[u] : 0u];
   }
 }
 
@@ -199,20 +218,21 @@ __device__ __forceinline__ void chain_level(const MfmaArgs &a, int k, Chain &c) 
 template <int W, int NI>
 struct Raw {
   uint64_t mk[4][W];
-  bool ok[4];
+  uint32_t ok[4];
   uint32_t g[kMG][4];
   uint32_t f[4];
   uint32_t v[NI > 0 ? NI : 1][8];
 };
 
-template <int W, int NI>
+template <int SH, int W, int NI>
 __device__ __forceinline__ void issue_words(const MfmaArgs &a, Chain c, Raw<W, NI> &r) {
-  for (int k = 2; k < a.n_links; ++k) chain_level(a, k, c);
+  for (int k = 2; k < Shape<SH>::n_links(a); ++k) chain_level(a, k, c);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    r.ok[u] = c.ok[u] && c.idx[u] < a.n_idx;
-    const uint32_t si = r.ok[u] ? c.idx[u] : 0u;
-    if (a.masks) {
+    const bool v = c.ok[u] && c.idx[u] < a.n_idx;
+    r.ok[u] = v;
+    const uint32_t si = v ? c.idx[u] : 0u;
+    if (Shape<SH>::masks(a)) {
 #pragma unroll
       for (int w = 0; w < W; ++w) r.mk[u][w] = a.masks[(size_t)si * W + w];
     } else {
@@ -222,7 +242,7 @@ __device__ __forceinline__ void issue_words(const MfmaArgs &a, Chain c, Raw<W, N
 }
 
 // Column words of the full tile starting at row0 (no bounds checks).
-template <int W, int NI>
+template <int SH, int W, int NI>
 __device__ __forceinline__ void issue_cols(const MfmaArgs &a, uint32_t row0, int lane, Raw<W, NI> &r) {
   const uint32_t r4 = row0 + 4 * lane;
 #pragma unroll
@@ -234,7 +254,7 @@ __device__ __forceinline__ void issue_cols(const MfmaArgs &a, uint32_t row0, int
       for (int j = 0; j < 4; ++j) r.g[k][j] = *(const uint32_t *)(base + 4 * min(j, gb - 1));
     }
   }
-  if (a.filter_col) {
+  if (Shape<SH>::filter(a)) {
     const v4u32 w = __builtin_nontemporal_load((const v4u32 *)(a.filter_col + r4));
     r.f[0] = w[0]; r.f[1] = w[1]; r.f[2] = w[2]; r.f[3] = w[3];
   }
@@ -308,11 +328,11 @@ struct Stage {
   uint32_t v[NI > 0 ? NI : 1][8][64];
 };
 
-template <int W, int NI>
+template <int SH, int W, int NI>
 __device__ __forceinline__ void stage_store(Stage<W, NI> *sg, int lane, const MfmaArgs &a, const Raw<W, NI> &r) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    if (a.masks) {
+    if (Shape<SH>::masks(a)) {
 #pragma unroll
       for (int w = 0; w < W; ++w) sg->mk[u][w][lane] = r.ok[u] ? r.mk[u][w] : 0ull;
     } else {
@@ -326,7 +346,7 @@ __device__ __forceinline__ void stage_store(Stage<W, NI> *sg, int lane, const Mf
     if (k < a.n_gcols)
 #pragma unroll
       for (int j = 0; j < 4; ++j) sg->g[k][j][lane] = r.g[k][j];
-  if (a.filter_col)
+  if (Shape<SH>::filter(a))
 #pragma unroll
     for (int j = 0; j < 4; ++j) sg->f[j][lane] = r.f[j];
 #pragma unroll
@@ -337,7 +357,7 @@ __device__ __forceinline__ void stage_store(Stage<W, NI> *sg, int lane, const Mf
 
 // ---------------------------------------------------------------- planes (B side)
 // Group byte planes, row counts and digit planes of the staged tile.
-template <int W, int NI>
+template <int SH, int W, int NI>
 __device__ __forceinline__ void build_planes(const MfmaArgs &a, const MfmaPlan &pl, const Stage<W, NI> *sg,
                                              uint32_t r4, uint8_t *planes, int64_t *blk, int nrows_off, int lane,
                                              uint32_t *status) {
@@ -373,13 +393,13 @@ __device__ __forceinline__ void build_planes(const MfmaArgs &a, const MfmaPlan &
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < 4; ++i) bad = bad || (r4 + i < n && !ok[i]);
-  if (a.group_mod > 0) {
+  if (Shape<SH>::modulo(a)) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) gv[i] = gv[i] % a.group_mod;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) ok[i] = ok[i] && gv[i] < (uint32_t)G;
-  if (a.filter_col) {
+  if (Shape<SH>::filter(a)) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) ok[i] = ok[i] && sg->f[i][lane] < a.filter_lt;
   }
@@ -435,18 +455,17 @@ __device__ __forceinline__ void mfma_tile(const Stage<W, NI> *sg, int lane, cons
                                           const TransposeConsts &tcs, int q, v4i (&acc)[4 * W][NT]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    v4i av[4 * W];
+    v4i av[4 * W];  // M-tile 4w + 2dw + h: word w, 32-bit half dw, bit-4 value h
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       const uint64_t word = sg->mk[u][w][lane];
-      const uint32_t lo = transpose16x2((uint32_t)word, tcs);
-      const uint32_t hi = transpose16x2((uint32_t)(word >> 32), tcs);
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const uint32_t x = h < 2 ? lo : hi;
-        const int sh = (h & 1) * 16;
-        av[4 * w + h] = v4i{expand_nibble(x, sh), expand_nibble(x, sh + 4), expand_nibble(x, sh + 8),
-                            expand_nibble(x, sh + 12)};
+      for (int dw = 0; dw < 2; ++dw) {
+        const uint32_t t = transpose_word((uint32_t)(word >> (32 * dw)), tcs);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          av[4 * w + 2 * dw + h] = v4i{(int)((t >> (4 * h)) & 0x01010101u), (int)((t >> (4 * h + 1)) & 0x01010101u),
+                                      (int)((t >> (4 * h + 2)) & 0x01010101u), (int)((t >> (4 * h + 3)) & 0x01010101u)};
       }
     }
     const int roff = 64 * u + 16 * q;
@@ -473,14 +492,14 @@ __device__ __forceinline__ void flush_acc(v4i (&acc)[4 * W][NT], uint8_t *buf, i
 #pragma unroll
   for (int mt = 0; mt < 4 * W; ++mt) {
     wave_lds_fence();
-    // acc[mt][nt] register r of lane (q,p) = C[world 16mt+4q+r][column 16nt+p]
+    // acc[mt][nt] register r of lane (q,p) = C[M row 4q+r][column 16nt+p]
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) R[(4 * q + r) * ncp + nt * 16 + p] = acc[mt][nt][r];
     wave_lds_fence();
-    const int wl = p;  // world within this M-tile
-    const int world = 16 * mt + wl;
+    const int wl = p;  // M row within this tile
+    const int world = 64 * (mt >> 2) + 32 * ((mt >> 1) & 1) + world_of(wl, mt & 1);
     for (int gc = q; gc < GA; gc += 4) {
       const int g = gc / A, c = gc - g * A;
       const int base = g * (pl.D + 1);
@@ -504,7 +523,7 @@ __device__ __forceinline__ void flush_acc(v4i (&acc)[4 * W][NT], uint8_t *buf, i
   wave_lds_fence();
 }
 
-template <int W, int NT, int NI>
+template <int SH, int W, int NT, int NI>
 __global__ __launch_bounds__(256, (16 * W * NT > 64) ? 1 : 2) void agg_mfma(MfmaArgs a, MfmaPlan pl, DevState st,
                                                                           uint32_t *status) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -549,7 +568,8 @@ __global__ __launch_bounds__(256, (16 * W * NT > 64) ? 1 : 2) void agg_mfma(Mfma
   const uint32_t n_full = a.n_rows / kTileRows;  // full tiles: pipelined, unchecked loads
   const uint32_t stride = gridDim.x * waves;
   const uint32_t first = blockIdx.x * waves + wave;
-  const int pre = a.n_links < 2 ? a.n_links : 2;  // chain levels gathered ahead
+  const int nl = Shape<SH>::n_links(a);
+  const int pre = nl < 2 ? nl : 2;  // chain levels gathered ahead
   if (first < n_full) {
     const uint32_t last = n_full - 1;
     auto clampt = [&](uint32_t t) { return t < n_full ? t : last; };
@@ -559,30 +579,30 @@ __global__ __launch_bounds__(256, (16 * W * NT > 64) ? 1 : 2) void agg_mfma(Mfma
       Chain c;
       chain_rows(a, tile * kTileRows, lane, c);
       for (int k = 0; k < pre; ++k) chain_level(a, k, c);
-      issue_words<W, NI>(a, c, r);
-      issue_cols<W, NI>(a, tile * kTileRows, lane, r);
-      stage_store<W, NI>(stage, lane, a, r);
+      issue_words<SH, W, NI>(a, c, r);
+      issue_cols<SH, W, NI>(a, tile * kTileRows, lane, r);
+      stage_store<SH, W, NI>(stage, lane, a, r);
     }
     Chain l1, l0;  // tile + stride after `pre` links, tile + 2 stride after one link
     chain_rows(a, clampt(tile + stride) * kTileRows, lane, l1);
     for (int k = 0; k < pre; ++k) chain_level(a, k, l1);
     chain_rows(a, clampt(tile + 2 * stride) * kTileRows, lane, l0);
-    if (a.n_links > 0) chain_level(a, 0, l0);
+    if (nl > 0) chain_level(a, 0, l0);
     for (; tile < n_full; tile += stride) {
       // ---- issue the next tile's words and the chain two and three tiles ahead
       Raw<W, NI> r;
-      issue_words<W, NI>(a, l1, r);
-      issue_cols<W, NI>(a, clampt(tile + stride) * kTileRows, lane, r);
+      issue_words<SH, W, NI>(a, l1, r);
+      issue_cols<SH, W, NI>(a, clampt(tile + stride) * kTileRows, lane, r);
       Chain n1 = l0;
-      if (a.n_links > 1) chain_level(a, 1, n1);
+      if (nl > 1) chain_level(a, 1, n1);
       chain_rows(a, clampt(tile + 3 * stride) * kTileRows, lane, l0);
-      if (a.n_links > 0) chain_level(a, 0, l0);
+      if (nl > 0) chain_level(a, 0, l0);
       // ---- tile t from the stage (its words were loaded during the previous tile)
-      build_planes<W, NI>(a, pl, stage, tile * kTileRows + 4 * lane, planes, blk, nrows_off, lane, status);
+      build_planes<SH, W, NI>(a, pl, stage, tile * kTileRows + 4 * lane, planes, blk, nrows_off, lane, status);
       wave_lds_fence();
       mfma_tile<W, NT, NI>(stage, lane, planes, boff_d, boff_g, tcs, q, acc);
       wave_lds_fence();
-      stage_store<W, NI>(stage, lane, a, r);
+      stage_store<SH, W, NI>(stage, lane, a, r);
       l1 = n1;
     }
   }
@@ -594,10 +614,10 @@ __global__ __launch_bounds__(256, (16 * W * NT > 64) ? 1 : 2) void agg_mfma(Mfma
     Chain c;
     chain_rows(a, row0, lane, c);
     for (int k = 0; k < pre; ++k) chain_level(a, k, c);
-    issue_words<W, NI>(a, c, r);
+    issue_words<SH, W, NI>(a, c, r);
     issue_cols_tail<W, NI>(a, row0, lane, r);
-    stage_store<W, NI>(stage, lane, a, r);
-    build_planes<W, NI>(a, pl, stage, row0 + 4 * lane, planes, blk, nrows_off, lane, status);
+    stage_store<SH, W, NI>(stage, lane, a, r);
+    build_planes<SH, W, NI>(a, pl, stage, row0 + 4 * lane, planes, blk, nrows_off, lane, status);
     wave_lds_fence();
     mfma_tile<W, NT, NI>(stage, lane, planes, boff_d, boff_g, tcs, q, acc);
     wave_lds_fence();
@@ -712,12 +732,12 @@ static MfmaArgs mfma_args(const DevInput &in, int64_t r0, int64_t n) {
   return a;
 }
 
-template <int W, int NT, int NI>
+template <int SH, int W, int NT, int NI>
 static hipError_t launch_mfma_t(const LaunchEnv &env, const DevInput &in, const DevState &st, const MfmaPlan &pl) {
   static_assert(sizeof(Stage<W, NI>) == 64 * (8 * 4 * W + 4 * (4 * kMG + 4 + 8 * (NI > 0 ? NI : 1))), "stage");
   const int lds = pl.blk_off + pl.blk_words * 8;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const void *fn = (const void *)agg_mfma<W, NT, NI>;
+  const void *fn = (const void *)agg_mfma<SH, W, NT, NI>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -732,7 +752,7 @@ static hipError_t launch_mfma_t(const LaunchEnv &env, const DevInput &in, const 
       std::min<int64_t>((int64_t)blocks * 4 * pl.flush_tiles * kTileRows, (int64_t)1 << 30);
   for (int64_t r0 = 0; r0 < in.n_rows; r0 += rows_per_launch) {
     const int64_t nr = std::min<int64_t>(in.n_rows - r0, rows_per_launch);
-    hipLaunchKernelGGL((agg_mfma<W, NT, NI>), dim3(blocks), dim3(256), (size_t)lds, env.stream,
+    hipLaunchKernelGGL((agg_mfma<SH, W, NT, NI>), dim3(blocks), dim3(256), (size_t)lds, env.stream,
                        mfma_args(in, r0, nr), pl, st, env.status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -740,14 +760,26 @@ static hipError_t launch_mfma_t(const LaunchEnv &env, const DevInput &in, const 
   return hipSuccess;
 }
 
+// The star shape: two FK links into a PU-word table, group columns only.
+static bool star_shape(const DevInput &in) {
+  return in.n_links == 2 && in.masks && !in.filter_col && in.group_mod == 0;
+}
+
 template <int W, int NT>
 static hipError_t launch_mfma_ni(const LaunchEnv &env, const DevInput &in, const DevState &st, const MfmaPlan &pl) {
+  if (W == 1 && star_shape(in) && pl.ni >= 1 && pl.ni <= 3) {
+    switch (pl.ni) {
+      case 1: return launch_mfma_t<1, W, NT, 1>(env, in, st, pl);
+      case 2: return launch_mfma_t<1, W, NT, 2>(env, in, st, pl);
+      default: return launch_mfma_t<1, W, NT, 3>(env, in, st, pl);
+    }
+  }
   switch (pl.ni) {
-    case 0: return launch_mfma_t<W, NT, 0>(env, in, st, pl);
-    case 1: return launch_mfma_t<W, NT, 1>(env, in, st, pl);
-    case 2: return launch_mfma_t<W, NT, 2>(env, in, st, pl);
-    case 3: return launch_mfma_t<W, NT, 3>(env, in, st, pl);
-    default: return launch_mfma_t<W, NT, 4>(env, in, st, pl);
+    case 0: return launch_mfma_t<0, W, NT, 0>(env, in, st, pl);
+    case 1: return launch_mfma_t<0, W, NT, 1>(env, in, st, pl);
+    case 2: return launch_mfma_t<0, W, NT, 2>(env, in, st, pl);
+    case 3: return launch_mfma_t<0, W, NT, 3>(env, in, st, pl);
+    default: return launch_mfma_t<0, W, NT, 4>(env, in, st, pl);
   }
 }
 
