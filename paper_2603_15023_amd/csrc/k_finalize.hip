@@ -1,10 +1,14 @@
 // a7: release of the result cells (Sec. 4.1 noise function pac_noised,
 // Sec. 3.2 NULLs, Sec. 5 Diversity Check, Sec. 2 adaptive composition).
 //
-// The posterior P over the m worlds is updated after every released cell, so
-// the chain is sequential by definition: one wavefront walks the cells in
-// order with lane j owning worlds j and j+64.  Each cell costs a handful of
-// fp64 wave reductions (mean, variance, max, normaliser) and is latency bound.
+// The posterior P over the m worlds changes after every released cell, so
+// the chain over cells is sequential by definition.  Everything that does not
+// depend on P runs first, in parallel, one wavefront per cell (phase 1): the
+// world vector y of the cell (COUNT / SUM / AVG of the per-world counters,
+// doubled for COUNT/SUM), the number of worlds that received a row, the
+// diversity flag and the cell's random draws.  Phase 2 is one wavefront that
+// streams those vectors in cell order (several cells in flight) and applies
+// the noise rule and the Bayesian update with DPP wave reductions.
 //
 // Randomness is counter based (Philox4x32-10 keyed by the query's noise
 // seed, counter = (cell, purpose)), so every draw depends only on the seed
@@ -39,27 +43,132 @@ __device__ __forceinline__ void draw2(uint64_t seed, int64_t index, uint32_t pur
 
 __device__ __forceinline__ double to_unit(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
 
-__device__ __forceinline__ double wave_sum(double v) {
+// Per-cell record written by phase 1 (besides the world vector).
+struct CellMeta {
+  double z;        // standard normal draw (Box-Muller)
+  uint32_t flags;  // PAC_CELL_* decided in phase 1 (NULL, DIVERSITY)
+  uint32_t bad;    // cell out of range: released as NULL, no update
+};
+
+constexpr int kCellChunk = 65536;
+
+template <int W>
+__global__ __launch_bounds__(256) void cell_vectors_kernel(DevState st, const pac_cell *__restrict__ cells,
+                                                           FinParams fp, int64_t c0, int64_t nc, double *ybuf,
+                                                           CellMeta *meta, double *out_y, uint32_t *status) {
+  constexpr int m = 64 * W;
+  const int lane = threadIdx.x & 63;
+  const int64_t ci = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (ci >= nc) return;
+  const int64_t c = c0 + ci;
+  const pac_cell cell = cells[c];
+  const int64_t g = cell.group;
+  const int ncol = (cell.kind == PAC_CELL_SUM_I || cell.kind == PAC_CELL_AVG_I) ? fp.n_int
+                   : (cell.kind == PAC_CELL_SUM_F || cell.kind == PAC_CELL_AVG_F) ? fp.n_float : 1;
+  if (g < 0 || g >= fp.n_groups || cell.kind < 0 || cell.kind > PAC_CELL_AVG_F ||
+      (cell.kind != PAC_CELL_COUNT && (cell.col < 0 || cell.col >= ncol))) {
+    if (lane == 0) {
+      atomicOr(status, PAC_STATUS_BAD_GROUP);
+      meta[ci] = CellMeta{0.0, PAC_CELL_NULL, 1u};
+    }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+    for (int w = 0; w < W; ++w) ybuf[ci * m + lane + 64 * w] = 0.0;
+    return;
+  }
+  int pop = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int j = lane + 64 * w;
+    const int64_t cnt = st.count[g * m + j];
+    pop += __popcll(__ballot(cnt > 0));
+    double v;
+    switch (cell.kind) {
+      case PAC_CELL_COUNT: v = (double)cnt; break;
+      case PAC_CELL_SUM_I:
+      case PAC_CELL_AVG_I: v = (double)st.isum[(g * fp.n_int + cell.col) * m + j]; break;
+      default: v = st.fsum[(g * fp.n_float + cell.col) * m + j]; break;
+    }
+    if (cell.kind == PAC_CELL_AVG_I || cell.kind == PAC_CELL_AVG_F) {
+      if (fp.flags & PAC_FIN_AVG_TOTALCOUNT) {
+        const double nr = (double)st.nrows[g];
+        v = nr > 0.0 ? (2.0 * v) / nr : 0.0;
+      } else {
+        v = cnt > 0 ? v / (double)cnt : 0.0;
+      }
+    } else if (fp.flags & PAC_FIN_SCALE2) {
+      v = 2.0 * v;
+    }
+    ybuf[ci * m + j] = v;
+    if (out_y) out_y[c * m + j] = v;
+  }
+  if (lane == 0) {
+    uint32_t flags = 0;
+    if (st.nrows[g] >= 16 && pop <= (m == 64 ? 40 : 80)) {
+      flags |= PAC_CELL_DIVERSITY;
+      if (fp.flags & PAC_FIN_STRICT_DIVERSITY) atomicOr(status, PAC_STATUS_DIVERSITY);
+    }
+    uint64_t a, b;
+    draw2(fp.seed, c, kDrawNull, &a, &b);
+    const double p_null = (double)(m - pop) / (double)m;
+    if (to_unit(a) < p_null) flags |= PAC_CELL_NULL;
+    draw2(fp.seed, c, kDrawNoise, &a, &b);
+    const double u1 = to_unit(a), u2 = to_unit(b);
+    const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
+    meta[ci] = CellMeta{z, flags, 0u};
+  }
+}
+
+// ---------------------------------------------------------------- wave reductions (fp64, DPP)
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int rlo, rhi;
+  switch (ctrl_sel) {
+    case 0: rlo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false); rhi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;  // xor 1
+    case 1: rlo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false); rhi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;  // xor 2
+    case 2: rlo = __builtin_amdgcn_mov_dpp(lo, 0x124, 0xF, 0xF, false); rhi = __builtin_amdgcn_mov_dpp(hi, 0x124, 0xF, 0xF, false); break;  // row_ror 4
+    default: rlo = __builtin_amdgcn_mov_dpp(lo, 0x128, 0xF, 0xF, false); rhi = __builtin_amdgcn_mov_dpp(hi, 0x128, 0xF, 0xF, false); break;  // row_ror 8
+  }
+  return __hiloint2double(rhi, rlo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same value returned to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64(v, 0);
+  v += dpp_f64(v, 1);
+  v += dpp_f64(v, 2);
+  v += dpp_f64(v, 3);  // every lane: sum of its row of 16
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
+  v = fmax(v, dpp_f64(v, 0));
+  v = fmax(v, dpp_f64(v, 1));
+  v = fmax(v, dpp_f64(v, 2));
+  v = fmax(v, dpp_f64(v, 3));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
+constexpr int kAhead = 4;  // cells in flight in the sequential phase
+
 template <int W>
-__global__ __launch_bounds__(64) void finalize_kernel(DevState st, const pac_cell *__restrict__ cells, FinParams fp,
-                                                      double *out_val, uint8_t *out_null, uint32_t *out_flags,
-                                                      double *post, double *out_y, uint32_t *status) {
+__global__ __launch_bounds__(64) void release_chain_kernel(FinParams fp, int64_t c0, int64_t nc, const double *ybuf,
+                                                           const CellMeta *meta, double *out_val, uint8_t *out_null,
+                                                           uint32_t *out_flags, double *post, int first_chunk) {
   constexpr int m = 64 * W;
   const int lane = threadIdx.x;
-  double P[W];
+  double P[W], L[W];
+  const bool prior = (fp.flags & PAC_FIN_PRIOR_IN) || !first_chunk;
 #pragma unroll
-  for (int w = 0; w < W; ++w) P[w] = (fp.flags & PAC_FIN_PRIOR_IN) ? post[lane + 64 * w] : 1.0 / m;
+  for (int w = 0; w < W; ++w) {
+    P[w] = prior ? post[lane + 64 * w] : 1.0 / m;
+    L[w] = log(P[w]);
+  }
   int jstar = fp.j_star;
   if (jstar < 0) {
     uint64_t a, b;
@@ -67,127 +176,145 @@ __global__ __launch_bounds__(64) void finalize_kernel(DevState st, const pac_cel
     jstar = (int)(a % (uint64_t)m);
   }
   const int js_w = jstar >> 6, js_l = jstar & 63;
-  const int div_max = m == 64 ? 40 : 80;
-  for (int64_t c = 0; c < fp.n_cells; ++c) {
-    const pac_cell cell = cells[c];
-    const int64_t g = cell.group;
-    const int ncol = (cell.kind == PAC_CELL_SUM_I || cell.kind == PAC_CELL_AVG_I) ? fp.n_int
-                     : (cell.kind == PAC_CELL_SUM_F || cell.kind == PAC_CELL_AVG_F) ? fp.n_float : 1;
-    if (g < 0 || g >= fp.n_groups || cell.kind < 0 || cell.kind > PAC_CELL_AVG_F ||
-        (cell.kind != PAC_CELL_COUNT && (cell.col < 0 || cell.col >= ncol))) {
-      if (lane == 0) {
-        atomicOr(status, PAC_STATUS_BAD_GROUP);
-        out_val[c] = 0.0;
-        out_null[c] = 1;
-        out_flags[c] = PAC_CELL_NULL;
-      }
-      continue;
-    }
-    double y[W];
-    int pop = 0;
+  // ring of prefetched world vectors: cell ci sits in slot ci % kAhead
+  double yq[kAhead][W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int j = lane + 64 * w;
-      const int64_t cnt = st.count[g * m + j];
-      pop += __popcll(__ballot(cnt > 0));
-      double v;
-      switch (cell.kind) {
-        case PAC_CELL_COUNT: v = (double)cnt; break;
-        case PAC_CELL_SUM_I:
-        case PAC_CELL_AVG_I: v = (double)st.isum[(g * fp.n_int + cell.col) * m + j]; break;
-        default: v = st.fsum[(g * fp.n_float + cell.col) * m + j]; break;
-      }
-      if (cell.kind == PAC_CELL_AVG_I || cell.kind == PAC_CELL_AVG_F) {
-        if (fp.flags & PAC_FIN_AVG_TOTALCOUNT) {
-          const double nr = (double)st.nrows[g];
-          v = nr > 0.0 ? (2.0 * v) / nr : 0.0;
-        } else {
-          v = cnt > 0 ? v / (double)cnt : 0.0;
+  for (int k = 0; k < kAhead; ++k)
+#pragma unroll
+    for (int w = 0; w < W; ++w) yq[k][w] = k < nc ? ybuf[(int64_t)k * m + lane + 64 * w] : 0.0;
+  // lane l holds z and the phase-1 flags of cell b + l of the current batch of 64
+  double zc = 0.0;
+  uint32_t fc = 0;
+  if (lane < nc) {
+    zc = meta[lane].z;
+    fc = meta[lane].flags;
+  }
+  for (int64_t b = 0; b < nc; b += 64) {
+    double zn = 0.0;
+    uint32_t fn = 0;
+    if (b + 64 + lane < nc) {  // next batch, in flight while this one is released
+      zn = meta[b + 64 + lane].z;
+      fn = meta[b + 64 + lane].flags;
+    }
+    const int nb = nc - b < 64 ? (int)(nc - b) : 64;
+    for (int k = 0; k < nb; k += kAhead) {
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int kk = k + u;
+        if (kk >= nb) break;
+        const int64_t ci = b + kk;
+        double y[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) y[w] = yq[u][w];
+        const int64_t nx = ci + kAhead;
+#pragma unroll
+        for (int w = 0; w < W; ++w) yq[u][w] = nx < nc ? ybuf[nx * m + lane + 64 * w] : 0.0;
+        const uint32_t cflags = (uint32_t)__builtin_amdgcn_readlane((int)fc, kk);
+        const int64_t c = c0 + ci;
+        if (cflags & PAC_CELL_NULL) {
+          if (lane == 0) {
+            out_val[c] = 0.0;
+            out_null[c] = 1;
+            out_flags[c] = cflags;
+          }
+          continue;
         }
-      } else if (fp.flags & PAC_FIN_SCALE2) {
-        v = 2.0 * v;
-      }
-      y[w] = v;
-      if (out_y) out_y[c * m + j] = v;
-    }
-    uint32_t flags = 0;
-    if (st.nrows[g] >= 16 && pop <= div_max) {
-      flags |= PAC_CELL_DIVERSITY;
-      if ((fp.flags & PAC_FIN_STRICT_DIVERSITY) && lane == 0) atomicOr(status, PAC_STATUS_DIVERSITY);
-    }
-    uint64_t a, b;
-    draw2(fp.seed, c, kDrawNull, &a, &b);
-    const double p_null = (double)(m - pop) / (double)m;
-    if (to_unit(a) < p_null) {
-      if (lane == 0) {
-        out_val[c] = 0.0;
-        out_null[c] = 1;
-        out_flags[c] = flags | PAC_CELL_NULL;
-      }
-      continue;
-    }
-    double part = 0.0;
+        double part = 0.0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) part += P[w] * y[w];
-    const double mu = wave_sum(part);
-    part = 0.0;
+        for (int w = 0; w < W; ++w) part += P[w] * y[w];
+        const double mu = wave_sum(part);
+        part = 0.0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) part += P[w] * ((y[w] - mu) * (y[w] - mu));
-    const double s2 = wave_sum(part);
-    const double delta = s2 / (2.0 * fp.budget);
-    const double ys = __shfl(y[js_w], js_l, 64);
-    if (!(delta > 0.0)) {
-      if (lane == 0) {
-        out_val[c] = ys;
-        out_null[c] = 0;
-        out_flags[c] = flags | PAC_CELL_ZERO_VARIANCE;
+        for (int w = 0; w < W; ++w) part += P[w] * ((y[w] - mu) * (y[w] - mu));
+        const double s2 = wave_sum(part);
+        const double delta = s2 / (2.0 * fp.budget);
+        const double ys = readlane_f64(y[js_w], js_l);
+        if (!(delta > 0.0)) {
+          if (lane == 0) {
+            out_val[c] = ys;
+            out_null[c] = 0;
+            out_flags[c] = cflags | PAC_CELL_ZERO_VARIANCE;
+          }
+          continue;
+        }
+        const double yrel = ys + sqrt(delta) * readlane_f64(zc, kk);
+        if (lane == 0) {
+          out_val[c] = yrel;
+          out_null[c] = 0;
+          out_flags[c] = cflags;
+        }
+        if (!(fp.flags & PAC_FIN_FIXED_PRIOR)) {
+          double l[W];
+          double mx = -INFINITY;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            const double d = yrel - y[w];
+            l[w] = L[w] - (d * d) / (2.0 * delta);
+            mx = fmax(mx, l[w]);
+          }
+          mx = wave_max(mx);
+          double e[W], se = 0.0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            e[w] = exp(l[w] - mx);
+            se += e[w];
+          }
+          se = wave_sum(se);
+          const double lse = mx + log(se);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            P[w] = e[w] / se;
+            L[w] = P[w] > 0.0 ? l[w] - lse : -INFINITY;  // an underflowed world stays at zero
+          }
+        }
       }
-      continue;
     }
-    draw2(fp.seed, c, kDrawNoise, &a, &b);
-    const double u1 = to_unit(a), u2 = to_unit(b);
-    const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
-    const double yrel = ys + sqrt(delta) * z;
-    if (lane == 0) {
-      out_val[c] = yrel;
-      out_null[c] = 0;
-      out_flags[c] = flags;
-    }
-    if (!(fp.flags & PAC_FIN_FIXED_PRIOR)) {
-      double l[W];
-      double mx = -INFINITY;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const double d = yrel - y[w];
-        l[w] = log(P[w]) - (d * d) / (2.0 * delta);
-        mx = fmax(mx, l[w]);
-      }
-      mx = wave_max(mx);
-      double e[W], se = 0.0;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        e[w] = exp(l[w] - mx);
-        se += e[w];
-      }
-      se = wave_sum(se);
-#pragma unroll
-      for (int w = 0; w < W; ++w) P[w] = e[w] / se;
-    }
+    zc = zn;
+    fc = fn;
   }
 #pragma unroll
   for (int w = 0; w < W; ++w) post[lane + 64 * w] = P[w];
 }
 
+size_t finalize_scratch_bytes(int m, int64_t n_cells) {
+  const int64_t chunk = n_cells < kCellChunk ? n_cells : kCellChunk;
+  return (size_t)chunk * (m * sizeof(double) + sizeof(CellMeta)) + 256;
+}
+
 hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_cell *cells, const FinParams &fp,
                            double *out_val, uint8_t *out_is_null, uint32_t *out_flags, double *posterior,
-                           double *out_y) {
-  if (fp.m == 64)
-    hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(64), 0, env.stream, st, cells, fp, out_val, out_is_null,
-                       out_flags, posterior, out_y, env.status);
-  else
-    hipLaunchKernelGGL(finalize_kernel<2>, dim3(1), dim3(64), 0, env.stream, st, cells, fp, out_val, out_is_null,
-                       out_flags, posterior, out_y, env.status);
-  return hipGetLastError();
+                           double *out_y, void *scratch) {
+  const int m = fp.m;
+  const int64_t chunk = fp.n_cells < kCellChunk ? fp.n_cells : kCellChunk;
+  double *ybuf = (double *)scratch;
+  CellMeta *meta = (CellMeta *)(((uintptr_t)(ybuf + chunk * m) + 255) & ~(uintptr_t)255);
+  if (fp.n_cells == 0) {  // posterior out = prior (or uniform)
+    hipLaunchKernelGGL(fp.m == 64 ? release_chain_kernel<1> : release_chain_kernel<2>, dim3(1), dim3(64), 0,
+                       env.stream, fp, (int64_t)0, (int64_t)0, ybuf, meta, out_val, out_is_null, out_flags, posterior,
+                       1);
+    return hipGetLastError();
+  }
+  for (int64_t c0 = 0; c0 < fp.n_cells; c0 += chunk) {
+    const int64_t nc = fp.n_cells - c0 < chunk ? fp.n_cells - c0 : chunk;
+    const int blocks = (int)((nc + 3) / 4);
+    if (m == 64)
+      hipLaunchKernelGGL(cell_vectors_kernel<1>, dim3(blocks), dim3(256), 0, env.stream, st, cells, fp, c0, nc, ybuf,
+                         meta, out_y, env.status);
+    else
+      hipLaunchKernelGGL(cell_vectors_kernel<2>, dim3(blocks), dim3(256), 0, env.stream, st, cells, fp, c0, nc, ybuf,
+                         meta, out_y, env.status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (m == 64)
+      hipLaunchKernelGGL(release_chain_kernel<1>, dim3(1), dim3(64), 0, env.stream, fp, c0, nc, ybuf, meta, out_val,
+                         out_is_null, out_flags, posterior, c0 == 0 ? 1 : 0);
+    else
+      hipLaunchKernelGGL(release_chain_kernel<2>, dim3(1), dim3(64), 0, env.stream, fp, c0, nc, ybuf, meta, out_val,
+                         out_is_null, out_flags, posterior, c0 == 0 ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace pac

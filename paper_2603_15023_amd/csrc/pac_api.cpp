@@ -369,7 +369,10 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
   pac::DevState ds{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used};
   pac::FinParams fp{params->mi_budget, params->noise_seed, params->j_star, params->flags, m, n_int, n_float, n_cells, n_groups};
   pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
-  hipError_t e = pac::launch_finalize(env, ds, cells, fp, out_val, out_is_null, out_flags, posterior, out_y);
+  const int rc = ensure_scratch(ctx, pac::finalize_scratch_bytes(m, n_cells));
+  if (rc != PAC_OK) return rc;
+  hipError_t e =
+      pac::launch_finalize(env, ds, cells, fp, out_val, out_is_null, out_flags, posterior, out_y, ctx->scratch);
   if (e != hipSuccess) return hip_fail(e, "finalize launch");
   return PAC_OK;
 }

@@ -214,6 +214,7 @@ struct FinParams {
 };
 hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_cell *cells, const FinParams &fp,
                            double *out_val, uint8_t *out_is_null, uint32_t *out_flags, double *posterior,
-                           double *out_y);
+                           double *out_y, void *scratch);
+size_t finalize_scratch_bytes(int m, int64_t n_cells);
 
 }  // namespace pac

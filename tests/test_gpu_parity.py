@@ -266,3 +266,86 @@ def test_finalize_matches_oracle(ctx, torch_mod, m):
     assert np.array_equal(flags.cpu().numpy().astype(np.uint32), wf)
     np.testing.assert_allclose(vals.cpu().numpy(), wv, rtol=1e-12, atol=0)
     np.testing.assert_allclose(post.cpu().numpy(), wP, rtol=1e-9, atol=1e-300)
+
+
+def _release_case(ctx, torch_mod, m, cells, B, seed, flags, j_star=-1, prior=None):
+    import paper_2603_15023_amd as P
+    t = gen.tiny_star(33, n_pu=60, n_orders=600, n_rows=9000, gcards=(3, 2), n_cols=1, value_range=(1, 10**5))
+    t.cols["f0"] = np.random.default_rng(3).lognormal(0, 1, size=t.n_rows)
+    got = gpu_star(ctx, t, 77, m, int_cols=["v0"], float_cols=["f0"], algo="plain")
+    counters = {k: got[k] for k in ("count", "isum", "fsum", "nrows")}
+    dev = torch_mod.device("cuda")
+    state = {k: torch_mod.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in counters.items()}
+    pr = None if prior is None else torch_mod.from_numpy(prior).to(dev)
+    vals, nulls, cflags, post, _ = P.pac_finalize(ctx, state, P.cells_tensor(cells), len(cells), m=m, mi_budget=B,
+                                                  noise_seed=seed, j_star=j_star, flags=flags, prior=pr)
+    return counters, (vals.cpu().numpy(), nulls.cpu().numpy(), cflags.cpu().numpy().astype(np.uint32),
+                      post.cpu().numpy())
+
+
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("flags", [R.FLAG_SCALE2, R.FLAG_SCALE2 | R.FLAG_AVG_TOTALCOUNT, R.FLAG_FIXED_PRIOR, 0])
+def test_finalize_flags_prior_jstar(ctx, torch_mod, m, flags):
+    """Every finalize flag, a given j*, and a non-uniform prior carried in."""
+    cells = [(g, k, 0) for g in range(6) for k in (R.KIND_COUNT, R.KIND_SUM_I, R.KIND_SUM_F, R.KIND_AVG_I,
+                                                   R.KIND_AVG_F)] * 3
+    prior = np.random.default_rng(m + flags).dirichlet(np.ones(m))
+    counters, (v, n, f, post) = _release_case(ctx, torch_mod, m, cells, 1.0 / 64, 0xABCDEF + flags, flags,
+                                                 j_star=m // 3, prior=prior)
+    wv, wn, wf, wP, _ = R.release(counters, cells, m, 1.0 / 64, 0xABCDEF + flags, j_star=m // 3, flags=flags,
+                                  prior=prior)
+    assert np.array_equal(n, wn) and np.array_equal(f, wf)
+    np.testing.assert_allclose(v, wv, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(post, wP, rtol=1e-9, atol=1e-300)
+
+
+def test_finalize_long_chain_crosses_chunks(ctx, torch_mod):
+    """More cells than one launch chunk (65536): the posterior is carried across launches.
+
+    The budget is small so that the posterior stays spread out over the whole
+    chain (checked below) and every cell exercises the update.  A released
+    value is y[j*] + sqrt(Delta) z; the comparison bound is relative to the
+    magnitudes of those two terms, since their sum can cancel.
+    """
+    rng = np.random.default_rng(44)
+    n_cells = 65536 + 777
+    kinds = rng.choice([R.KIND_COUNT, R.KIND_SUM_I, R.KIND_AVG_F], size=n_cells)
+    groups = rng.integers(0, 6, size=n_cells)
+    cells = [(int(g), int(k), 0) for g, k in zip(groups, kinds)]
+    counters, (v, n, f, post) = _release_case(ctx, torch_mod, 64, cells, 1e-6, 99, R.FLAG_SCALE2)
+    wv, wn, wf, wP, wy = R.release(counters, cells, 64, 1e-6, 99)
+    assert wP.min() > 1e-3  # the posterior never concentrated: no world underflows along the chain
+    assert np.array_equal(n, wn) and np.array_equal(f, wf)
+    y_js = wy[:, R.secret_world(99, 64)]
+    bound = 1e-12 * (np.abs(y_js) + np.abs(wv - y_js))
+    assert np.all(np.abs(v - wv) <= bound)
+    np.testing.assert_allclose(post, wP, rtol=1e-9, atol=1e-300)
+
+
+def test_finalize_invalid_cells_are_null(ctx, torch_mod):
+    """Cells naming a missing group, kind or column release NULL and leave the posterior alone."""
+    import paper_2603_15023_amd as P
+    good = [(g, R.KIND_SUM_I, 0) for g in range(6)]
+    bad = [(6, R.KIND_COUNT, 0), (-1, R.KIND_COUNT, 0), (0, 9, 0), (1, R.KIND_SUM_I, 1), (2, R.KIND_AVG_F, -1)]
+    cells = good[:3] + bad + good[3:]
+    counters, (v, n, f, post) = _release_case(ctx, torch_mod, 64, cells, 1.0 / 128, 5, R.FLAG_SCALE2)
+    assert ctx.status() & P._abi.PAC_STATUS_BAD_GROUP  # reading clears the bits
+    # oracle view: an invalid cell is a cell whose worlds were never updated (always NULL)
+    ys = [R.cell_vector(counters, g, k, c, R.FLAG_SCALE2) for (g, k, c) in good]
+    ys = ys[:3] + [np.zeros(64)] * len(bad) + ys[3:]
+    pops = [int(np.count_nonzero(counters["count"][g])) for (g, _, _) in good]
+    pops = pops[:3] + [0] * len(bad) + pops[3:]
+    ns = [int(counters["nrows"][g]) for (g, _, _) in good]
+    ns = ns[:3] + [0] * len(bad) + ns[3:]
+    wv, wn, wf, wP = R.pac_noised_sequence(ys, pops, ns, 64, 1.0 / 128, 5)
+    assert np.array_equal(n, wn) and np.array_equal(f, wf)
+    np.testing.assert_allclose(v, wv, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(post, wP, rtol=1e-9, atol=1e-300)
+
+
+@pytest.mark.parametrize("with_prior", [False, True])
+def test_finalize_no_cells_returns_prior(ctx, torch_mod, with_prior):
+    prior = np.random.default_rng(8).dirichlet(np.ones(64)) if with_prior else None
+    _, (v, n, f, post) = _release_case(ctx, torch_mod, 64, [], 1.0 / 128, 5, R.FLAG_SCALE2, prior=prior)
+    assert v.shape == (0,)
+    np.testing.assert_array_equal(post, prior if with_prior else np.full(64, 1.0 / 64))
