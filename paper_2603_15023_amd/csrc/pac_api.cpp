@@ -237,7 +237,7 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
       if (!pac::mfma_supported(d))
         return fail(PAC_ERR_UNSUPPORTED, "int8 matrix-core form needs int columns, <= 254 dense groups and "
                                          "groups x (digits+1) within the tile");
-      e = pac::launch_agg_mfma(env, d, ds);
+      e = pac::star_supported(d) ? pac::launch_agg_star(env, d, ds) : pac::launch_agg_mfma(env, d, ds);
       break;
     default:
       return fail(PAC_ERR_INVALID, "unknown algorithm %u", algo);

@@ -202,6 +202,8 @@ hipError_t launch_agg_ballot(const LaunchEnv &env, const DevInput &in, const Dev
 bool ballot_supported(const DevInput &in);
 hipError_t launch_agg_mfma(const LaunchEnv &env, const DevInput &in, const DevState &st);
 bool mfma_supported(const DevInput &in);
+hipError_t launch_agg_star(const LaunchEnv &env, const DevInput &in, const DevState &st);
+bool star_supported(const DevInput &in);
 
 struct FinParams {
   double budget;

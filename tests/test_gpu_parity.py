@@ -151,6 +151,55 @@ def test_bad_group_value_sets_status(ctx):
         assert got["nrows"].sum() == keep.sum()
 
 
+STAR_SHAPES = [((3, 2), 3), ((2, 4), 1), ((1, 8), 2), ((8, 1), 3), ((1, 1), 1), ((2, 3), 2)]
+
+
+@pytest.mark.parametrize("gcards,n_cols", STAR_SHAPES)
+def test_star_kernel_shapes(ctx, gcards, n_cols):
+    """Shapes of the specialised star-schema matrix-core kernel: two u8 group columns,
+    at most 8 groups, 1-3 int64 columns whose range spans 3 byte digits, signed
+    values, 37 full tiles and a ragged 101-row tail."""
+    n_rows = 256 * 37 + 101
+    t = gen.tiny_star(40 + n_cols, n_pu=500, n_orders=3000, n_rows=n_rows, gcards=gcards, n_cols=n_cols,
+                      value_range=(-5_000_000, 5_000_000))
+    ints = [f"v{i}" for i in range(n_cols)]
+    _say("star kernel", gcards, n_cols)
+    got = gpu_star(ctx, t, 0x5151, 64, int_cols=ints, algo="mfma")
+    assert got["status"] == 0
+    compare_counters(got, star_definition(t, 0x5151, 64, int_cols=ints))
+
+
+def test_star_kernel_skips_bad_group_rows(ctx):
+    import dataclasses
+    t = gen.tiny_star(47, n_pu=300, n_orders=2000, n_rows=256 * 20 + 7, gcards=(3, 2), n_cols=3,
+                      value_range=(0, 9_999_999))
+    bad = np.array([3, 100, 511, 5000, t.n_rows - 1])
+    t.gcols[0][bad[:3]] = [3, 200, 255]
+    t.gcols[1][bad[3:]] = [2, 129]
+    ints = ["v0", "v1", "v2"]
+    got = gpu_star(ctx, t, 9, 64, int_cols=ints, algo="mfma")
+    assert got["status"] & 1
+    keep = np.ones(t.n_rows, dtype=bool)
+    keep[bad] = False
+    t2 = dataclasses.replace(t, f_order=t.f_order[keep], gcols=[g[keep] for g in t.gcols],
+                             cols={k: v[keep] for k, v in t.cols.items()})
+    compare_counters(got, star_definition(t2, 9, 64, int_cols=ints))
+
+
+@pytest.mark.parametrize("which", ["fact", "order"])
+def test_star_kernel_flags_bad_links(ctx, which):
+    t = gen.tiny_star(48, n_pu=200, n_orders=1500, n_rows=256 * 12 + 30, gcards=(3, 2), n_cols=1,
+                      value_range=(0, 9_999_999))
+    if which == "fact":
+        t.f_order = t.f_order.copy()
+        t.f_order[[17, t.n_rows - 3]] = 1_000_000
+    else:
+        t.o_pu = t.o_pu.copy()
+        t.o_pu[t.f_order[100]] = 10_000
+    got = gpu_star(ctx, t, 3, 64, int_cols=["v0"], algo="mfma")
+    assert got["status"] & 2
+
+
 def test_bad_link_sets_status(ctx):
     t = gen.tiny_star(29, n_pu=10, n_orders=20, n_rows=300, gcards=(2,), n_cols=1)
     t.f_order = t.f_order.copy()
