@@ -33,8 +33,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # Measured HBM traffic of the aggregation kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # calibrated against a copy kernel of known size); valid only for the kernel
 # sources whose hash it records.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "agg_mfma_star60M_traffic.md")
-KERNEL_SOURCES = ["paper_2603_15023_amd/csrc/k_agg_mfma.hip", "paper_2603_15023_amd/csrc/pac_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "agg_star_star60M_traffic.md")
+KERNEL_SOURCES = ["paper_2603_15023_amd/csrc/k_agg_star.hip", "paper_2603_15023_amd/csrc/mfma_common.h",
+                  "paper_2603_15023_amd/csrc/pac_internal.h"]
 
 
 def log(*a):
@@ -46,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto"])
+    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv"])
     ap.add_argument("--compare-steps", type=int, default=5, help="steps timed for the other GPU forms")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -107,6 +108,10 @@ def main():
     masks = torch.empty((n_pu, 1), dtype=torch.int64, device=dev)
     spec = P.AggSpec(n_rows=n, masks=masks, links=links, gcols=gcols, gcards=t.gcards, n_groups=6, cols=cols,
                      stats=stats)
+    # the same query with the orders carrying their PU key (one FK link, the key hashed in the kernel)
+    spec_kv = P.AggSpec(n_rows=n, links=[links[0]], gcols=gcols, gcards=t.gcards, n_groups=6, cols=cols,
+                        stats=stats)
+    spec_kv.pu_keys = torch.from_numpy(t.pu_key[t.o_pu]).to(dev)
     state = P.new_state(spec, 64)
     cells = []
     for g in range(6):
@@ -120,12 +125,15 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(algo, ev=None):
-        P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+        kv = algo == "mfma_kv"
+        if not kv:
+            P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
         for v in state.values():  # counters start at zero (fill kernels, outside the event bracket)
             v.zero_()
         if ev is not None:
             ev[0].record(stream)
-        P.pac_group_aggregate(ctx, spec, state, m=64, query_key=K, algo=algo, init=False)
+        P.pac_group_aggregate(ctx, spec_kv if kv else spec, state, m=64, query_key=K, algo="mfma" if kv else algo,
+                              init=False)
         if ev is not None:
             ev[1].record(stream)
         return P.pac_finalize(ctx, state, cells_t, len(cells), m=64, mi_budget=1.0 / 128, noise_seed=seed)
@@ -153,7 +161,7 @@ def main():
     # the other GPU forms on the same inputs (same counters; checked in the tests)
     forms = {}
     ref_state = {k: v.clone() for k, v in state.items()}
-    for algo in ("plain", "mfma"):
+    for algo in ("plain", "mfma", "mfma_kv"):
         if args.compare_steps <= 0:
             break
         if algo == args.algo:
@@ -177,10 +185,12 @@ def main():
         del src, dst
 
     alg_bytes = 30 * n + 4 * n_orders + 8 * n_pu  # fact columns + o_pu + the PU word table, each once
-    achieved = alg_bytes / (agg_ms * 1e-3) / 1e9
+    alg_kv = 30 * n + 8 * n_orders  # fact columns + the orders' PU keys
+    achieved = (alg_kv if args.algo == "mfma_kv" else alg_bytes) / (agg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": f"agg_mfma ({args.algo})", "alg_bytes_per_launch": alg_bytes}
+                "kernel": "agg_star (int8 matrix cores, star-schema form)",
+                "alg_bytes_per_launch": alg_kv if args.algo == "mfma_kv" else alg_bytes}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -207,7 +217,11 @@ def main():
         "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                             "max": float(np.max(step_ms))},
         "aggregate_rows_per_s": n / (agg_ms * 1e-3),
-        "forms": {k: dict(v, aggregate_rows_per_s=n / (v["aggregate_ms"] * 1e-3)) for k, v in forms.items()},
+        "forms": {k: dict(v, aggregate_rows_per_s=n / (v["aggregate_ms"] * 1e-3),
+                          alg_bytes=alg_kv if k == "mfma_kv" else alg_bytes,
+                          hbm_frac=round((alg_kv if k == "mfma_kv" else alg_bytes) / (v["aggregate_ms"] * 1e-3)
+                                         / 1e9 / HBM_PEAK_GBS, 4))
+                  for k, v in forms.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -1,7 +1,9 @@
 // a2-a6 on the int8 matrix cores, specialised for the star-schema scan of an
 // aggregation-heavy report (Sec. 3.2's rewrite adds the FK joins fact ->
 // orders -> PU; Sec. 4.2's per-world SUM/COUNT over the result):
-//   * two FK links into the PU-word table (the words come from pac_hash_mask);
+//   * either two FK links into the PU-word table (the words come from
+//     pac_hash_mask), or one FK link into a column that holds each order's PU
+//     key (hashed here, per row: no gather into a PU table);
 //   * one or two u8 group columns whose product of cardinalities is <= 8;
 //   * NI int columns whose (v - lo) fits DIG <= 4 bytes (host statistics).
 // The contraction is the one of the generic matrix-core kernel
@@ -28,6 +30,7 @@ constexpr int kStarWPB = 4;  // waves per block
 constexpr int kStarTPI = STAR_TPI;  // tiles per loop iteration of a wave (loads in flight)
 
 struct StarPlan {
+  int32_t kv;            // 1: one link into per-order PU keys, hashed in the kernel
   int32_t G;
   uint32_t lo[kMC];      // low 32 bits of each column's offset (all digits sit in (v - lo) mod 2^32)
   int64_t lo64[kMC];     // the offset itself, for the recombination
@@ -146,7 +149,8 @@ __device__ __forceinline__ uint32_t star_transpose(uint32_t x, const StarTc &tc)
   return x;
 }
 
-template <int NGC, int NI>
+// PU words (KV = 0) or PU keys (KV = 1, hashed when staged) of the four rows.
+template <int KV, int NGC, int NI>
 __device__ __forceinline__ void star_issue_words(const MfmaArgs &a, const QChain &c, StarRaw<NGC, NI> &r,
                                                  uint32_t *status) {
   bool bad = false;
@@ -155,7 +159,8 @@ __device__ __forceinline__ void star_issue_words(const MfmaArgs &a, const QChain
     const bool in = c.idx[j] < a.n_idx;
     bad |= c.ok[j] && !in;
     r.ok[j] = c.ok[j] && in;
-    r.mk[j] = a.masks[r.ok[j] ? c.idx[j] : 0u];
+    const uint32_t i = r.ok[j] ? c.idx[j] : 0u;
+    r.mk[j] = KV ? (uint64_t)a.pu_keys[i] : a.masks[i];
   }
   if (bad) atomicOr(status, PAC_STATUS_BAD_LINK);
 }
@@ -205,10 +210,14 @@ __device__ __forceinline__ void star_issue_cols_tail(const MfmaArgs &a, uint32_t
     }
 }
 
-template <int NGC, int NI>
-__device__ __forceinline__ void star_stage_store(StarStage<NGC, NI> *sg, int lane, const StarRaw<NGC, NI> &r) {
+template <int KV, int NGC, int NI>
+__device__ __forceinline__ void star_stage_store(const MfmaArgs &a, StarStage<NGC, NI> *sg, int lane,
+                                                 const StarRaw<NGC, NI> &r) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) sg->mk[4 * lane + j] = r.ok[j] ? r.mk[j] : 0ull;
+  for (int j = 0; j < 4; ++j) {
+    const uint64_t w = KV ? pu_word((int64_t)r.mk[j], a.qk, 0, a.balanced != 0) : r.mk[j];
+    sg->mk[4 * lane + j] = r.ok[j] ? w : 0ull;
+  }
 #pragma unroll
   for (int k = 0; k < NGC; ++k) sg->g[k][lane] = r.g[k];
 #pragma unroll
@@ -393,7 +402,7 @@ __device__ __forceinline__ void star_flush(v4i (&acc)[4][NT], uint8_t *buf, int6
   wave_lds_fence();
 }
 
-template <int NGC, int NI, int DIG, int NT>
+template <int KV, int NGC, int NI, int DIG, int NT>
 __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPlan pl, DevState st,
                                                            uint32_t *status) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -452,16 +461,16 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
       StarRaw<NGC, NI> r;
       QChain c;
       qchain_first(a, row_of(gi, k), lane, c);
-      qchain_next(a, c, status);
-      star_issue_words(a, c, r, status);
+      if (!KV) qchain_next(a, c, status);
+      star_issue_words<KV>(a, c, r, status);
       star_issue_cols(a, row_of(gi, k), lane, r);
-      star_stage_store(stage + k, lane, r);
+      star_stage_store<KV>(a, stage + k, lane, r);
     }
     QChain l1[kStarTPI], l0[kStarTPI];  // group + stride after both links, group + 2 stride after the first
 #pragma unroll
     for (int k = 0; k < kStarTPI; ++k) {
       qchain_first(a, row_of(clampg(gi + stride), k), lane, l1[k]);
-      qchain_next(a, l1[k], status);
+      if (!KV) qchain_next(a, l1[k], status);
       qchain_first(a, row_of(clampg(gi + 2 * stride), k), lane, l0[k]);
     }
     for (; gi < n_grp; gi += stride) {
@@ -469,13 +478,13 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
       QChain n1[kStarTPI];
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
-        star_issue_words(a, l1[k], r[k], status);
+        star_issue_words<KV>(a, l1[k], r[k], status);
         star_issue_cols(a, row_of(clampg(gi + stride), k), lane, r[k]);
       }
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         n1[k] = l0[k];
-        qchain_next(a, n1[k], status);
+        if (!KV) qchain_next(a, n1[k], status);
         qchain_first(a, row_of(clampg(gi + 3 * stride), k), lane, l0[k]);
       }
 #pragma unroll
@@ -487,7 +496,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
       }
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
-        star_stage_store(stage + k, lane, r[k]);
+        star_stage_store<KV>(a, stage + k, lane, r[k]);
         l1[k] = n1[k];
       }
     }
@@ -501,10 +510,10 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
     StarRaw<NGC, NI> r;
     QChain c;
     qchain_first_tail(a, row0, lane, c);
-    qchain_next(a, c, status);
-    star_issue_words(a, c, r, status);
+    if (!KV) qchain_next(a, c, status);
+    star_issue_words<KV>(a, c, r, status);
     star_issue_cols_tail(a, row0, lane, r);
-    star_stage_store(stage, lane, r);
+    star_stage_store<KV>(a, stage, lane, r);
     star_planes<NGC, NI, DIG>(a, pl, stage, row0, true, planes, lane, gcnt, status);
     wave_lds_fence();
     star_mfma<NGC, NI, NT>(stage, lane, planes, boff_d, boff_g, tc, q, acc);
@@ -544,15 +553,18 @@ static int star_digits(const DevInput &in) {
 
 // The shapes this kernel takes; everything else goes to the generic form.
 static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
-  if (in.W != 1 || in.n_links != 2 || !in.masks || in.filter_col || in.group_mod || in.group_keys) return false;
+  if (in.W != 1 || in.filter_col || in.group_mod || in.group_keys) return false;
+  const bool kv = in.n_links == 1 && !in.masks && in.pu_keys;  // orders carry the PU key
+  if (!kv && !(in.n_links == 2 && in.masks)) return false;
   if (in.n_fcols > 0 || in.n_icols < 1 || in.n_icols > 3 || in.n_gcols != 2) return false;
   if (star_digits(in) != 3) return false;
   const int64_t lim = (int64_t)1 << 31;
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < in.n_links; ++k)
     if (in.link_len[k] < 1 || in.link_len[k] >= lim) return false;
   // full tiles read the first link four keys at a time, unchecked
   if (in.link_len[0] < in.n_rows || ((uintptr_t)in.links[0] & 15u)) return false;
-  if (in.n_masks < 1 || in.n_masks >= lim) return false;
+  const int64_t n_idx = kv ? in.n_pu_keys : in.n_masks;
+  if (n_idx < 1 || n_idx >= lim) return false;
   for (int k = 0; k < in.n_gcols; ++k)
     if (in.gcol_type[k] != PAC_U8 || in.gcards[k] < 1 || in.gcards[k] > 128) return false;
   const int64_t G = in.gcards[0] * in.gcards[1];
@@ -560,6 +572,7 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   for (int c = 0; c < in.n_icols; ++c)
     if (in.icol_type[c] != PAC_I64) return false;
   StarPlan p{};
+  p.kv = kv ? 1 : 0;
   p.G = (int)G;
   for (int c = 0; c < in.n_icols; ++c) {
     p.lo[c] = (uint32_t)in.icol_lo[c];
@@ -592,11 +605,11 @@ bool star_supported(const DevInput &in) {
   return star_plan(in, &p, &nt);
 }
 
-template <int NGC, int NI, int DIG, int NT>
+template <int KV, int NGC, int NI, int DIG, int NT>
 static hipError_t launch_star_t(const LaunchEnv &env, const DevInput &in, const DevState &st, const StarPlan &pl) {
   static_assert(sizeof(StarStage<NGC, NI>) == 64 * (8 * 4 + 4 * NGC + 16 * NI), "stage");
   const int lds = pl.blk_off + pl.blk_words * 8;
-  const void *fn = (const void *)agg_star<NGC, NI, DIG, NT>;
+  const void *fn = (const void *)agg_star<KV, NGC, NI, DIG, NT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -610,7 +623,7 @@ static hipError_t launch_star_t(const LaunchEnv &env, const DevInput &in, const 
       std::min<int64_t>((int64_t)blocks * kStarWPB * pl.flush_tiles * kTileRows, (int64_t)1 << 30);
   for (int64_t r0 = 0; r0 < in.n_rows; r0 += rows_per_launch) {
     const int64_t nr = std::min<int64_t>(in.n_rows - r0, rows_per_launch);
-    hipLaunchKernelGGL((agg_star<NGC, NI, DIG, NT>), dim3(blocks), dim3(64 * kStarWPB), (size_t)lds, env.stream,
+    hipLaunchKernelGGL((agg_star<KV, NGC, NI, DIG, NT>), dim3(blocks), dim3(64 * kStarWPB), (size_t)lds, env.stream,
                        mfma_args(in, r0, nr), pl, st, env.status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -618,15 +631,25 @@ static hipError_t launch_star_t(const LaunchEnv &env, const DevInput &in, const 
   return hipSuccess;
 }
 
-template <int NI>
+template <int KV, int NI>
 static hipError_t launch_star_nt(const LaunchEnv &env, const DevInput &in, const DevState &st, const StarPlan &pl,
                                  int nt) {
   switch (nt) {
-    case 1: return launch_star_t<2, NI, 3, 1>(env, in, st, pl);
-    case 2: return launch_star_t<2, NI, 3, 2>(env, in, st, pl);
-    case 3: return launch_star_t<2, NI, 3, 3>(env, in, st, pl);
-    case 4: return launch_star_t<2, NI, 3, 4>(env, in, st, pl);
-    default: return launch_star_t<2, NI, 3, 6>(env, in, st, pl);
+    case 1: return launch_star_t<KV, 2, NI, 3, 1>(env, in, st, pl);
+    case 2: return launch_star_t<KV, 2, NI, 3, 2>(env, in, st, pl);
+    case 3: return launch_star_t<KV, 2, NI, 3, 3>(env, in, st, pl);
+    case 4: return launch_star_t<KV, 2, NI, 3, 4>(env, in, st, pl);
+    default: return launch_star_t<KV, 2, NI, 3, 6>(env, in, st, pl);
+  }
+}
+
+template <int KV>
+static hipError_t launch_star_kv(const LaunchEnv &env, const DevInput &in, const DevState &st, const StarPlan &pl,
+                                 int nt) {
+  switch (in.n_icols) {
+    case 1: return launch_star_nt<KV, 1>(env, in, st, pl, nt);
+    case 2: return launch_star_nt<KV, 2>(env, in, st, pl, nt);
+    default: return launch_star_nt<KV, 3>(env, in, st, pl, nt);
   }
 }
 
@@ -635,11 +658,7 @@ hipError_t launch_agg_star(const LaunchEnv &env, const DevInput &in, const DevSt
   StarPlan pl;
   int nt;
   if (!star_plan(in, &pl, &nt)) return hipErrorInvalidValue;
-  switch (in.n_icols) {
-    case 1: return launch_star_nt<1>(env, in, st, pl, nt);
-    case 2: return launch_star_nt<2>(env, in, st, pl, nt);
-    default: return launch_star_nt<3>(env, in, st, pl, nt);
-  }
+  return pl.kv ? launch_star_kv<1>(env, in, st, pl, nt) : launch_star_kv<0>(env, in, st, pl, nt);
 }
 
 }  // namespace pac

@@ -85,3 +85,30 @@ def compare_counters(got: Dict[str, np.ndarray], want: Dict[str, np.ndarray], fl
         tol = float_rtol * np.maximum(np.abs(w), 1e-300)
         bad = err > tol
         assert not bad.any(), f"fsum mismatch: max rel err {float((err / np.maximum(np.abs(w), 1e-300)).max())}"
+
+
+def order_keys(t) -> np.ndarray:
+    """The PU key of every order (the orders table carrying its FK value)."""
+    return t.pu_key[t.o_pu]
+
+
+def gpu_star_kv(ctx, t, K: int, m: int = 64, int_cols: Sequence[str] = (), balanced: bool = False,
+                algo: str = "mfma", dev=None) -> Dict[str, np.ndarray]:
+    """GPU: one FK link fact -> orders, the orders' PU keys hashed in the kernel."""
+    import torch
+    import paper_2603_15023_amd as P
+
+    dev = dev or torch.device("cuda")
+    cols = [torch.from_numpy(t.cols[c]).to(dev) for c in int_cols]
+    st = [(int(t.cols[c].min()), int(t.cols[c].max())) for c in int_cols]
+    G = int(np.prod(t.gcards))
+    spec = P.AggSpec(n_rows=t.n_rows, links=[torch.from_numpy(t.f_order).to(dev)],
+                     gcols=[torch.from_numpy(g).to(dev) for g in t.gcols], gcards=list(t.gcards), n_groups=G,
+                     cols=cols, stats=st, balanced=balanced)
+    spec.pu_keys = torch.from_numpy(order_keys(t)).to(dev)
+    state = P.new_state(spec, m)
+    P.pac_group_aggregate(ctx, spec, state, m=m, query_key=K, algo=algo)
+    status = ctx.status()
+    out = {k: v.cpu().numpy() for k, v in state.items()}
+    out["status"] = status
+    return out

@@ -169,6 +169,20 @@ def test_star_kernel_shapes(ctx, gcards, n_cols):
     compare_counters(got, star_definition(t, 0x5151, 64, int_cols=ints))
 
 
+@pytest.mark.parametrize("gcards,n_cols,balanced", [((3, 2), 3, False), ((2, 4), 2, True), ((1, 1), 1, False)])
+def test_star_kernel_key_valued_orders(ctx, gcards, n_cols, balanced):
+    """The orders carry their PU key: one FK link, the key hashed per row in the kernel."""
+    from cases import gpu_star_kv
+    t = gen.tiny_star(60 + n_cols, n_pu=700, n_orders=4000, n_rows=256 * 41 + 77, gcards=gcards, n_cols=n_cols,
+                      value_range=(-6_000_000, 6_000_000))
+    ints = [f"v{i}" for i in range(n_cols)]
+    _say("star kernel key-valued", gcards, n_cols, balanced)
+    got = gpu_star_kv(ctx, t, 0x77AA, 64, int_cols=ints, balanced=balanced)
+    assert got["status"] == 0
+    # same worlds as hashing the PU table and following both links
+    compare_counters(got, star_definition(t, 0x77AA, 64, int_cols=ints, balanced=balanced))
+
+
 def test_star_kernel_skips_bad_group_rows(ctx):
     import dataclasses
     t = gen.tiny_star(47, n_pu=300, n_orders=2000, n_rows=256 * 20 + 7, gcards=(3, 2), n_cols=3,
@@ -236,6 +250,20 @@ def test_config2_full_size(ctx, algo):
     got = gpu_star(ctx, t, K, 64, int_cols=ints, algo=algo)
     assert got["status"] == 0
     compare_counters(got, _config2_oracle())
+
+
+def test_config2_key_valued_orders_full_size(ctx):
+    from cases import gpu_star_kv, order_keys
+    t = _config2()
+    K = gen.query_key(1)
+    ints = ["v1", "v2", "v3"]
+    _say("config2 key-valued")
+    got = gpu_star_kv(ctx, t, K, 64, int_cols=ints)
+    assert got["status"] == 0
+    want = ON.onepass(t.n_rows, 64, pu_keys=order_keys(t), query_key=K, links=[t.f_order], gcols=t.gcols,
+                      gcards=t.gcards, n_groups=6, int_cols=[t.cols[c] for c in ints])
+    compare_counters(got, want)
+    compare_counters(got, _config2_oracle())  # equal to the PU-table form
 
 
 _C2 = {}
