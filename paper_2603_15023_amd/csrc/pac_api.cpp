@@ -298,14 +298,13 @@ int pac_ctx_destroy(pac_ctx *ctx) {
 int pac_check(pac_ctx *ctx, void *stream, uint32_t *status) {
   if (!ctx) return fail(PAC_ERR_INVALID, "null context");
   DeviceGuard guard(ctx->device);
-  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  // read and clear on the caller's stream only (other streams keep running)
+  const hipStream_t st = (hipStream_t)stream;
   uint32_t s = 0;
-  e = hipMemcpy(&s, ctx->d_status, sizeof(s), hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpyAsync(&s, ctx->d_status, sizeof(s), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_status, 0, sizeof(uint32_t), st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "status read");
-  const uint32_t zero = 0;
-  e = hipMemcpy(ctx->d_status, &zero, sizeof(zero), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "status clear");
   if (status) *status = s;
   if (s) return fail(PAC_ERR_DEVICE_STATUS, "device status bits 0x%x", s);
   return PAC_OK;

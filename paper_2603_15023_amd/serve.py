@@ -1,0 +1,226 @@
+"""Query serving over a resident star schema with continuous batching.
+
+Tables stay resident in HBM.  Each query of the served workload (a filter on
+a selection column, groups = a group-source column modulo G, 1-3 of COUNT /
+SUM / AVG over int64 or float64 columns, its own query key and noise seed) is
+one hash (a1), one aggregation (a2-a6) and one release (a7) through the C ABI.
+
+The server keeps a fixed number of slots.  Each slot owns a library context
+(scratch and status word), a HIP stream and a PU-word buffer, so the queries
+of different slots run concurrently on the device.  Queries wait in arrival
+order; the head of the queue is admitted as soon as a slot is free and its
+counters fit in the counter pool (admission by counter memory), so queries
+that arrive while others are on the GPU join as resources free up instead of
+waiting for a batch to drain.  Completion is detected by polling events; the
+latency of a query is completion minus arrival on the host clock.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from .api import AggSpec, Context, new_state, pac_finalize, pac_group_aggregate, pac_hash_mask
+
+CELL_DTYPE = np.dtype([("group", "<i8"), ("kind", "<i4"), ("col", "<i4")])
+INT_COLS = ("v1", "v2", "v3")
+FLOAT_COLS = ("vf",)
+
+
+@dataclasses.dataclass
+class ResidentStar:
+    """Device copies of a star schema: PU keys, fact -> orders -> PU links, filter / group / value columns."""
+
+    n_rows: int
+    pu_key: torch.Tensor
+    f_order: torch.Tensor
+    o_pu: torch.Tensor
+    sel: torch.Tensor      # uint32 bits in int32
+    gsrc: torch.Tensor     # uint32 bits in int32
+    gsrc_card: int
+    cols: Dict[str, torch.Tensor]
+    stats: Dict[str, tuple]
+
+    @classmethod
+    def from_table(cls, t, device=None, gsrc_card: int = 100_000) -> "ResidentStar":
+        dev = device or torch.device("cuda")
+        cols = {k: torch.from_numpy(v).to(dev) for k, v in t.cols.items()}
+        stats = {k: (int(v.min()), int(v.max())) for k, v in t.cols.items() if v.dtype.kind == "i" and v.size}
+        return cls(n_rows=t.n_rows, pu_key=torch.from_numpy(t.pu_key).to(dev),
+                   f_order=torch.from_numpy(t.f_order).to(dev), o_pu=torch.from_numpy(t.o_pu).to(dev),
+                   sel=torch.from_numpy(t.sel.view(np.int32)).to(dev),
+                   gsrc=torch.from_numpy(t.gsrc.view(np.int32)).to(dev), gsrc_card=gsrc_card, cols=cols,
+                   stats=stats)
+
+
+def query_columns(q) -> tuple:
+    """(int columns, float columns) that the query's aggregates read, in first-use order."""
+    ints, flts = [], []
+    for _, col in q.aggs:
+        if col is None or col in ints or col in flts:
+            continue
+        if col in INT_COLS:
+            ints.append(col)
+        else:
+            flts.append(col)
+    return ints, flts
+
+
+def query_cells(q) -> np.ndarray:
+    """Released cells in posterior order: group ascending, then the aggregates in argument order."""
+    ints, flts = query_columns(q)
+    per = []
+    for kind, col in q.aggs:
+        if kind == "count":
+            per.append((A.PAC_CELL_COUNT, 0))
+        elif col in ints:
+            per.append((A.PAC_CELL_SUM_I if kind == "sum" else A.PAC_CELL_AVG_I, ints.index(col)))
+        else:
+            per.append((A.PAC_CELL_SUM_F if kind == "sum" else A.PAC_CELL_AVG_F, flts.index(col)))
+    G = q.n_groups
+    cells = np.empty(G * len(per), dtype=CELL_DTYPE)
+    cells["group"] = np.repeat(np.arange(G, dtype=np.int64), len(per))
+    cells["kind"] = np.tile(np.array([k for k, _ in per], dtype=np.int32), G)
+    cells["col"] = np.tile(np.array([c for _, c in per], dtype=np.int32), G)
+    return cells
+
+
+def counter_bytes(q, m: int = 64) -> int:
+    ints, flts = query_columns(q)
+    return q.n_groups * ((1 + len(ints) + len(flts)) * m + 1) * 8
+
+
+def query_spec(table: ResidentStar, q, masks: torch.Tensor) -> AggSpec:
+    ints, flts = query_columns(q)
+    return AggSpec(n_rows=table.n_rows, masks=masks, links=[table.f_order, table.o_pu], gcols=[table.gsrc],
+                   gcards=[table.gsrc_card], group_mod=q.n_groups, n_groups=q.n_groups, filter_col=table.sel,
+                   filter_lt=q.filter_lt, cols=[table.cols[c] for c in ints + flts],
+                   stats=[table.stats[c] for c in ints] + [(0, 0)] * len(flts))
+
+
+class Admission:
+    """FIFO admission by free slots and counter memory (host logic only)."""
+
+    def __init__(self, n_slots: int, pool_bytes: int):
+        self.free_slots = list(range(n_slots))[::-1]
+        self.pool_bytes = pool_bytes
+        self.used = 0
+
+    def try_admit(self, need: int) -> Optional[int]:
+        if need > self.pool_bytes:
+            raise ValueError(f"query needs {need} counter bytes, pool holds {self.pool_bytes}")
+        if not self.free_slots or self.used + need > self.pool_bytes:
+            return None
+        self.used += need
+        return self.free_slots.pop()
+
+    def release(self, slot: int, need: int) -> None:
+        self.used -= need
+        self.free_slots.append(slot)
+
+
+@dataclasses.dataclass
+class QueryResult:
+    qid: int
+    values: np.ndarray
+    is_null: np.ndarray
+    flags: np.ndarray
+    status: int
+    arrival: float = 0.0
+    admitted: float = 0.0
+    done: float = 0.0
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Slot:
+    def __init__(self, device_index: int, n_pu: int, m: int):
+        self.ctx = Context(device_index)
+        self.stream = torch.cuda.Stream()  # default priority
+        self.masks = torch.empty((n_pu, m // 64), dtype=torch.int64, device=torch.device("cuda", device_index))
+
+
+class Server:
+    """Continuous-batching query server over one resident table on one GPU."""
+
+    def __init__(self, table: ResidentStar, n_slots: int = 4, pool_bytes: int = 8 << 30, m: int = 64,
+                 mi_budget: float = 1.0 / 128, device_index: int = 0):
+        self.table, self.m, self.budget = table, m, mi_budget
+        self.slots = [_Slot(device_index, table.pu_key.shape[0], m) for _ in range(n_slots)]
+        self.n_slots, self.pool_bytes = n_slots, pool_bytes
+
+    def _launch(self, slot: _Slot, q):
+        s = slot.stream
+        with torch.cuda.stream(s):
+            pac_hash_mask(slot.ctx, self.table.pu_key, q.query_key, self.m, out=slot.masks, stream=s)
+            spec = query_spec(self.table, q, slot.masks)
+            state = new_state(spec, self.m)
+            pac_group_aggregate(slot.ctx, spec, state, m=self.m, query_key=q.query_key, algo="auto", stream=s)
+            cells = query_cells(q)
+            cells_d = torch.from_numpy(cells.view(np.uint8)).to(slot.masks.device)
+            vals, nulls, flags, _, _ = pac_finalize(slot.ctx, state, cells_d, len(cells), m=self.m,
+                                                    mi_budget=self.budget, noise_seed=q.noise_seed, stream=s)
+            host = tuple(torch.empty(x.shape, dtype=x.dtype, pin_memory=True) for x in (vals, nulls, flags))
+            for h, x in zip(host, (vals, nulls, flags)):
+                h.copy_(x, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        # device tensors stay referenced until completion
+        return ev, host, (state, cells_d, vals, nulls, flags)
+
+    def run(self, queries: Sequence, arrivals: Optional[Sequence[float]] = None,
+            poll_sleep: float = 0.0) -> List[QueryResult]:
+        """Serves the queries; arrivals are offsets in seconds from the start (None: all at once)."""
+        arrivals = np.zeros(len(queries)) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
+        order = np.argsort(arrivals, kind="stable")
+        adm = Admission(self.n_slots, self.pool_bytes)
+        waiting = collections.deque()
+        inflight = {}
+        results: List[QueryResult] = []
+        nxt = 0
+        t0 = time.perf_counter()
+        while nxt < len(order) or waiting or inflight:
+            now = time.perf_counter() - t0
+            while nxt < len(order) and arrivals[order[nxt]] <= now:
+                waiting.append(int(order[nxt]))
+                nxt += 1
+            while waiting:  # admit from the head while a slot and counter memory are free
+                i = waiting[0]
+                need = counter_bytes(queries[i], self.m)
+                slot_id = adm.try_admit(need)
+                if slot_id is None:
+                    break
+                waiting.popleft()
+                ev, host, keep = self._launch(self.slots[slot_id], queries[i])
+                inflight[i] = (slot_id, need, ev, host, keep, time.perf_counter() - t0)
+            done = [i for i, rec in inflight.items() if rec[2].query()]
+            for i in done:
+                slot_id, need, ev, host, keep, t_adm = inflight.pop(i)
+                t_done = time.perf_counter() - t0
+                st = self.slots[slot_id].ctx.status(self.slots[slot_id].stream)
+                results.append(QueryResult(qid=queries[i].qid, values=host[0].numpy().copy(),
+                                           is_null=host[1].numpy().copy(), flags=host[2].numpy().copy(),
+                                           status=st, arrival=float(arrivals[i]), admitted=t_adm, done=t_done))
+                adm.release(slot_id, need)
+            if not done and poll_sleep:
+                time.sleep(poll_sleep)
+        return results
+
+    def close(self):
+        torch.cuda.synchronize()
+        for s in self.slots:
+            s.ctx.close()
+
+
+def latency_summary(results: Sequence[QueryResult]) -> dict:
+    lat = np.array([r.latency for r in results]) * 1e3
+    span = max(r.done for r in results) - min(r.arrival for r in results)
+    return {"queries": len(results), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "qps": len(results) / span if span > 0 else float("inf")}

@@ -18,3 +18,20 @@ def oracle_native():
     from oracle import native
     native.build(force=False)
     return native
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    """A library context on GPU 0 (GPU tests only)."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2603_15023_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch

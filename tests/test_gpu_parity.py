@@ -25,22 +25,6 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
-    import torch
-    assert torch.cuda.is_available(), "GPU tests need a GPU"
-    import paper_2603_15023_amd as P
-    c = P.Context(0)
-    yield c
-    c.close()
-
-
-@pytest.fixture(scope="module")
-def torch_mod():
-    import torch
-    return torch
-
-
 # ----------------------------------------------------------------------------- a1 hash
 @pytest.mark.parametrize("m", [64, 128])
 @pytest.mark.parametrize("balanced", [False, True])
@@ -264,6 +248,60 @@ def test_config2_key_valued_orders_full_size(ctx):
                       gcards=t.gcards, n_groups=6, int_cols=[t.cols[c] for c in ints])
     compare_counters(got, want)
     compare_counters(got, _config2_oracle())  # equal to the PU-table form
+
+
+def test_config3_full_size_hash_table(ctx, torch_mod):
+    """100M rows, 2M PU keys per row, Zipf(1.1) group keys over 1M ranks into the HBM hash table."""
+    import paper_2603_15023_amd as P
+    t = gen.config3_zipf()
+    K = gen.query_key(3)
+    _say("config3 full size")
+    dev = torch_mod.device("cuda")
+    spec = P.AggSpec(n_rows=t.n_rows, pu_keys=torch_mod.from_numpy(t.pu_key).to(dev),
+                     group_keys=torch_mod.from_numpy(t.group_keys).to(dev), n_groups=1 << 21,
+                     cols=[torch_mod.from_numpy(t.cols["v"]).to(dev)])
+    st = P.new_state(spec, 64)
+    P.pac_group_aggregate(ctx, spec, st, m=64, query_key=K, algo="auto")
+    assert ctx.status() == 0
+    want = ON.onepass(t.n_rows, 64, pu_keys=t.pu_key, query_key=K, group_keys=t.group_keys, n_groups=1 << 20,
+                      int_cols=[t.cols["v"]])
+    slot_keys = st["slot_keys"].cpu().numpy()
+    used = slot_keys != np.iinfo(np.int64).min
+    assert int(st["n_used"].cpu()[0]) == used.sum() == len(want["keys"])
+    order = np.argsort(slot_keys[used])
+    assert np.array_equal(slot_keys[used][order], want["keys"])
+    got = {k: st[k].cpu().numpy()[used][order] for k in ("count", "isum", "nrows")}
+    got["fsum"] = np.zeros((len(order), 0, 64))
+    compare_counters(got, want)
+
+
+@pytest.mark.parametrize("m", [64, 128])
+def test_config4_full_size_float(ctx, torch_mod, m):
+    """200M rows, lognormal FP64 values and their FP32 copy, 64 groups: FP64 sums within 1e-12."""
+    import paper_2603_15023_amd as P
+    t = _config4()
+    K = gen.query_key(4)
+    _say("config4 full size", m)
+    dev = torch_mod.device("cuda")
+    spec = P.AggSpec(n_rows=t.n_rows, pu_keys=torch_mod.from_numpy(t.pu_key).to(dev),
+                     gcols=[torch_mod.from_numpy(t.gcols[0]).to(dev)], gcards=[64], n_groups=64,
+                     cols=[torch_mod.from_numpy(t.cols["v64"]).to(dev), torch_mod.from_numpy(t.cols["v32"]).to(dev)])
+    st = P.new_state(spec, m)
+    P.pac_group_aggregate(ctx, spec, st, m=m, query_key=K, algo="auto")
+    assert ctx.status() == 0
+    got = {k: v.cpu().numpy() for k, v in st.items()}
+    want = ON.onepass(t.n_rows, m, pu_keys=t.pu_key, query_key=K, gcols=t.gcols, gcards=[64], n_groups=64,
+                      float_cols=[t.cols["v64"], t.cols["v32"].astype(np.float64)])
+    compare_counters(got, want)
+
+
+_C4 = {}
+
+
+def _config4():
+    if "t" not in _C4:
+        _C4["t"] = gen.config4_float()
+    return _C4["t"]
 
 
 _C2 = {}

@@ -1,0 +1,46 @@
+"""Host-side serving logic (no GPU): admission by slots and counter memory, cell order, sizes."""
+import numpy as np
+import pytest
+
+from workloads import gen
+
+
+def test_admission_respects_slots_and_memory():
+    from paper_2603_15023_amd.serve import Admission
+    a = Admission(n_slots=2, pool_bytes=100)
+    s0 = a.try_admit(60)
+    assert s0 is not None
+    assert a.try_admit(50) is None          # memory: 60 + 50 > 100
+    s1 = a.try_admit(40)
+    assert s1 is not None and s1 != s0
+    assert a.try_admit(1) is None           # no slot left
+    a.release(s0, 60)
+    assert a.try_admit(50) == s0
+    with pytest.raises(ValueError):
+        a.try_admit(101)                    # can never fit
+
+
+def test_query_cells_order_and_columns():
+    from paper_2603_15023_amd import _abi as A
+    from paper_2603_15023_amd.serve import counter_bytes, query_cells, query_columns
+    q = gen.ServedQuery(qid=0, filter_lt=1 << 31, n_groups=3,
+                        aggs=[("avg", "vf"), ("count", None), ("sum", "v2"), ("sum", "vf")],
+                        query_key=5, noise_seed=7, gap=1.0)
+    ints, flts = query_columns(q)
+    assert ints == ["v2"] and flts == ["vf"]
+    cells = query_cells(q)
+    assert list(cells["group"]) == [0] * 4 + [1] * 4 + [2] * 4
+    assert list(cells["kind"][:4]) == [A.PAC_CELL_AVG_F, A.PAC_CELL_COUNT, A.PAC_CELL_SUM_I, A.PAC_CELL_SUM_F]
+    assert list(cells["col"][:4]) == [0, 0, 0, 0]
+    assert counter_bytes(q) == 3 * ((1 + 1 + 1) * 64 + 1) * 8
+
+
+def test_served_workload_shape():
+    qs = gen.config5_queries(2000)
+    G = np.array([q.n_groups for q in qs])
+    theta = np.array([q.filter_lt for q in qs]) / 2.0 ** 32
+    assert G.min() >= 1 and G.max() <= 100_000
+    assert 0.0009 <= theta.min() and theta.max() <= 0.5
+    # log-uniform: about half of the queries below the geometric middle
+    assert 0.4 < np.mean(np.log10(G) < 2.5) < 0.6
+    assert all(1 <= len(q.aggs) <= 3 for q in qs)
