@@ -53,6 +53,11 @@ typedef struct pac_ctx pac_ctx;
  * a scratch pool on device `hip_device`.  Not thread-safe. */
 int pac_ctx_create(int hip_device, pac_ctx **out);
 int pac_ctx_destroy(pac_ctx *ctx);
+/* Grows the context's device scratch pool to at least `bytes` now.  Calls
+ * otherwise grow it on demand, which synchronises the device once per growth;
+ * a serving loop reserves its working size up front instead.  Returns
+ * PAC_ERR_OOM if the allocation fails (the old pool is kept). */
+int pac_ctx_reserve(pac_ctx *ctx, size_t bytes);
 const char *pac_last_error(void);
 /* Synchronises `stream`, returns the device status bits in *status (may be
  * NULL) and clears them.  Returns PAC_ERR_DEVICE_STATUS if any bit was set. */
@@ -139,6 +144,7 @@ typedef struct {
 #define PAC_ALGO_PLAIN 1u   /* lane = world, rows broadcast, predicated adds (the paper's update loop) */
 #define PAC_ALGO_BALLOT 2u  /* ballot transpose of world bits, popcounts of bit-sliced values (ints) */
 #define PAC_ALGO_MFMA_I8 3u /* int8 matrix cores on byte digits, exact int32 -> int64 recombination */
+#define PAC_ALGO_PARTITION 4u /* many groups: rows radix-partitioned by group slot, each partition in LDS */
 #define PAC_AGG_INIT 1u     /* clear the state (and the sparse table) before aggregating */
 
 /* m in {64, 128}; query_key is used by the fused hash.  Returns

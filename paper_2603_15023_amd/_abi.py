@@ -16,8 +16,9 @@ ERRORS = {-1: "PAC_ERR_INVALID", -2: "PAC_ERR_OOM", -3: "PAC_ERR_HIP", -4: "PAC_
           -5: "PAC_ERR_DIVERSITY", -6: "PAC_ERR_UNSUPPORTED", -7: "PAC_ERR_DEVICE_STATUS"}
 PAC_U8, PAC_U16, PAC_U32, PAC_I32, PAC_I64, PAC_F32, PAC_F64 = 1, 2, 3, 4, 5, 6, 7
 PAC_HASH_BALANCED = 1
-PAC_ALGO_AUTO, PAC_ALGO_PLAIN, PAC_ALGO_BALLOT, PAC_ALGO_MFMA_I8 = 0, 1, 2, 3
-ALGOS = {"auto": PAC_ALGO_AUTO, "plain": PAC_ALGO_PLAIN, "ballot": PAC_ALGO_BALLOT, "mfma": PAC_ALGO_MFMA_I8}
+PAC_ALGO_AUTO, PAC_ALGO_PLAIN, PAC_ALGO_BALLOT, PAC_ALGO_MFMA_I8, PAC_ALGO_PARTITION = 0, 1, 2, 3, 4
+ALGOS = {"auto": PAC_ALGO_AUTO, "plain": PAC_ALGO_PLAIN, "ballot": PAC_ALGO_BALLOT, "mfma": PAC_ALGO_MFMA_I8,
+         "partition": PAC_ALGO_PARTITION}
 PAC_AGG_INIT = 1
 PAC_EMPTY_KEY = -(1 << 63)
 PAC_STATUS_BAD_GROUP, PAC_STATUS_BAD_LINK, PAC_STATUS_TABLE_FULL, PAC_STATUS_DIVERSITY = 1, 2, 4, 8
@@ -58,6 +59,7 @@ class FinalizeParams(C.Structure):
 EXPORTS = {
     "pac_ctx_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
     "pac_ctx_destroy": (C.c_int, [C.c_void_p]),
+    "pac_ctx_reserve": (C.c_int, [C.c_void_p, C.c_size_t]),
     "pac_last_error": (C.c_char_p, []),
     "pac_check": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]),
     "pac_version": (C.c_int, []),

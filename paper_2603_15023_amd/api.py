@@ -66,6 +66,10 @@ class Context:
             A.check(rc)
         return st.value
 
+    def reserve(self, nbytes: int) -> None:
+        """Grow the device scratch pool to ``nbytes`` now (no growth later inside timed or served work)."""
+        A.check(A.load().pac_ctx_reserve(self._h, int(nbytes)))
+
     def close(self):
         if self._h:
             A.load().pac_ctx_destroy(self._h)

@@ -1,0 +1,590 @@
+// a6 for many groups: radix partitioning by group slot, then aggregation of
+// each partition in LDS.
+//
+// When the per-world counters of all groups do not fit in LDS (hundreds of
+// groups and up: a report grouped by a high-cardinality column, or sparse
+// group keys kept in the HBM open-addressing table), updating them with
+// global atomics costs one atomic per (row, world, counter).  Instead:
+//   1. route:     row -> group slot (dense id, or table slot after insert),
+//                 count the rows of every partition of 2^SB consecutive slots;
+//   2. scan:      partition offsets and work items (a partition's rows in
+//                 chunks, so a heavy group -- Zipf head -- is split over many
+//                 workgroups);
+//   3. scatter:   each live row's PU words and values go to its partition as
+//                 a compact record (structure of arrays);
+//   4. aggregate: a workgroup takes work items from a queue, accumulates the
+//                 records into LDS counters [2^SB slots][A][m] (lane = world,
+//                 records broadcast, LDS atomics), then adds the non-zero
+//                 counters to the global state.
+// Counter semantics are those of every other form (per-world COUNT, exact
+// int64 SUM, FP64 SUM, row count per group).  Integer counters are exact in
+// any order, so without float columns a partition is split into chunks and
+// merged with atomics.  With float columns the form is deterministic: one
+// workgroup owns each partition, each of its waves sums a fixed quarter of the
+// records into a private LDS region, the regions are combined in wave order
+// and the owner adds the result to the state without atomics.
+#include <algorithm>
+#include <initializer_list>
+
+#include "pac_internal.h"
+
+namespace pac {
+
+struct PartItem {
+  int64_t part;
+  int64_t begin;
+  int64_t end;
+};
+
+struct PartPlan {
+  bool det;             // float columns: fixed summation order
+  int SB;               // log2 of the slots of a partition
+  int64_t n_slots;      // dense groups, or the table capacity
+  int64_t n_parts;
+  int64_t cap;          // record capacity (= rows)
+  int64_t slot_words;   // A * m + 1 (the last word counts rows)
+  int lds_bytes;
+  int64_t chunk;        // records per work item
+  int64_t max_items;
+  int64_t n_waves;      // deterministic routing: waves, each with a fixed contiguous row range
+  size_t off_mat;       // deterministic routing: per-wave partition counts [n_waves][n_parts]
+  size_t off_row_slot, off_count, off_off, off_cur, off_items, off_meta, off_rec_slot, off_rec_mk, off_rec_iv,
+      off_rec_fv, total;
+};
+
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr int kPartLdsTarget = 80 * 1024;  // two workgroups per CU
+constexpr int kPartWaves = 4;              // waves per workgroup of the aggregation
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool part_plan(const DevInput &in, PartPlan *pl) {
+  PartPlan p{};
+  p.n_slots = in.n_groups;
+  if (in.n_rows <= 0 || in.n_rows >= ((int64_t)1 << 31) || p.n_slots >= (int64_t)kNoSlot) return false;
+  const int A = 1 + in.n_icols + in.n_fcols;
+  p.slot_words = (int64_t)A * in.m + 1;
+  p.det = in.n_fcols > 0;
+  const int regions = p.det ? kPartWaves : 1;  // deterministic: one private region per wave
+  const int64_t per_slot = p.slot_words * 8 * regions;
+  if (per_slot > kPartLdsTarget) return false;
+  int64_t slots = kPartLdsTarget / per_slot;
+  int SB = 0;
+  while (((int64_t)2 << SB) <= slots) ++SB;
+  p.SB = SB;
+  p.lds_bytes = (int)(((int64_t)1 << SB) * per_slot);
+  p.n_parts = (p.n_slots + ((int64_t)1 << SB) - 1) >> SB;
+  p.cap = in.n_rows;
+  p.chunk = p.det ? p.cap : 16384;  // deterministic: one work item per partition
+  p.max_items = p.n_parts + p.cap / p.chunk + 1;
+  if (p.det) {  // records land in row order: per-wave counts instead of atomic cursors
+    const int64_t n_chunks = (in.n_rows + 63) / 64;
+    p.n_waves = std::max<int64_t>(1, std::min<int64_t>({(int64_t)2048, n_chunks, ((int64_t)64 << 20) / p.n_parts}));
+  }
+  size_t o = 0;
+  p.off_mat = o;
+  if (p.det) o = align256(o + 4 * (size_t)p.n_waves * p.n_parts);
+  p.off_row_slot = o; o = align256(o + 4 * (size_t)p.cap);
+  p.off_count = o;    o = align256(o + 4 * (size_t)p.n_parts);
+  p.off_off = o;      o = align256(o + 8 * (size_t)(p.n_parts + 1));
+  p.off_cur = o;      o = align256(o + 4 * (size_t)p.n_parts);
+  p.off_items = o;    o = align256(o + sizeof(PartItem) * (size_t)p.max_items);
+  p.off_meta = o;     o = align256(o + 2 * sizeof(int64_t));  // [0] items, [1] queue head
+  p.off_rec_slot = o; o = align256(o + 4 * (size_t)p.cap);
+  p.off_rec_mk = o;   o = align256(o + 8 * (size_t)in.W * p.cap);
+  p.off_rec_iv = o;   o = align256(o + 8 * (size_t)in.n_icols * p.cap);
+  p.off_rec_fv = o;   o = align256(o + 8 * (size_t)in.n_fcols * p.cap);
+  p.total = o;
+  *pl = p;
+  return true;
+}
+
+bool part_supported(const DevInput &in) {
+  PartPlan p;
+  return part_plan(in, &p);
+}
+
+size_t part_scratch_bytes(const DevInput &in) {
+  PartPlan p;
+  return part_plan(in, &p) ? p.total : 0;
+}
+
+// Each distinct key among the active lanes: leader gets the lanes sharing it.
+__device__ __forceinline__ uint64_t lanes_lt(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+// 1. route and count
+__global__ __launch_bounds__(256) void part_route(DevInput in, DevState st, uint32_t *status, uint32_t *row_slot,
+                                                  uint32_t *count, int SB) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n_chunks = (in.n_rows + 63) >> 6;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks; c += waves) {
+    const int64_t r = c * 64 + lane;
+    int64_t g = -1;
+    if (r < in.n_rows) {
+      g = row_group(in, st, r, status);
+      int64_t idx;
+      if (g >= 0 && !chain_index(in, r, &idx, status)) g = -1;
+      row_slot[r] = g >= 0 ? (uint32_t)g : kNoSlot;
+    }
+    const uint32_t part = g >= 0 ? (uint32_t)(g >> SB) : kNoSlot;
+    uint64_t todo = __ballot(g >= 0);
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
+      const uint64_t same = __ballot(part == p0) & todo;
+      if (lane == leader) atomicAdd(&count[p0], (uint32_t)__popcll(same));
+      todo &= ~same;
+    }
+  }
+}
+
+// 1'. deterministic routing: wave w takes the contiguous chunks [w*cpw, (w+1)*cpw)
+// in order and counts its rows per partition in its own row of `mat`.
+__global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, uint32_t *status,
+                                                      uint32_t *row_slot, uint32_t *mat, int64_t n_parts, int SB,
+                                                      int64_t n_waves) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n_waves) return;
+  const int64_t n_chunks = (in.n_rows + 63) >> 6, cpw = (n_chunks + n_waves - 1) / n_waves;
+  uint32_t *row = mat + w * n_parts;
+  for (int64_t c = w * cpw; c < min(n_chunks, (w + 1) * cpw); ++c) {
+    const int64_t r = c * 64 + lane;
+    int64_t g = -1;
+    if (r < in.n_rows) {
+      g = row_group(in, st, r, status);
+      int64_t idx;
+      if (g >= 0 && !chain_index(in, r, &idx, status)) g = -1;
+      row_slot[r] = g >= 0 ? (uint32_t)g : kNoSlot;
+    }
+    const uint32_t part = g >= 0 ? (uint32_t)(g >> SB) : kNoSlot;
+    uint64_t todo = __ballot(g >= 0);
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
+      const uint64_t same = __ballot(part == p0) & todo;
+      if (lane == leader) row[p0] += (uint32_t)__popcll(same);  // only this wave writes its row
+      todo &= ~same;
+    }
+  }
+}
+
+// Per partition: exclusive prefix of the per-wave counts (in wave order) and the total.
+__global__ __launch_bounds__(256) void part_colscan(uint32_t *mat, int64_t n_parts, int64_t n_waves,
+                                                    uint32_t *count) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_parts) return;
+  uint32_t run = 0;
+  for (int64_t w = 0; w < n_waves; ++w) {
+    const uint32_t c = mat[w * n_parts + p];
+    mat[w * n_parts + p] = run;
+    run += c;
+  }
+  count[p] = run;
+}
+
+// 2. offsets and work items (one workgroup; each thread scans a contiguous run of partitions)
+__global__ __launch_bounds__(1024) void part_scan(const uint32_t *count, int64_t n_parts, int64_t chunk,
+                                                  int64_t *off, uint32_t *cur, PartItem *items, int64_t *meta) {
+  __shared__ int64_t s_rows[1024], s_items[1024];
+  const int t = threadIdx.x, T = blockDim.x;
+  const int64_t per = (n_parts + T - 1) / T;
+  const int64_t p0 = t * per, p1 = min(n_parts, p0 + per);
+  int64_t rows = 0, nit = 0;
+  for (int64_t p = p0; p < p1; ++p) {
+    rows += count[p];
+    nit += (count[p] + chunk - 1) / chunk;
+  }
+  s_rows[t] = rows;
+  s_items[t] = nit;
+  __syncthreads();
+  for (int d = 1; d < T; d <<= 1) {  // inclusive scan over the threads
+    int64_t a = 0, b = 0;
+    if (t >= d) {
+      a = s_rows[t - d];
+      b = s_items[t - d];
+    }
+    __syncthreads();
+    s_rows[t] += a;
+    s_items[t] += b;
+    __syncthreads();
+  }
+  int64_t r0 = s_rows[t] - rows, i0 = s_items[t] - nit;
+  for (int64_t p = p0; p < p1; ++p) {
+    off[p] = r0;
+    cur[p] = 0;
+    const int64_t n = count[p];
+    for (int64_t b = 0; b < n; b += chunk) items[i0++] = PartItem{p, r0 + b, r0 + min(n, b + chunk)};
+    r0 += n;
+  }
+  if (t == T - 1) {
+    off[n_parts] = s_rows[t];
+    meta[0] = s_items[t];
+    meta[1] = 0;
+  }
+}
+
+// 3. scatter the live rows into their partitions
+template <int W>
+__global__ __launch_bounds__(256) void part_scatter(DevInput in, uint32_t *status, const uint32_t *row_slot,
+                                                    const int64_t *off, uint32_t *cur, int SB, int64_t cap,
+                                                    uint32_t *rec_slot, uint64_t *rec_mk, uint64_t *rec_iv,
+                                                    uint64_t *rec_fv) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n_chunks = (in.n_rows + 63) >> 6;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const uint32_t lmask = (1u << SB) - 1u;
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks; c += waves) {
+    const int64_t r = c * 64 + lane;
+    const uint32_t s = r < in.n_rows ? row_slot[r] : kNoSlot;
+    const uint32_t part = s != kNoSlot ? s >> SB : kNoSlot;
+    int64_t pos = -1;
+    uint64_t todo = __ballot(s != kNoSlot);
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
+      const uint64_t same = __ballot(part == p0) & todo;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&cur[p0], (uint32_t)__popcll(same));
+      base = __builtin_amdgcn_readlane(base, leader);
+      if ((same >> lane) & 1ull) pos = off[p0] + base + __popcll(same & lanes_lt(lane));
+      todo &= ~same;
+    }
+    if (pos >= 0) {
+      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+      load_payload<W>(in, r, status, mk, iv, fv);
+      rec_slot[pos] = s & lmask;
+#pragma unroll
+      for (int w = 0; w < W; ++w) rec_mk[w * cap + pos] = mk[w];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < in.n_icols) rec_iv[k * cap + pos] = iv[k];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < in.n_fcols) rec_fv[k * cap + pos] = fv[k];
+    }
+  }
+}
+
+// 3'. deterministic scatter: the chunks of the routing, in the same order;
+// a row's position is its partition's offset plus the rows before it.
+template <int W>
+__global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *status, const uint32_t *row_slot,
+                                                        const int64_t *off, uint32_t *mat, int64_t n_parts, int SB,
+                                                        int64_t n_waves, int64_t cap, uint32_t *rec_slot,
+                                                        uint64_t *rec_mk, uint64_t *rec_iv, uint64_t *rec_fv) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (w >= n_waves) return;
+  const int64_t n_chunks = (in.n_rows + 63) >> 6, cpw = (n_chunks + n_waves - 1) / n_waves;
+  uint32_t *row = mat + w * n_parts;
+  const uint32_t lmask = (1u << SB) - 1u;
+  for (int64_t c = w * cpw; c < min(n_chunks, (w + 1) * cpw); ++c) {
+    const int64_t r = c * 64 + lane;
+    const uint32_t s = r < in.n_rows ? row_slot[r] : kNoSlot;
+    const uint32_t part = s != kNoSlot ? s >> SB : kNoSlot;
+    int64_t pos = -1;
+    uint64_t todo = __ballot(s != kNoSlot);
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
+      const uint64_t same = __ballot(part == p0) & todo;
+      uint32_t base = 0;
+      if (lane == leader) {
+        base = row[p0];
+        row[p0] = base + (uint32_t)__popcll(same);
+      }
+      base = __builtin_amdgcn_readlane(base, leader);
+      if ((same >> lane) & 1ull) pos = off[p0] + base + __popcll(same & lanes_lt(lane));
+      todo &= ~same;
+    }
+    if (pos >= 0) {
+      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+      load_payload<W>(in, r, status, mk, iv, fv);
+      rec_slot[pos] = s & lmask;
+#pragma unroll
+      for (int k = 0; k < W; ++k) rec_mk[k * cap + pos] = mk[k];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < in.n_icols) rec_iv[k * cap + pos] = iv[k];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < in.n_fcols) rec_fv[k * cap + pos] = fv[k];
+    }
+  }
+}
+
+// 4. per-partition aggregation in LDS
+template <int W>
+__global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, int ni, int nf, int64_t n_slots, int SB,
+                                                      int64_t slot_words, int64_t cap, const uint32_t *rec_slot,
+                                                      const uint64_t *rec_mk, const uint64_t *rec_iv,
+                                                      const uint64_t *rec_fv, const PartItem *items,
+                                                      int64_t *meta) {
+  extern __shared__ uint64_t lds[];
+  __shared__ int64_t s_item;
+  constexpr int m = 64 * W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int A = 1 + ni + nf;
+  const int64_t words = slot_words << SB;
+  const int64_t n_items = meta[0];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd((unsigned long long *)&meta[1], 1ull);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= n_items) break;  // the same value in every thread: every wave leaves
+    const PartItem item = items[it];
+    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0;
+    __syncthreads();
+    for (int64_t b = item.begin + 64 * wave; b < item.end; b += 64 * waves) {
+      const int64_t r = b + lane;
+      const bool live = r < item.end;
+      const int64_t rr_idx = live ? r : item.begin;
+      const uint32_t ls = rec_slot[rr_idx];
+      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+#pragma unroll
+      for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + rr_idx];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < ni) iv[k] = rec_iv[k * cap + rr_idx];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < nf) fv[k] = rec_fv[k * cap + rr_idx];
+      uint64_t todo = __ballot(live);
+      while (todo) {
+        const int rr = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const uint32_t sl = __builtin_amdgcn_readlane(ls, rr);
+        uint64_t *base = lds + (int64_t)sl * slot_words;
+        if (lane == 0) __hip_atomic_fetch_add(&base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        uint64_t rv[kMaxCols], rf[kMaxCols];
+#pragma unroll
+        for (int k = 0; k < kMaxCols; ++k) {
+          if (k < ni) rv[k] = readlane_u64(iv[k], rr);
+          if (k < nf) rf[k] = readlane_u64(fv[k], rr);
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint64_t word = readlane_u64(mk[w], rr);
+          const int j = w * 64 + lane;
+          if ((word >> lane) & 1ull) {
+            __hip_atomic_fetch_add(&base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+            for (int k = 0; k < kMaxCols; ++k)
+              if (k < ni)
+                __hip_atomic_fetch_add(&base[(int64_t)(1 + k) * m + j], rv[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+            for (int k = 0; k < kMaxCols; ++k)
+              if (k < nf)
+                __hip_atomic_fetch_add((double *)&base[(int64_t)(1 + ni + k) * m + j],
+                                       __longlong_as_double((long long)rf[k]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // non-zero counters of this partition -> global state
+    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) {
+      const uint64_t v = lds[i];
+      if (!v) continue;
+      const int64_t g = (item.part << SB) + i / slot_words, o = i % slot_words;
+      if (g >= n_slots) continue;
+      if (o == (int64_t)A * m) {
+        atomicAdd((unsigned long long *)&st.nrows[g], (unsigned long long)v);
+        continue;
+      }
+      const int a = (int)(o / m), j = (int)(o % m);
+      if (a == 0)
+        atomicAdd((unsigned long long *)&st.count[g * m + j], (unsigned long long)v);
+      else if (a <= ni)
+        atomicAdd((unsigned long long *)&st.isum[(g * ni + (a - 1)) * m + j], (unsigned long long)v);
+      else
+        atomicAdd(&st.fsum[(g * nf + (a - 1 - ni)) * m + j], __longlong_as_double((long long)v));
+    }
+  }
+}
+
+// 4'. deterministic per-partition aggregation (float columns): wave w sums the
+// w-th quarter of the partition's records, in record order, into its own LDS
+// region (lane = world: no two lanes touch one word); the regions are then
+// combined in wave order and the owning workgroup adds them to the state.
+template <int W>
+__global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
+    DevState st, int ni, int nf, int64_t n_slots, int SB, int64_t slot_words, int64_t cap, const uint32_t *rec_slot,
+    const uint64_t *rec_mk, const uint64_t *rec_iv, const uint64_t *rec_fv, const PartItem *items, int64_t *meta) {
+  extern __shared__ uint64_t lds[];
+  __shared__ int64_t s_item;
+  constexpr int m = 64 * W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int A = 1 + ni + nf;
+  const int64_t words = slot_words << SB;
+  uint64_t *mine = lds + (int64_t)wave * words;
+  const int64_t n_items = meta[0];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd((unsigned long long *)&meta[1], 1ull);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= n_items) break;
+    const PartItem item = items[it];
+    for (int64_t i = threadIdx.x; i < words * kPartWaves; i += blockDim.x) lds[i] = 0;
+    __syncthreads();
+    const int64_t n = item.end - item.begin, q = (n + kPartWaves - 1) / kPartWaves;
+    const int64_t b0 = item.begin + q * wave, b1 = min(item.end, b0 + q);
+    for (int64_t b = b0; b < b1; b += 64) {
+      const int64_t r = b + lane;
+      const bool live = r < b1;
+      const int64_t ri = live ? r : b0;
+      const uint32_t ls = rec_slot[ri];
+      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+#pragma unroll
+      for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + ri];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < ni) iv[k] = rec_iv[k * cap + ri];
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < nf) fv[k] = rec_fv[k * cap + ri];
+      uint64_t todo = __ballot(live);
+      while (todo) {  // records in order
+        const int rr = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        uint64_t *base = mine + (int64_t)__builtin_amdgcn_readlane(ls, rr) * slot_words;
+        if (lane == 0) base[(int64_t)A * m] += 1;
+        uint64_t rv[kMaxCols], rf[kMaxCols];
+#pragma unroll
+        for (int k = 0; k < kMaxCols; ++k) {
+          if (k < ni) rv[k] = readlane_u64(iv[k], rr);
+          if (k < nf) rf[k] = readlane_u64(fv[k], rr);
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint64_t word = readlane_u64(mk[w], rr);
+          const int j = w * 64 + lane;
+          if ((word >> lane) & 1ull) {
+            base[j] += 1;
+#pragma unroll
+            for (int k = 0; k < kMaxCols; ++k)
+              if (k < ni) base[(int64_t)(1 + k) * m + j] += rv[k];
+#pragma unroll
+            for (int k = 0; k < kMaxCols; ++k)
+              if (k < nf) {
+                double *d = (double *)&base[(int64_t)(1 + ni + k) * m + j];
+                *d += __longlong_as_double((long long)rf[k]);
+              }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) {
+      const int64_t g = (item.part << SB) + i / slot_words, o = i % slot_words;
+      if (g >= n_slots) continue;
+      const int a = o == (int64_t)A * m ? -1 : (int)(o / m), j = (int)(o % m);
+      if (a < 0 || a <= ni) {  // integers: any order
+        uint64_t v = 0;
+        for (int w = 0; w < kPartWaves; ++w) v += lds[(int64_t)w * words + i];
+        if (!v) continue;
+        unsigned long long *dst = a < 0   ? (unsigned long long *)&st.nrows[g]
+                                  : a == 0 ? (unsigned long long *)&st.count[g * m + j]
+                                           : (unsigned long long *)&st.isum[(g * ni + (a - 1)) * m + j];
+        *dst += v;  // this workgroup owns the partition
+      } else {
+        double v = 0.0;
+        for (int w = 0; w < kPartWaves; ++w) v += __longlong_as_double((long long)lds[(int64_t)w * words + i]);
+        st.fsum[(g * nf + (a - 1 - ni)) * m + j] += v;
+      }
+    }
+  }
+}
+
+hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
+                           size_t scratch_bytes) {
+  if (in.n_rows <= 0) return hipSuccess;
+  PartPlan p;
+  if (!part_plan(in, &p) || scratch_bytes < p.total) return hipErrorInvalidValue;
+  uint8_t *base = (uint8_t *)scratch;
+  uint32_t *row_slot = (uint32_t *)(base + p.off_row_slot);
+  uint32_t *count = (uint32_t *)(base + p.off_count);
+  int64_t *off = (int64_t *)(base + p.off_off);
+  uint32_t *cur = (uint32_t *)(base + p.off_cur);
+  PartItem *items = (PartItem *)(base + p.off_items);
+  int64_t *meta = (int64_t *)(base + p.off_meta);
+  uint32_t *rec_slot = (uint32_t *)(base + p.off_rec_slot);
+  uint64_t *rec_mk = (uint64_t *)(base + p.off_rec_mk);
+  uint64_t *rec_iv = (uint64_t *)(base + p.off_rec_iv);
+  uint64_t *rec_fv = (uint64_t *)(base + p.off_rec_fv);
+
+  const int64_t n_chunks = (in.n_rows + 63) / 64;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n_chunks + 3) / 4, (int64_t)env.n_cu * 8));
+  hipError_t e;
+  if (p.det) {
+    uint32_t *mat = (uint32_t *)(base + p.off_mat);
+    const int64_t mat_words = p.n_waves * p.n_parts;
+    if ((e = launch_fill_i64(env, (int64_t *)mat, (mat_words + 1) / 2, 0)) != hipSuccess) return e;
+    const int wgrid = (int)((p.n_waves + 3) / 4);
+    hipLaunchKernelGGL(part_route_det, dim3(wgrid), dim3(256), 0, env.stream, in, st, env.status, row_slot, mat,
+                       p.n_parts, p.SB, p.n_waves);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(part_colscan, dim3((unsigned)((p.n_parts + 255) / 256)), dim3(256), 0, env.stream, mat,
+                       p.n_parts, p.n_waves, count);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, count, p.n_parts, p.chunk, off, cur, items,
+                       meta);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (in.W == 1)
+      hipLaunchKernelGGL(part_scatter_det<1>, dim3(wgrid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
+                         mat, p.n_parts, p.SB, p.n_waves, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+    else
+      hipLaunchKernelGGL(part_scatter_det<2>, dim3(wgrid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
+                         mat, p.n_parts, p.SB, p.n_waves, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+  } else {
+    if ((e = launch_fill_i64(env, (int64_t *)count, (p.n_parts + 1) / 2, 0)) != hipSuccess)  // u32 counts in pairs
+      return e;
+    hipLaunchKernelGGL(part_route, dim3(grid), dim3(256), 0, env.stream, in, st, env.status, row_slot, count, p.SB);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, count, p.n_parts, p.chunk, off, cur, items,
+                       meta);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (in.W == 1)
+      hipLaunchKernelGGL(part_scatter<1>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off, cur,
+                         p.SB, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+    else
+      hipLaunchKernelGGL(part_scatter<2>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off, cur,
+                         p.SB, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const void *fn = p.det ? (in.W == 1 ? (const void *)part_aggregate_det<1> : (const void *)part_aggregate_det<2>)
+                         : (in.W == 1 ? (const void *)part_aggregate<1> : (const void *)part_aggregate<2>);
+  if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes)) != hipSuccess) return e;
+  int per_cu = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kPartWaves, p.lds_bytes)) != hipSuccess)
+    return e;
+  const int agg_grid = std::max(1, env.n_cu * std::max(1, per_cu));
+  if (p.det) {
+    if (in.W == 1)
+      hipLaunchKernelGGL(part_aggregate_det<1>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes,
+                         env.stream, st, in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot,
+                         rec_mk, rec_iv, rec_fv, items, meta);
+    else
+      hipLaunchKernelGGL(part_aggregate_det<2>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes,
+                         env.stream, st, in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot,
+                         rec_mk, rec_iv, rec_fv, items, meta);
+    return hipGetLastError();
+  }
+  if (in.W == 1)
+    hipLaunchKernelGGL(part_aggregate<1>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st,
+                       in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv,
+                       rec_fv, items, meta);
+  else
+    hipLaunchKernelGGL(part_aggregate<2>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st,
+                       in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv,
+                       rec_fv, items, meta);
+  return hipGetLastError();
+}
+
+}  // namespace pac

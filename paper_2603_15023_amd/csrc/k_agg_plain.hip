@@ -20,37 +20,6 @@
 
 namespace pac {
 
-__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Loads row r of a chunk: group (or -1), PU words and values.
-template <int W>
-__device__ __forceinline__ int64_t load_row(const DevInput &in, const DevState &st, int64_t r, uint32_t *status,
-                                            uint64_t (&mk)[W], uint64_t (&iv)[kMaxCols], uint64_t (&fv)[kMaxCols]) {
-  int64_t g = -1;
-#pragma unroll
-  for (int w = 0; w < W; ++w) mk[w] = 0;
-  if (r < in.n_rows) {
-    g = row_group(in, st, r, status);
-    int64_t idx = 0;
-    if (g >= 0 && !chain_index(in, r, &idx, status)) g = -1;
-    if (g >= 0) {
-#pragma unroll
-      for (int w = 0; w < W; ++w) mk[w] = pu_of_index(in, idx, w);
-#pragma unroll
-      for (int c = 0; c < kMaxCols; ++c)
-        if (c < in.n_icols) iv[c] = (uint64_t)load_icol(in.icols[c], in.icol_type[c], r);
-#pragma unroll
-      for (int c = 0; c < kMaxCols; ++c)
-        if (c < in.n_fcols) fv[c] = (uint64_t)__double_as_longlong(load_fcol(in.fcols[c], in.fcol_type[c], r));
-    }
-  }
-  return g;
-}
-
 template <int W>
 __global__ __launch_bounds__(256) void agg_plain_lds(DevInput in, DevState st, uint32_t *status, double *fpart,
                                                      int waves_per_block) {
@@ -217,6 +186,8 @@ static PlainPlan plain_plan(const LaunchEnv &env, const DevInput &in) {
   }
   return p;
 }
+
+bool plain_fits_lds(const DevInput &in) { return !in.group_keys && plain_region_bytes(in) <= kLdsBudget; }
 
 size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in) {
   const PlainPlan p = plain_plan(env, in);

@@ -188,6 +188,8 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
 }
 
 uint32_t choose_algo(const pac::DevInput &d) {
+  // counters that do not fit in LDS (many groups, sparse keys): partition the rows by group
+  if (!pac::plain_fits_lds(d) && pac::part_supported(d) && d.n_rows >= 4096) return PAC_ALGO_PARTITION;
   if (d.group_keys || d.n_fcols > 0) return PAC_ALGO_PLAIN;
   int64_t bits = 1;
   for (int c = 0; c < d.n_icols; ++c) bits += d.icol_bits[c];
@@ -239,6 +241,14 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
                                          "groups x (digits+1) within the tile");
       e = pac::star_supported(d) ? pac::launch_agg_star(env, d, ds) : pac::launch_agg_mfma(env, d, ds);
       break;
+    case PAC_ALGO_PARTITION: {
+      if (!pac::part_supported(d))
+        return fail(PAC_ERR_UNSUPPORTED, "partitioned form needs < 2^31 rows and one group's counters within LDS");
+      rc = ensure_scratch(ctx, pac::part_scratch_bytes(d));
+      if (rc != PAC_OK) return rc;
+      e = pac::launch_agg_part(env, d, ds, ctx->scratch, ctx->scratch_bytes);
+      break;
+    }
     default:
       return fail(PAC_ERR_INVALID, "unknown algorithm %u", algo);
   }
@@ -293,6 +303,12 @@ int pac_ctx_destroy(pac_ctx *ctx) {
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   delete ctx;
   return PAC_OK;
+}
+
+int pac_ctx_reserve(pac_ctx *ctx, size_t bytes) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  DeviceGuard guard(ctx->device);
+  return ensure_scratch(ctx, bytes);
 }
 
 int pac_check(pac_ctx *ctx, void *stream, uint32_t *status) {

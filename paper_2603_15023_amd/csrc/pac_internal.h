@@ -184,6 +184,54 @@ __device__ __forceinline__ int64_t row_group(const DevInput &in, const DevState 
   return g;
 }
 
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Loads row r: group (or -1), PU words and values.
+template <int W>
+__device__ __forceinline__ int64_t load_row(const DevInput &in, const DevState &st, int64_t r, uint32_t *status,
+                                            uint64_t (&mk)[W], uint64_t (&iv)[kMaxCols], uint64_t (&fv)[kMaxCols]) {
+  int64_t g = -1;
+#pragma unroll
+  for (int w = 0; w < W; ++w) mk[w] = 0;
+  if (r < in.n_rows) {
+    g = row_group(in, st, r, status);
+    int64_t idx = 0;
+    if (g >= 0 && !chain_index(in, r, &idx, status)) g = -1;
+    if (g >= 0) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) mk[w] = pu_of_index(in, idx, w);
+#pragma unroll
+      for (int c = 0; c < kMaxCols; ++c)
+        if (c < in.n_icols) iv[c] = (uint64_t)load_icol(in.icols[c], in.icol_type[c], r);
+#pragma unroll
+      for (int c = 0; c < kMaxCols; ++c)
+        if (c < in.n_fcols) fv[c] = (uint64_t)__double_as_longlong(load_fcol(in.fcols[c], in.fcol_type[c], r));
+    }
+  }
+  return g;
+}
+
+// PU words and values of row r after its FK chain; false (status bit set) if a link is out of range.
+template <int W>
+__device__ __forceinline__ bool load_payload(const DevInput &in, int64_t r, uint32_t *status, uint64_t (&mk)[W],
+                                             uint64_t (&iv)[kMaxCols], uint64_t (&fv)[kMaxCols]) {
+  int64_t idx = 0;
+  if (!chain_index(in, r, &idx, status)) return false;
+#pragma unroll
+  for (int w = 0; w < W; ++w) mk[w] = pu_of_index(in, idx, w);
+#pragma unroll
+  for (int c = 0; c < kMaxCols; ++c)
+    if (c < in.n_icols) iv[c] = (uint64_t)load_icol(in.icols[c], in.icol_type[c], r);
+#pragma unroll
+  for (int c = 0; c < kMaxCols; ++c)
+    if (c < in.n_fcols) fv[c] = (uint64_t)__double_as_longlong(load_fcol(in.fcols[c], in.fcol_type[c], r));
+  return true;
+}
+
 // ---------------------------------------------------------------- launch helpers (host)
 struct LaunchEnv {
   hipStream_t stream;
@@ -203,6 +251,11 @@ bool ballot_supported(const DevInput &in);
 hipError_t launch_agg_mfma(const LaunchEnv &env, const DevInput &in, const DevState &st);
 bool mfma_supported(const DevInput &in);
 hipError_t launch_agg_star(const LaunchEnv &env, const DevInput &in, const DevState &st);
+hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
+                           size_t scratch_bytes);
+bool part_supported(const DevInput &in);
+size_t part_scratch_bytes(const DevInput &in);
+bool plain_fits_lds(const DevInput &in);
 bool star_supported(const DevInput &in);
 
 struct FinParams {

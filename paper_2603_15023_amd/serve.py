@@ -141,19 +141,46 @@ class QueryResult:
 
 
 class _Slot:
-    def __init__(self, device_index: int, n_pu: int, m: int):
+    """One query in flight: its own context (scratch, status word), stream, PU words and pinned result area."""
+
+    def __init__(self, device_index: int, n_pu: int, m: int, max_cells: int):
+        dev = torch.device("cuda", device_index)
         self.ctx = Context(device_index)
-        self.stream = torch.cuda.Stream()  # default priority
-        self.masks = torch.empty((n_pu, m // 64), dtype=torch.int64, device=torch.device("cuda", device_index))
+        self.ctx.reserve(256 << 20)  # no scratch growth (a device-wide synchronisation) while serving
+        self.stream = torch.cuda.Stream(device=dev)  # default priority
+        self.masks = torch.empty((n_pu, m // 64), dtype=torch.int64, device=dev)
+        self.max_cells = max_cells
+        self.h_vals = torch.empty(max_cells, dtype=torch.float64, pin_memory=True)
+        self.h_null = torch.empty(max_cells, dtype=torch.uint8, pin_memory=True)
+        self.h_flags = torch.empty(max_cells, dtype=torch.int32, pin_memory=True)
+
+
+def device_cells(q, device) -> torch.Tensor:
+    """query_cells(q) built on the device (pac_cell layout: int64 group, int32 kind, int32 col).
+
+    Only device fills on the current stream: no host-to-device copy, which
+    would make the host wait for the stream."""
+    kinds = query_cells(gen_single_group(q))
+    per = torch.empty(len(kinds), dtype=torch.int64, device=device)
+    for i, c in enumerate(kinds):
+        per[i] = int(c["kind"]) | (int(c["col"]) << 32)
+    G = q.n_groups
+    groups = torch.arange(G, dtype=torch.int64, device=device).repeat_interleave(per.numel())
+    return torch.stack([groups, per.repeat(G)], dim=1).contiguous().view(torch.uint8).view(-1)
+
+
+def gen_single_group(q):
+    """The query restricted to one group (its per-group cell pattern)."""
+    return dataclasses.replace(q, n_groups=1)
 
 
 class Server:
     """Continuous-batching query server over one resident table on one GPU."""
 
     def __init__(self, table: ResidentStar, n_slots: int = 4, pool_bytes: int = 8 << 30, m: int = 64,
-                 mi_budget: float = 1.0 / 128, device_index: int = 0):
+                 mi_budget: float = 1.0 / 128, device_index: int = 0, max_cells: int = 300_000):
         self.table, self.m, self.budget = table, m, mi_budget
-        self.slots = [_Slot(device_index, table.pu_key.shape[0], m) for _ in range(n_slots)]
+        self.slots = [_Slot(device_index, table.pu_key.shape[0], m, max_cells) for _ in range(n_slots)]
         self.n_slots, self.pool_bytes = n_slots, pool_bytes
 
     def _launch(self, slot: _Slot, q):
@@ -163,11 +190,13 @@ class Server:
             spec = query_spec(self.table, q, slot.masks)
             state = new_state(spec, self.m)
             pac_group_aggregate(slot.ctx, spec, state, m=self.m, query_key=q.query_key, algo="auto", stream=s)
-            cells = query_cells(q)
-            cells_d = torch.from_numpy(cells.view(np.uint8)).to(slot.masks.device)
-            vals, nulls, flags, _, _ = pac_finalize(slot.ctx, state, cells_d, len(cells), m=self.m,
+            n_cells = q.n_groups * len(q.aggs)
+            if n_cells > slot.max_cells:
+                raise ValueError(f"query {q.qid} releases {n_cells} cells, a slot holds {slot.max_cells}")
+            cells_d = device_cells(q, slot.masks.device)
+            vals, nulls, flags, _, _ = pac_finalize(slot.ctx, state, cells_d, n_cells, m=self.m,
                                                     mi_budget=self.budget, noise_seed=q.noise_seed, stream=s)
-            host = tuple(torch.empty(x.shape, dtype=x.dtype, pin_memory=True) for x in (vals, nulls, flags))
+            host = (slot.h_vals[:n_cells], slot.h_null[:n_cells], slot.h_flags[:n_cells])
             for h, x in zip(host, (vals, nulls, flags)):
                 h.copy_(x, non_blocking=True)
             ev = torch.cuda.Event()

@@ -17,7 +17,7 @@ from cases import compare_counters, gpu_star, star_definition, star_oracle
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = ["plain", "ballot", "mfma"]
+ALGOS = ["plain", "ballot", "mfma"]  # dense few-group forms
 
 
 def _say(*a):
@@ -340,6 +340,66 @@ def test_sparse_group_keys(ctx, torch_mod):
     want = ON.onepass(t.n_rows, 64, pu_keys=t.pu_key, query_key=K, group_keys=t.group_keys, n_groups=4000,
                       int_cols=[t.cols["v"]])
     assert np.array_equal(slot_keys[used][order], want["keys"])
+    compare_counters(got, want)
+
+
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("algo", ["partition", "plain"])
+def test_many_groups_partitioned(ctx, torch_mod, m, algo):
+    """3000 groups (a group-source column modulo G), filter, int and float columns:
+    counters far beyond LDS, partitioned form against the global-atomic plain form
+    and the oracle; ragged row count."""
+    import paper_2603_15023_amd as P
+    t = gen.tiny_star(51, n_pu=2000, n_orders=20_000, n_rows=200_003, gcards=(3,), n_cols=2,
+                      value_range=(-10**9, 10**9), with_sel=True, float_cols=1)
+    gsrc = np.random.default_rng(5).integers(0, 100_000, size=t.n_rows, dtype=np.uint32)
+    G, lt, K = 3000, 3 << 30, 0x9A9A
+    dev = torch_mod.device("cuda")
+    masks = P.pac_hash_mask(ctx, torch_mod.from_numpy(t.pu_key).to(dev), K, m)
+    names = ["v0", "v1", "f0"]
+    spec = P.AggSpec(n_rows=t.n_rows, masks=masks,
+                     links=[torch_mod.from_numpy(t.f_order).to(dev), torch_mod.from_numpy(t.o_pu).to(dev)],
+                     gcols=[torch_mod.from_numpy(gsrc.view(np.int32)).to(dev)], gcards=[100_000], group_mod=G,
+                     n_groups=G, filter_col=torch_mod.from_numpy(t.sel.view(np.int32)).to(dev), filter_lt=lt,
+                     cols=[torch_mod.from_numpy(t.cols[c]).to(dev) for c in names])
+    st = P.new_state(spec, m)
+    _say("many groups", algo, m)
+    P.pac_group_aggregate(ctx, spec, st, m=m, query_key=K, algo=algo)
+    assert ctx.status() == 0
+    got = {k: v.cpu().numpy() for k, v in st.items()}
+    kw = dict(masks=R.pac_hash_np(t.pu_key, K, m), links=[t.f_order, t.o_pu], gcols=[gsrc], gcards=[100_000],
+              group_mod=G, n_groups=G, filter_col=t.sel, filter_lt=lt, int_cols=[t.cols["v0"], t.cols["v1"]])
+    want = ON.onepass(t.n_rows, m, float_cols=[t.cols["f0"]], **kw)
+    mag = ON.onepass(t.n_rows, m, float_cols=[np.abs(t.cols["f0"])], **kw)["fsum"]
+    # signed float values: the summation order differs between forms, so the
+    # bound is 1e-12 of the sum of magnitudes (ints and counts exact)
+    compare_counters(dict(got, fsum=np.zeros((G, 0, m))), dict(want, fsum=np.zeros((G, 0, m))))
+    assert np.all(np.abs(got["fsum"] - want["fsum"]) <= 1e-12 * mag + 1e-300)
+
+
+def test_partitioned_skewed_sparse_keys(ctx, torch_mod):
+    """Zipf-skewed sparse keys: the head group spans many work items of the partitioned form."""
+    import paper_2603_15023_amd as P
+    g = np.random.default_rng(77)
+    n = 1_000_003
+    rank = gen.zipf_ranks(g, n, 50_000, 1.1)
+    keys = gen.distinct_keys(g, 50_000)[rank]
+    pu = g.integers(1, 40_001, size=n, dtype=np.int64)
+    v = g.integers(-10**12, 10**12, size=n, dtype=np.int64)
+    K = 31
+    dev = torch_mod.device("cuda")
+    spec = P.AggSpec(n_rows=n, pu_keys=torch_mod.from_numpy(pu).to(dev), group_keys=torch_mod.from_numpy(keys).to(dev),
+                     n_groups=1 << 17, cols=[torch_mod.from_numpy(v).to(dev)])
+    st = P.new_state(spec, 64)
+    P.pac_group_aggregate(ctx, spec, st, m=64, query_key=K, algo="partition")
+    assert ctx.status() == 0
+    want = ON.onepass(n, 64, pu_keys=pu, query_key=K, group_keys=keys, n_groups=1 << 16, int_cols=[v])
+    slot_keys = st["slot_keys"].cpu().numpy()
+    used = slot_keys != np.iinfo(np.int64).min
+    order = np.argsort(slot_keys[used])
+    assert np.array_equal(slot_keys[used][order], want["keys"])
+    got = {k: st[k].cpu().numpy()[used][order] for k in ("count", "isum", "nrows")}
+    got["fsum"] = np.zeros((len(order), 0, 64))
     compare_counters(got, want)
 
 
