@@ -34,6 +34,7 @@ struct PartItem {
   int64_t part;
   int64_t begin;
   int64_t end;
+  int64_t exclusive;  // 1: the partition's only work item (its workgroup owns the partition's counters)
 };
 
 struct PartPlan {
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(1024) void part_scan(const uint32_t *count, int64_t
     off[p] = r0;
     cur[p] = 0;
     const int64_t n = count[p];
-    for (int64_t b = 0; b < n; b += chunk) items[i0++] = PartItem{p, r0 + b, r0 + min(n, b + chunk)};
+    for (int64_t b = 0; b < n; b += chunk) items[i0++] = PartItem{p, r0 + b, r0 + min(n, b + chunk), n <= chunk};
     r0 += n;
   }
   if (t == T - 1) {
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
                                                       int64_t slot_words, int64_t cap, const uint32_t *rec_slot,
                                                       const uint64_t *rec_mk, const uint64_t *rec_iv,
                                                       const uint64_t *rec_fv, const PartItem *items,
-                                                      int64_t *meta) {
+                                                      int64_t *meta, int fresh) {
   extern __shared__ uint64_t lds[];
   __shared__ int64_t s_item;
   constexpr int m = 64 * W;
@@ -393,17 +394,22 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
       if (!v) continue;
       const int64_t g = (item.part << SB) + i / slot_words, o = i % slot_words;
       if (g >= n_slots) continue;
-      if (o == (int64_t)A * m) {
-        atomicAdd((unsigned long long *)&st.nrows[g], (unsigned long long)v);
+      const int a = o == (int64_t)A * m ? -1 : (int)(o / m), j = (int)(o % m);
+      if (a > ni) {
+        double *dst = &st.fsum[(g * nf + (a - 1 - ni)) * m + j];
+        if (item.exclusive && fresh)
+          *dst = __longlong_as_double((long long)v);
+        else
+          atomicAdd(dst, __longlong_as_double((long long)v));
         continue;
       }
-      const int a = (int)(o / m), j = (int)(o % m);
-      if (a == 0)
-        atomicAdd((unsigned long long *)&st.count[g * m + j], (unsigned long long)v);
-      else if (a <= ni)
-        atomicAdd((unsigned long long *)&st.isum[(g * ni + (a - 1)) * m + j], (unsigned long long)v);
+      unsigned long long *dst = a < 0   ? (unsigned long long *)&st.nrows[g]
+                                : a == 0 ? (unsigned long long *)&st.count[g * m + j]
+                                         : (unsigned long long *)&st.isum[(g * ni + (a - 1)) * m + j];
+      if (item.exclusive && fresh)
+        *dst = v;  // sole owner of the partition's counters, which start at zero
       else
-        atomicAdd(&st.fsum[(g * nf + (a - 1 - ni)) * m + j], __longlong_as_double((long long)v));
+        atomicAdd(dst, (unsigned long long)v);
     }
   }
 }
@@ -503,7 +509,7 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
 }
 
 hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
-                           size_t scratch_bytes) {
+                           size_t scratch_bytes, bool fresh) {
   if (in.n_rows <= 0) return hipSuccess;
   PartPlan p;
   if (!part_plan(in, &p) || scratch_bytes < p.total) return hipErrorInvalidValue;
@@ -579,11 +585,11 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
   if (in.W == 1)
     hipLaunchKernelGGL(part_aggregate<1>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st,
                        in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv,
-                       rec_fv, items, meta);
+                       rec_fv, items, meta, fresh ? 1 : 0);
   else
     hipLaunchKernelGGL(part_aggregate<2>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st,
                        in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv,
-                       rec_fv, items, meta);
+                       rec_fv, items, meta, fresh ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -246,7 +246,7 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
         return fail(PAC_ERR_UNSUPPORTED, "partitioned form needs < 2^31 rows and one group's counters within LDS");
       rc = ensure_scratch(ctx, pac::part_scratch_bytes(d));
       if (rc != PAC_OK) return rc;
-      e = pac::launch_agg_part(env, d, ds, ctx->scratch, ctx->scratch_bytes);
+      e = pac::launch_agg_part(env, d, ds, ctx->scratch, ctx->scratch_bytes, (flags & PAC_AGG_INIT) != 0);
       break;
     }
     default:

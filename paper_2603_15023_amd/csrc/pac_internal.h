@@ -252,7 +252,7 @@ hipError_t launch_agg_mfma(const LaunchEnv &env, const DevInput &in, const DevSt
 bool mfma_supported(const DevInput &in);
 hipError_t launch_agg_star(const LaunchEnv &env, const DevInput &in, const DevState &st);
 hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
-                           size_t scratch_bytes);
+                           size_t scratch_bytes, bool fresh);
 bool part_supported(const DevInput &in);
 size_t part_scratch_bytes(const DevInput &in);
 bool plain_fits_lds(const DevInput &in);
