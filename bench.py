@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shuffled", action="store_true", help="fact rows in random order instead of by order")
+    ap.add_argument("--serve-queries", type=int, default=64, help="served-workload queries (0: skip serving)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="Poisson arrival rate / saturation throughput")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="also run a plain copy kernel over this many GiB (counter calibration runs)")
     return ap.parse_args()
@@ -192,6 +195,8 @@ def main():
                 "kernel": "agg_star (int8 matrix cores, star-schema form)",
                 "alg_bytes_per_launch": alg_kv if args.algo == "mfma_kv" else alg_bytes}
 
+    serving = serve_measurement(args) if args.serve_queries > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(t, K, args.cpu_seconds)
@@ -223,10 +228,43 @@ def main():
                                          / 1e9 / HBM_PEAK_GBS, 4))
                   for k, v in forms.items()},
         "roofline": roofline,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def serve_measurement(args):
+    """Served workload: a resident 100M-row star schema (2.5M PU, 25M orders, filter, group-source and FP64
+    columns); queries with log-uniform selectivity (0.1%-50%) and group count (1-1e5), 1-3 COUNT/SUM/AVG over
+    int64/FP64 columns, own query key and noise seed.  Closed loop first (all queries at once) for the
+    saturation throughput, then Poisson arrivals at `serve_load` times it; latency = completion - arrival."""
+    import torch
+    from paper_2603_15023_amd.serve import ResidentStar, Server, latency_summary
+    from workloads import gen
+
+    t0 = time.time()
+    t = gen.config5_star()
+    table = ResidentStar.from_table(t)
+    del t
+    torch.cuda.synchronize()
+    log(f"served table ready in {time.time() - t0:.1f}s")
+    qs = gen.config5_queries(args.serve_queries)
+    srv = Server(table, n_slots=args.serve_slots)
+    srv.run(qs[:min(8, len(qs))])  # warm-up
+    closed = latency_summary(srv.run(qs))
+    rate = args.serve_load * closed["qps"]
+    gaps = np.array([q.gap for q in qs]) / rate
+    opened = latency_summary(srv.run(qs, arrivals=np.cumsum(gaps) - gaps[0]))
+    srv.close()
+    log(f"serving: saturation {closed['qps']:.1f} QPS; at {args.serve_load:.1f}x: p50 {opened['p50_ms']:.1f} ms, "
+        f"p99 {opened['p99_ms']:.1f} ms")
+    return {"workload": "served star: 100M fact rows, 2.5M PU, 25M orders; filter 0.1%-50%, 1-1e5 groups, "
+                        "1-3 COUNT/SUM/AVG over int64/FP64, m=64",
+            "queries": len(qs), "slots": args.serve_slots, "saturation_qps": closed["qps"],
+            "load": args.serve_load, "arrival_qps": rate, "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"],
+            "max_ms": opened["max_ms"], "qps": opened["qps"]}
 
 
 def cpu_baseline(t, K, target_s):
