@@ -185,6 +185,68 @@ __global__ __launch_bounds__(256) void part_colscan(uint32_t *mat, int64_t n_par
   count[p] = run;
 }
 
+// 1''. route with a workgroup histogram in LDS (few partitions: the global
+// counters then see one atomic per workgroup and partition).
+constexpr int64_t kLdsParts = 16384;
+
+__global__ __launch_bounds__(256) void part_route_lds(DevInput in, DevState st, uint32_t *status, uint32_t *row_slot,
+                                                      uint32_t *count, int SB, int64_t n_parts) {
+  __shared__ uint32_t hist[kLdsParts];
+  for (int64_t i = threadIdx.x; i < n_parts; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t n = in.n_rows, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    int64_t g = row_group(in, st, r, status);
+    int64_t idx;
+    if (g >= 0 && !chain_index(in, r, &idx, status)) g = -1;
+    row_slot[r] = g >= 0 ? (uint32_t)g : kNoSlot;
+    if (g >= 0) atomicAdd(&hist[g >> SB], 1u);
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n_parts; i += blockDim.x)
+    if (hist[i]) atomicAdd(&count[i], hist[i]);
+}
+
+// 3''. scatter with per-workgroup range reservation: count this workgroup's
+// rows per partition, reserve one range per partition, then place the rows.
+template <int W>
+__global__ __launch_bounds__(256) void part_scatter_lds(DevInput in, uint32_t *status, const uint32_t *row_slot,
+                                                        const int64_t *off, uint32_t *cur, int SB, int64_t n_parts,
+                                                        int64_t cap, uint32_t *rec_slot, uint64_t *rec_mk,
+                                                        uint64_t *rec_iv, uint64_t *rec_fv) {
+  __shared__ uint32_t at[kLdsParts];
+  for (int64_t i = threadIdx.x; i < n_parts; i += blockDim.x) at[i] = 0;
+  __syncthreads();
+  const int64_t n = in.n_rows, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t r = r0; r < n; r += stride) {
+    const uint32_t s = row_slot[r];
+    if (s != kNoSlot) atomicAdd(&at[s >> SB], 1u);
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n_parts; i += blockDim.x)
+    if (at[i]) at[i] = atomicAdd(&cur[i], at[i]);  // start of this workgroup's range
+  __syncthreads();
+  const uint32_t lmask = (1u << SB) - 1u;
+  for (int64_t r = r0; r < n; r += stride) {
+    const uint32_t s = row_slot[r];
+    if (s == kNoSlot) continue;
+    const uint32_t p = s >> SB;
+    const int64_t pos = off[p] + atomicAdd(&at[p], 1u);
+    uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+    load_payload<W>(in, r, status, mk, iv, fv);
+    rec_slot[pos] = s & lmask;
+#pragma unroll
+    for (int k = 0; k < W; ++k) rec_mk[k * cap + pos] = mk[k];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k)
+      if (k < in.n_icols) rec_iv[k * cap + pos] = iv[k];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k)
+      if (k < in.n_fcols) rec_fv[k * cap + pos] = fv[k];
+  }
+}
+
 // 2. offsets and work items (one workgroup; each thread scans a contiguous run of partitions)
 __global__ __launch_bounds__(1024) void part_scan(const uint32_t *count, int64_t n_parts, int64_t chunk,
                                                   int64_t *off, uint32_t *cur, PartItem *items, int64_t *meta) {
@@ -551,12 +613,24 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
   } else {
     if ((e = launch_fill_i64(env, (int64_t *)count, (p.n_parts + 1) / 2, 0)) != hipSuccess)  // u32 counts in pairs
       return e;
-    hipLaunchKernelGGL(part_route, dim3(grid), dim3(256), 0, env.stream, in, st, env.status, row_slot, count, p.SB);
+    const bool few = p.n_parts <= kLdsParts;  // workgroup histograms and range reservations in LDS
+    if (few)
+      hipLaunchKernelGGL(part_route_lds, dim3(grid), dim3(256), 0, env.stream, in, st, env.status, row_slot, count,
+                         p.SB, p.n_parts);
+    else
+      hipLaunchKernelGGL(part_route, dim3(grid), dim3(256), 0, env.stream, in, st, env.status, row_slot, count,
+                         p.SB);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, count, p.n_parts, p.chunk, off, cur, items,
                        meta);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (in.W == 1)
+    if (few && in.W == 1)
+      hipLaunchKernelGGL(part_scatter_lds<1>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
+                         cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+    else if (few)
+      hipLaunchKernelGGL(part_scatter_lds<2>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
+                         cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+    else if (in.W == 1)
       hipLaunchKernelGGL(part_scatter<1>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off, cur,
                          p.SB, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
     else
