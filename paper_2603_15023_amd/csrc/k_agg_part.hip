@@ -19,10 +19,11 @@
 // Counter semantics are those of every other form (per-world COUNT, exact
 // int64 SUM, FP64 SUM, row count per group).  Integer counters are exact in
 // any order, so without float columns a partition is split into chunks and
-// merged with atomics.  With float columns the form is deterministic: one
-// workgroup owns each partition, each of its waves sums a fixed quarter of the
-// records into a private LDS region, the regions are combined in wave order
-// and the owner adds the result to the state without atomics.
+// merged with atomics.  With float columns the form is deterministic: records
+// reach their partition in row order (per-wave counts, no atomic cursors),
+// each work item's waves sum fixed quarters of its records into private LDS
+// regions combined in wave order, and the items of a partition are added in
+// item order by one thread per counter word.
 #include <algorithm>
 #include <initializer_list>
 
@@ -49,6 +50,8 @@ struct PartPlan {
   int64_t max_items;
   int64_t n_waves;      // deterministic routing: waves, each with a fixed contiguous row range
   size_t off_mat;       // deterministic routing: per-wave partition counts [n_waves][n_parts]
+  size_t off_partial;   // deterministic: each work item's counters [max_items][2^SB * slot_words]
+  size_t off_pfirst;    // deterministic: first work item and item count of each partition
   size_t off_row_slot, off_count, off_off, off_cur, off_items, off_meta, off_rec_slot, off_rec_mk, off_rec_iv,
       off_rec_fv, total;
 };
@@ -76,15 +79,19 @@ static bool part_plan(const DevInput &in, PartPlan *pl) {
   p.lds_bytes = (int)(((int64_t)1 << SB) * per_slot);
   p.n_parts = (p.n_slots + ((int64_t)1 << SB) - 1) >> SB;
   p.cap = in.n_rows;
-  p.chunk = p.det ? p.cap : 16384;  // deterministic: one work item per partition
+  p.chunk = 16384;
   p.max_items = p.n_parts + p.cap / p.chunk + 1;
   if (p.det) {  // records land in row order: per-wave counts instead of atomic cursors
     const int64_t n_chunks = (in.n_rows + 63) / 64;
-    p.n_waves = std::max<int64_t>(1, std::min<int64_t>({(int64_t)2048, n_chunks, ((int64_t)64 << 20) / p.n_parts}));
+    p.n_waves = std::max<int64_t>(1, std::min<int64_t>({(int64_t)32768, n_chunks, ((int64_t)16 << 20) / p.n_parts}));
   }
   size_t o = 0;
   p.off_mat = o;
   if (p.det) o = align256(o + 4 * (size_t)p.n_waves * p.n_parts);
+  p.off_partial = o;
+  if (p.det) o = align256(o + 8 * (size_t)p.max_items * ((size_t)p.slot_words << p.SB));
+  p.off_pfirst = o;
+  if (p.det) o = align256(o + 16 * (size_t)p.n_parts);
   p.off_row_slot = o; o = align256(o + 4 * (size_t)p.cap);
   p.off_count = o;    o = align256(o + 4 * (size_t)p.n_parts);
   p.off_off = o;      o = align256(o + 8 * (size_t)(p.n_parts + 1));
@@ -141,7 +148,7 @@ __global__ __launch_bounds__(256) void part_route(DevInput in, DevState st, uint
 }
 
 // 1'. deterministic routing: wave w takes the contiguous chunks [w*cpw, (w+1)*cpw)
-// in order and counts its rows per partition in its own row of `mat`.
+// in order and counts its rows per partition in its own entry mat[part][w].
 __global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, uint32_t *status,
                                                       uint32_t *row_slot, uint32_t *mat, int64_t n_parts, int SB,
                                                       int64_t n_waves) {
@@ -149,7 +156,6 @@ __global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, 
   const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_waves) return;
   const int64_t n_chunks = (in.n_rows + 63) >> 6, cpw = (n_chunks + n_waves - 1) / n_waves;
-  uint32_t *row = mat + w * n_parts;
   for (int64_t c = w * cpw; c < min(n_chunks, (w + 1) * cpw); ++c) {
     const int64_t r = c * 64 + lane;
     int64_t g = -1;
@@ -165,24 +171,38 @@ __global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, 
       const int leader = __ffsll((unsigned long long)todo) - 1;
       const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
       const uint64_t same = __ballot(part == p0) & todo;
-      if (lane == leader) row[p0] += (uint32_t)__popcll(same);  // only this wave writes its row
+      if (lane == leader) mat[(int64_t)p0 * n_waves + w] += (uint32_t)__popcll(same);  // only this wave writes it
       todo &= ~same;
     }
   }
 }
 
-// Per partition: exclusive prefix of the per-wave counts (in wave order) and the total.
+// Per partition (one workgroup each): exclusive prefix of the per-wave counts
+// mat[part][0..n_waves) in wave order, and the partition's total.
 __global__ __launch_bounds__(256) void part_colscan(uint32_t *mat, int64_t n_parts, int64_t n_waves,
                                                     uint32_t *count) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_parts) return;
-  uint32_t run = 0;
-  for (int64_t w = 0; w < n_waves; ++w) {
-    const uint32_t c = mat[w * n_parts + p];
-    mat[w * n_parts + p] = run;
+  __shared__ uint32_t sums[256];
+  const int64_t p = blockIdx.x;
+  const int t = threadIdx.x;
+  uint32_t *col = mat + p * n_waves;
+  const int64_t per = (n_waves + 255) / 256, w0 = t * per, w1 = min(n_waves, w0 + per);
+  uint32_t s = 0;
+  for (int64_t w = w0; w < w1; ++w) s += col[w];
+  sums[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    const uint32_t a = t >= d ? sums[t - d] : 0u;
+    __syncthreads();
+    sums[t] += a;
+    __syncthreads();
+  }
+  uint32_t run = sums[t] - s;
+  for (int64_t w = w0; w < w1; ++w) {
+    const uint32_t c = col[w];
+    col[w] = run;
     run += c;
   }
-  count[p] = run;
+  if (t == 255) count[p] = sums[255];
 }
 
 // 1''. route with a workgroup histogram in LDS (few partitions: the global
@@ -249,7 +269,8 @@ __global__ __launch_bounds__(256) void part_scatter_lds(DevInput in, uint32_t *s
 
 // 2. offsets and work items (one workgroup; each thread scans a contiguous run of partitions)
 __global__ __launch_bounds__(1024) void part_scan(const uint32_t *count, int64_t n_parts, int64_t chunk,
-                                                  int64_t *off, uint32_t *cur, PartItem *items, int64_t *meta) {
+                                                  int64_t *off, uint32_t *cur, PartItem *items, int64_t *meta,
+                                                  int64_t *pfirst) {
   __shared__ int64_t s_rows[1024], s_items[1024];
   const int t = threadIdx.x, T = blockDim.x;
   const int64_t per = (n_parts + T - 1) / T;
@@ -278,6 +299,10 @@ __global__ __launch_bounds__(1024) void part_scan(const uint32_t *count, int64_t
     off[p] = r0;
     cur[p] = 0;
     const int64_t n = count[p];
+    if (pfirst) {
+      pfirst[2 * p] = i0;
+      pfirst[2 * p + 1] = (n + chunk - 1) / chunk;
+    }
     for (int64_t b = 0; b < n; b += chunk) items[i0++] = PartItem{p, r0 + b, r0 + min(n, b + chunk), n <= chunk};
     r0 += n;
   }
@@ -341,7 +366,6 @@ __global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *s
   const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_waves) return;
   const int64_t n_chunks = (in.n_rows + 63) >> 6, cpw = (n_chunks + n_waves - 1) / n_waves;
-  uint32_t *row = mat + w * n_parts;
   const uint32_t lmask = (1u << SB) - 1u;
   for (int64_t c = w * cpw; c < min(n_chunks, (w + 1) * cpw); ++c) {
     const int64_t r = c * 64 + lane;
@@ -355,8 +379,9 @@ __global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *s
       const uint64_t same = __ballot(part == p0) & todo;
       uint32_t base = 0;
       if (lane == leader) {
-        base = row[p0];
-        row[p0] = base + (uint32_t)__popcll(same);
+        uint32_t *e = &mat[(int64_t)p0 * n_waves + w];
+        base = *e;
+        *e = base + (uint32_t)__popcll(same);
       }
       base = __builtin_amdgcn_readlane(base, leader);
       if ((same >> lane) & 1ull) pos = off[p0] + base + __popcll(same & lanes_lt(lane));
@@ -483,7 +508,8 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
 template <int W>
 __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
     DevState st, int ni, int nf, int64_t n_slots, int SB, int64_t slot_words, int64_t cap, const uint32_t *rec_slot,
-    const uint64_t *rec_mk, const uint64_t *rec_iv, const uint64_t *rec_fv, const PartItem *items, int64_t *meta) {
+    const uint64_t *rec_mk, const uint64_t *rec_iv, const uint64_t *rec_fv, const PartItem *items, int64_t *meta,
+    uint64_t *partial) {
   extern __shared__ uint64_t lds[];
   __shared__ int64_t s_item;
   constexpr int m = 64 * W;
@@ -549,24 +575,51 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
       }
     }
     __syncthreads();
+    // this work item's counters, the wave regions combined in wave order
+    uint64_t *out = partial + it * words;
     for (int64_t i = threadIdx.x; i < words; i += blockDim.x) {
-      const int64_t g = (item.part << SB) + i / slot_words, o = i % slot_words;
-      if (g >= n_slots) continue;
-      const int a = o == (int64_t)A * m ? -1 : (int)(o / m), j = (int)(o % m);
-      if (a < 0 || a <= ni) {  // integers: any order
+      const int64_t o = i % slot_words;
+      const int a = o == (int64_t)A * m ? -1 : (int)(o / m);
+      if (a < 0 || a <= ni) {
         uint64_t v = 0;
         for (int w = 0; w < kPartWaves; ++w) v += lds[(int64_t)w * words + i];
-        if (!v) continue;
-        unsigned long long *dst = a < 0   ? (unsigned long long *)&st.nrows[g]
-                                  : a == 0 ? (unsigned long long *)&st.count[g * m + j]
-                                           : (unsigned long long *)&st.isum[(g * ni + (a - 1)) * m + j];
-        *dst += v;  // this workgroup owns the partition
+        out[i] = v;
       } else {
         double v = 0.0;
         for (int w = 0; w < kPartWaves; ++w) v += __longlong_as_double((long long)lds[(int64_t)w * words + i]);
-        st.fsum[(g * nf + (a - 1 - ni)) * m + j] += v;
+        out[i] = (uint64_t)__double_as_longlong(v);
       }
     }
+  }
+}
+
+// Deterministic merge: each (partition, counter word) adds its work items'
+// counters in item order and the thread owning the word updates the state.
+__global__ __launch_bounds__(256) void part_reduce_det(DevState st, int ni, int nf, int m, int64_t n_slots, int SB,
+                                                       int64_t slot_words, int64_t n_parts, const int64_t *pfirst,
+                                                       const uint64_t *partial, int fresh) {
+  const int64_t words = slot_words << SB;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_parts * words) return;
+  const int64_t part = t / words, i = t % words;
+  const int64_t first = pfirst[2 * part], n_it = pfirst[2 * part + 1];
+  if (n_it == 0) return;
+  const int64_t g = (part << SB) + i / slot_words, o = i % slot_words;
+  if (g >= n_slots) return;
+  const int A = 1 + ni + nf;
+  const int a = o == (int64_t)A * m ? -1 : (int)(o / m), j = (int)(o % m);
+  if (a < 0 || a <= ni) {
+    uint64_t v = 0;
+    for (int64_t k = 0; k < n_it; ++k) v += partial[(first + k) * words + i];
+    if (!v) return;
+    uint64_t *dst = a < 0 ? (uint64_t *)&st.nrows[g] : a == 0 ? (uint64_t *)&st.count[g * m + j]
+                                                             : (uint64_t *)&st.isum[(g * ni + (a - 1)) * m + j];
+    *dst = fresh ? v : *dst + v;
+  } else {
+    double v = 0.0;
+    for (int64_t k = 0; k < n_it; ++k) v += __longlong_as_double((long long)partial[(first + k) * words + i]);
+    double *dst = &st.fsum[(g * nf + (a - 1 - ni)) * m + j];
+    *dst = fresh ? v : *dst + v;
   }
 }
 
@@ -598,11 +651,11 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
     hipLaunchKernelGGL(part_route_det, dim3(wgrid), dim3(256), 0, env.stream, in, st, env.status, row_slot, mat,
                        p.n_parts, p.SB, p.n_waves);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(part_colscan, dim3((unsigned)((p.n_parts + 255) / 256)), dim3(256), 0, env.stream, mat,
-                       p.n_parts, p.n_waves, count);
+    hipLaunchKernelGGL(part_colscan, dim3((unsigned)p.n_parts), dim3(256), 0, env.stream, mat, p.n_parts, p.n_waves,
+                       count);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, count, p.n_parts, p.chunk, off, cur, items,
-                       meta);
+                       meta, (int64_t *)(base + p.off_pfirst));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (in.W == 1)
       hipLaunchKernelGGL(part_scatter_det<1>, dim3(wgrid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
@@ -622,7 +675,7 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
                          p.SB);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, count, p.n_parts, p.chunk, off, cur, items,
-                       meta);
+                       meta, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (few && in.W == 1)
       hipLaunchKernelGGL(part_scatter_lds<1>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
@@ -646,14 +699,20 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
     return e;
   const int agg_grid = std::max(1, env.n_cu * std::max(1, per_cu));
   if (p.det) {
+    uint64_t *partial = (uint64_t *)(base + p.off_partial);
     if (in.W == 1)
       hipLaunchKernelGGL(part_aggregate_det<1>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes,
                          env.stream, st, in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot,
-                         rec_mk, rec_iv, rec_fv, items, meta);
+                         rec_mk, rec_iv, rec_fv, items, meta, partial);
     else
       hipLaunchKernelGGL(part_aggregate_det<2>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes,
                          env.stream, st, in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot,
-                         rec_mk, rec_iv, rec_fv, items, meta);
+                         rec_mk, rec_iv, rec_fv, items, meta, partial);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t threads = p.n_parts * (p.slot_words << p.SB);
+    hipLaunchKernelGGL(part_reduce_det, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, env.stream, st,
+                       in.n_icols, in.n_fcols, in.m, p.n_slots, p.SB, p.slot_words, p.n_parts,
+                       (const int64_t *)(base + p.off_pfirst), partial, fresh ? 1 : 0);
     return hipGetLastError();
   }
   if (in.W == 1)
