@@ -548,7 +548,7 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
         const int rr = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
         uint64_t *base = mine + (int64_t)__builtin_amdgcn_readlane(ls, rr) * slot_words;
-        if (lane == 0) base[(int64_t)A * m] += 1;
+        if (lane == 0) __hip_atomic_fetch_add(&base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         uint64_t rv[kMaxCols], rf[kMaxCols];
 #pragma unroll
         for (int k = 0; k < kMaxCols; ++k) {
@@ -559,17 +559,19 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
         for (int w = 0; w < W; ++w) {
           const uint64_t word = readlane_u64(mk[w], rr);
           const int j = w * 64 + lane;
-          if ((word >> lane) & 1ull) {
-            base[j] += 1;
+          if ((word >> lane) & 1ull) {  // no-return LDS adds: one wave's adds apply in issue order
+            __hip_atomic_fetch_add(&base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
             for (int k = 0; k < kMaxCols; ++k)
-              if (k < ni) base[(int64_t)(1 + k) * m + j] += rv[k];
+              if (k < ni)
+                __hip_atomic_fetch_add(&base[(int64_t)(1 + k) * m + j], rv[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
             for (int k = 0; k < kMaxCols; ++k)
-              if (k < nf) {
-                double *d = (double *)&base[(int64_t)(1 + ni + k) * m + j];
-                *d += __longlong_as_double((long long)rf[k]);
-              }
+              if (k < nf)
+                __hip_atomic_fetch_add((double *)&base[(int64_t)(1 + ni + k) * m + j],
+                                       __longlong_as_double((long long)rf[k]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
       }

@@ -5,8 +5,9 @@
 // the SIMD lanes are the worlds, each row's PU word is broadcast and lane j
 // adds the row's value into world j's counter when bit j is set.  Counters
 // live in a wave-private LDS region [G][A][m] (A = 1 + ints + floats, plus
-// nrows), so a lane only ever touches its own world column (no atomics, fixed
-// order per wave).  Workgroups flush int counters with int64 global atomics
+// nrows), so a lane only ever touches its own world column; the adds are LDS
+// atomics without a return value (no read-modify-write latency), applied in
+// issue order because one wave owns the region, so FP64 sums keep a fixed order.  Workgroups flush int counters with int64 global atomics
 // and float counters as per-block partials reduced in a fixed order (same
 // bits on every run).  Groups whose counters do not fit in LDS, and sparse
 // group keys (HBM hash table), update the global counters with atomics.
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void agg_plain_lds(DevInput in, DevState st, u
         live &= live - 1;
         const int64_t gg = (int64_t)readlane_u64((uint64_t)g, rr);
         uint64_t *base = my + gg * gstride;
-        if (lane == 0) base[(int64_t)A * m] += 1;
+        if (lane == 0) __hip_atomic_fetch_add(&base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         uint64_t rv[kMaxCols], rf[kMaxCols];
 #pragma unroll
         for (int c = 0; c < kMaxCols; ++c) {
@@ -57,17 +58,19 @@ __global__ __launch_bounds__(256) void agg_plain_lds(DevInput in, DevState st, u
         for (int w = 0; w < W; ++w) {
           const uint64_t word = readlane_u64(mk[w], rr);
           const int j = w * 64 + lane;
-          if ((word >> lane) & 1ull) {
-            base[j] += 1;
+          if ((word >> lane) & 1ull) {  // no-return LDS adds: one wave's adds apply in issue order
+            __hip_atomic_fetch_add(&base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
             for (int c = 0; c < kMaxCols; ++c)
-              if (c < ni) base[(int64_t)(1 + c) * m + j] += rv[c];
+              if (c < ni)
+                __hip_atomic_fetch_add(&base[(int64_t)(1 + c) * m + j], rv[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
             for (int c = 0; c < kMaxCols; ++c)
-              if (c < nf) {
-                double *d = (double *)&base[(int64_t)(1 + ni + c) * m + j];
-                *d += __longlong_as_double((long long)rf[c]);
-              }
+              if (c < nf)
+                __hip_atomic_fetch_add((double *)&base[(int64_t)(1 + ni + c) * m + j],
+                                       __longlong_as_double((long long)rf[c]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
       }
@@ -188,6 +191,9 @@ static PlainPlan plain_plan(const LaunchEnv &env, const DevInput &in) {
 }
 
 bool plain_fits_lds(const DevInput &in) { return !in.group_keys && plain_region_bytes(in) <= kLdsBudget; }
+
+// Whether four wave-private regions fit (enough waves per CU to hide latency).
+bool plain_fits_lds4(const DevInput &in) { return !in.group_keys && 4 * plain_region_bytes(in) <= kLdsBudget; }
 
 size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in) {
   const PlainPlan p = plain_plan(env, in);

@@ -190,6 +190,9 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
 uint32_t choose_algo(const pac::DevInput &d) {
   // counters that do not fit in LDS (many groups, sparse keys): partition the rows by group
   if (!pac::plain_fits_lds(d) && pac::part_supported(d) && d.n_rows >= 4096) return PAC_ALGO_PARTITION;
+  // float columns whose wave-private regions would leave fewer than four waves per workgroup
+  if (d.n_fcols > 0 && !pac::plain_fits_lds4(d) && pac::part_supported(d) && d.n_rows >= 4096)
+    return PAC_ALGO_PARTITION;
   if (d.group_keys || d.n_fcols > 0) return PAC_ALGO_PLAIN;
   int64_t bits = 1;
   for (int c = 0; c < d.n_icols; ++c) bits += d.icol_bits[c];

@@ -256,6 +256,7 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
 bool part_supported(const DevInput &in);
 size_t part_scratch_bytes(const DevInput &in);
 bool plain_fits_lds(const DevInput &in);
+bool plain_fits_lds4(const DevInput &in);
 bool star_supported(const DevInput &in);
 
 struct FinParams {
