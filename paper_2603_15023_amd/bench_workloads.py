@@ -1,0 +1,107 @@
+"""Timing of the library on the other synthetic workloads (one GPU).
+
+    python -m paper_2603_15023_amd.bench_workloads zipf   [--reps 3]
+    python -m paper_2603_15023_amd.bench_workloads float  [--reps 3] [--algo auto]
+    python -m paper_2603_15023_amd.bench_workloads serve  [--queries 64] [--slots 4] [--load 0.7]
+
+zipf:  100M rows, 2M PU keys per row, group keys Zipf(1.1) over 1M ranks
+       (HBM hash table), SUM int64 + COUNT, m = 64.
+float: 200M rows, 4M PU keys per row, 64 uniform groups, lognormal(0, 2)
+       FP64 values and their FP32 copy; m = 64 and 128.
+serve: the served workload (100M-row resident star schema, queries of mixed
+       selectivity, group count and aggregates) through the slot server.
+
+Each prints one JSON line per configuration: milliseconds per aggregation
+(mean of --reps after one warm-up) and the algorithmic bytes of the input.
+Inputs are resident on the GPU before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import AggSpec, Context, new_state, pac_group_aggregate
+
+
+def _time(ctx, spec, state, m, K, algo, reps):
+    pac_group_aggregate(ctx, spec, state, m=m, query_key=K, algo=algo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pac_group_aggregate(ctx, spec, state, m=m, query_key=K, algo=algo)
+    torch.cuda.synchronize()
+    ctx.check()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def zipf(args):
+    from workloads import gen
+    t = gen.config3_zipf()
+    dev = torch.device("cuda")
+    ctx = Context(0)
+    spec = AggSpec(n_rows=t.n_rows, pu_keys=torch.from_numpy(t.pu_key).to(dev),
+                   group_keys=torch.from_numpy(t.group_keys).to(dev), n_groups=1 << 21,
+                   cols=[torch.from_numpy(t.cols["v"]).to(dev)])
+    st = new_state(spec, 64)
+    ms = _time(ctx, spec, st, 64, gen.query_key(3), args.algo, args.reps)
+    groups = int(st["n_used"].cpu()[0])
+    alg = t.n_rows * 24 + groups * (2 * 64 + 1) * 8
+    print(json.dumps({"workload": "zipf 100M rows, 1M-rank Zipf(1.1) group keys, hash table", "algo": args.algo,
+                      "ms": ms, "groups": groups, "alg_bytes": alg, "hbm_frac": alg / (ms * 1e-3) / 8e12}),
+          flush=True)
+    ctx.close()
+
+
+def float_(args):
+    from workloads import gen
+    t = gen.config4_float()
+    dev = torch.device("cuda")
+    ctx = Context(0)
+    pu, g = torch.from_numpy(t.pu_key).to(dev), torch.from_numpy(t.gcols[0]).to(dev)
+    cols = {"v64": torch.from_numpy(t.cols["v64"]).to(dev), "v32": torch.from_numpy(t.cols["v32"]).to(dev)}
+    for m in (64, 128):
+        for name in ("v64", "v32"):
+            spec = AggSpec(n_rows=t.n_rows, pu_keys=pu, gcols=[g], gcards=[64], n_groups=64, cols=[cols[name]])
+            st = new_state(spec, m)
+            ms = _time(ctx, spec, st, m, gen.query_key(4), args.algo, args.reps)
+            alg = t.n_rows * (8 + 1 + cols[name].element_size())
+            print(json.dumps({"workload": f"float 200M rows, 64 groups, {name}", "m": m, "algo": args.algo,
+                              "ms": ms, "alg_bytes": alg, "hbm_frac": alg / (ms * 1e-3) / 8e12}), flush=True)
+    ctx.close()
+
+
+def serve(args):
+    from workloads import gen
+    from .serve import ResidentStar, Server, latency_summary
+    table = ResidentStar.from_table(gen.config5_star())
+    qs = gen.config5_queries(args.queries)
+    srv = Server(table, n_slots=args.slots)
+    srv.run(qs[:min(8, len(qs))])
+    closed = latency_summary(srv.run(qs))
+    rate = args.load * closed["qps"]
+    gaps = np.array([q.gap for q in qs]) / rate
+    opened = latency_summary(srv.run(qs, arrivals=np.cumsum(gaps) - gaps[0]))
+    srv.close()
+    print(json.dumps({"workload": "served star 100M rows", "slots": args.slots, "closed_loop": closed,
+                      "load": args.load, "open_loop": opened}), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["zipf", "float", "serve"])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--algo", default="auto")
+    ap.add_argument("--queries", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--load", type=float, default=0.7)
+    args = ap.parse_args(argv)
+    {"zipf": zipf, "float": float_, "serve": serve}[args.what](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
