@@ -58,6 +58,11 @@ struct PartPlan {
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr int kPartLdsTarget = 80 * 1024;  // two workgroups per CU
+#ifndef PART_DET_LDS_KB
+#define PART_DET_LDS_KB 40
+#endif
+// Deterministic form: four workgroups per CU (its per-record loop is latency bound).
+constexpr int kPartLdsTargetDet = PART_DET_LDS_KB * 1024;
 constexpr int kPartWaves = 4;              // waves per workgroup of the aggregation
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -71,8 +76,9 @@ static bool part_plan(const DevInput &in, PartPlan *pl) {
   p.det = in.n_fcols > 0;
   const int regions = p.det ? kPartWaves : 1;  // deterministic: one private region per wave
   const int64_t per_slot = p.slot_words * 8 * regions;
-  if (per_slot > kPartLdsTarget) return false;
-  int64_t slots = kPartLdsTarget / per_slot;
+  const int64_t target = p.det ? kPartLdsTargetDet : kPartLdsTarget;
+  if (per_slot > target) return false;
+  int64_t slots = target / per_slot;
   int SB = 0;
   while (((int64_t)2 << SB) <= slots) ++SB;
   p.SB = SB;
@@ -205,13 +211,14 @@ __global__ __launch_bounds__(256) void part_colscan(uint32_t *mat, int64_t n_par
   if (t == 255) count[p] = sums[255];
 }
 
-// 1''. route with a workgroup histogram in LDS (few partitions: the global
-// counters then see one atomic per workgroup and partition).
-constexpr int64_t kLdsParts = 16384;
+// 1''. route with a workgroup histogram in LDS (up to kLdsParts partitions:
+// the global counters then see one atomic per workgroup and partition).
+constexpr int64_t kLdsParts = 32768;   // 128 KB of LDS
+constexpr int64_t kLdsPartsBig = 8192; // above: 1024-thread workgroups, one per CU
 
-__global__ __launch_bounds__(256) void part_route_lds(DevInput in, DevState st, uint32_t *status, uint32_t *row_slot,
-                                                      uint32_t *count, int SB, int64_t n_parts) {
-  __shared__ uint32_t hist[kLdsParts];
+__global__ __launch_bounds__(1024) void part_route_lds(DevInput in, DevState st, uint32_t *status,
+                                                       uint32_t *row_slot, uint32_t *count, int SB, int64_t n_parts) {
+  extern __shared__ uint32_t hist[];
   for (int64_t i = threadIdx.x; i < n_parts; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   const int64_t n = in.n_rows, stride = (int64_t)gridDim.x * blockDim.x;
@@ -230,11 +237,11 @@ __global__ __launch_bounds__(256) void part_route_lds(DevInput in, DevState st, 
 // 3''. scatter with per-workgroup range reservation: count this workgroup's
 // rows per partition, reserve one range per partition, then place the rows.
 template <int W>
-__global__ __launch_bounds__(256) void part_scatter_lds(DevInput in, uint32_t *status, const uint32_t *row_slot,
-                                                        const int64_t *off, uint32_t *cur, int SB, int64_t n_parts,
-                                                        int64_t cap, uint32_t *rec_slot, uint64_t *rec_mk,
-                                                        uint64_t *rec_iv, uint64_t *rec_fv) {
-  __shared__ uint32_t at[kLdsParts];
+__global__ __launch_bounds__(1024) void part_scatter_lds(DevInput in, uint32_t *status, const uint32_t *row_slot,
+                                                         const int64_t *off, uint32_t *cur, int SB, int64_t n_parts,
+                                                         int64_t cap, uint32_t *rec_slot, uint64_t *rec_mk,
+                                                         uint64_t *rec_iv, uint64_t *rec_fv) {
+  extern __shared__ uint32_t at[];
   for (int64_t i = threadIdx.x; i < n_parts; i += blockDim.x) at[i] = 0;
   __syncthreads();
   const int64_t n = in.n_rows, stride = (int64_t)gridDim.x * blockDim.x;
@@ -404,15 +411,19 @@ __global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *s
 }
 
 // 4. per-partition aggregation in LDS
-template <int W>
-__global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, int ni, int nf, int64_t n_slots, int SB,
-                                                      int64_t slot_words, int64_t cap, const uint32_t *rec_slot,
-                                                      const uint64_t *rec_mk, const uint64_t *rec_iv,
-                                                      const uint64_t *rec_fv, const PartItem *items,
-                                                      int64_t *meta, int fresh) {
+// NI / NF >= 0: the column counts are compile-time (no per-column branches in
+// the per-record loop); -1: taken from ni_rt / nf_rt.
+template <int W, int NI, int NF>
+__global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, int ni_rt, int nf_rt, int64_t n_slots,
+                                                      int SB, int64_t slot_words, int64_t cap,
+                                                      const uint32_t *rec_slot, const uint64_t *rec_mk,
+                                                      const uint64_t *rec_iv, const uint64_t *rec_fv,
+                                                      const PartItem *items, int64_t *meta, int fresh) {
   extern __shared__ uint64_t lds[];
   __shared__ int64_t s_item;
   constexpr int m = 64 * W;
+  constexpr int CI = NI < 0 ? kMaxCols : NI, CF = NF < 0 ? kMaxCols : NF;
+  const int ni = NI < 0 ? ni_rt : NI, nf = NF < 0 ? nf_rt : NF;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
   const int A = 1 + ni + nf;
   const int64_t words = slot_words << SB;
@@ -431,14 +442,14 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
       const bool live = r < item.end;
       const int64_t rr_idx = live ? r : item.begin;
       const uint32_t ls = rec_slot[rr_idx];
-      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+      uint64_t mk[W], iv[CI > 0 ? CI : 1], fv[CF > 0 ? CF : 1];
 #pragma unroll
       for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + rr_idx];
 #pragma unroll
-      for (int k = 0; k < kMaxCols; ++k)
+      for (int k = 0; k < CI; ++k)
         if (k < ni) iv[k] = rec_iv[k * cap + rr_idx];
 #pragma unroll
-      for (int k = 0; k < kMaxCols; ++k)
+      for (int k = 0; k < CF; ++k)
         if (k < nf) fv[k] = rec_fv[k * cap + rr_idx];
       uint64_t todo = __ballot(live);
       while (todo) {
@@ -447,12 +458,13 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
         const uint32_t sl = __builtin_amdgcn_readlane(ls, rr);
         uint64_t *base = lds + (int64_t)sl * slot_words;
         if (lane == 0) __hip_atomic_fetch_add(&base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        uint64_t rv[kMaxCols], rf[kMaxCols];
+        uint64_t rv[CI > 0 ? CI : 1], rf[CF > 0 ? CF : 1];
 #pragma unroll
-        for (int k = 0; k < kMaxCols; ++k) {
+        for (int k = 0; k < CI; ++k)
           if (k < ni) rv[k] = readlane_u64(iv[k], rr);
+#pragma unroll
+        for (int k = 0; k < CF; ++k)
           if (k < nf) rf[k] = readlane_u64(fv[k], rr);
-        }
 #pragma unroll
         for (int w = 0; w < W; ++w) {
           const uint64_t word = readlane_u64(mk[w], rr);
@@ -460,12 +472,12 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
           if ((word >> lane) & 1ull) {
             __hip_atomic_fetch_add(&base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
-            for (int k = 0; k < kMaxCols; ++k)
+            for (int k = 0; k < CI; ++k)
               if (k < ni)
                 __hip_atomic_fetch_add(&base[(int64_t)(1 + k) * m + j], rv[k], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
-            for (int k = 0; k < kMaxCols; ++k)
+            for (int k = 0; k < CF; ++k)
               if (k < nf)
                 __hip_atomic_fetch_add((double *)&base[(int64_t)(1 + ni + k) * m + j],
                                        __longlong_as_double((long long)rf[k]), __ATOMIC_RELAXED,
@@ -499,14 +511,16 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
 // w-th quarter of the partition's records, in record order, into its own LDS
 // region (lane = world: no two lanes touch one word); the regions are then
 // combined in wave order and the owning workgroup adds them to the state.
-template <int W>
+template <int W, int NI, int NF>
 __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
-    DevState st, int ni, int nf, int64_t n_slots, int SB, int64_t slot_words, int64_t cap, const uint32_t *rec_slot,
-    const uint64_t *rec_mk, const uint64_t *rec_iv, const uint64_t *rec_fv, const PartItem *items, int64_t *meta,
-    uint64_t *partial) {
+    DevState st, int ni_rt, int nf_rt, int64_t n_slots, int SB, int64_t slot_words, int64_t cap,
+    const uint32_t *rec_slot, const uint64_t *rec_mk, const uint64_t *rec_iv, const uint64_t *rec_fv,
+    const PartItem *items, int64_t *meta, uint64_t *partial) {
   extern __shared__ uint64_t lds[];
   __shared__ int64_t s_item;
   constexpr int m = 64 * W;
+  constexpr int CI = NI < 0 ? kMaxCols : NI, CF = NF < 0 ? kMaxCols : NF;
+  const int ni = NI < 0 ? ni_rt : NI, nf = NF < 0 ? nf_rt : NF;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int A = 1 + ni + nf;
   const int64_t words = slot_words << SB;
@@ -528,46 +542,67 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
       const bool live = r < b1;
       const int64_t ri = live ? r : b0;
       const uint32_t ls = rec_slot[ri];
-      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+      uint64_t mk[W], iv[CI > 0 ? CI : 1], fv[CF > 0 ? CF : 1];
 #pragma unroll
       for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + ri];
 #pragma unroll
-      for (int k = 0; k < kMaxCols; ++k)
+      for (int k = 0; k < CI; ++k)
         if (k < ni) iv[k] = rec_iv[k * cap + ri];
 #pragma unroll
-      for (int k = 0; k < kMaxCols; ++k)
+      for (int k = 0; k < CF; ++k)
         if (k < nf) fv[k] = rec_fv[k * cap + ri];
       uint64_t todo = __ballot(live);
-      while (todo) {  // records in order
-        const int rr = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        uint64_t *base = mine + (int64_t)__builtin_amdgcn_readlane(ls, rr) * slot_words;
-        if (lane == 0) __hip_atomic_fetch_add(&base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        uint64_t rv[kMaxCols], rf[kMaxCols];
+      // Records in order, two per iteration: the cross-lane reads of both are
+      // issued before the LDS adds of the first.  No-return LDS adds of one
+      // wave apply in issue order.
+      struct Rec {
+        uint64_t *base;
+        uint64_t word[W], rv[CI > 0 ? CI : 1], rf[CF > 0 ? CF : 1];
+      };
+      auto fetch = [&](int rr, Rec &c) {
+        c.base = mine + (int64_t)__builtin_amdgcn_readlane(ls, rr) * slot_words;
 #pragma unroll
-        for (int k = 0; k < kMaxCols; ++k) {
-          if (k < ni) rv[k] = readlane_u64(iv[k], rr);
-          if (k < nf) rf[k] = readlane_u64(fv[k], rr);
-        }
+        for (int k = 0; k < CI; ++k)
+          if (k < ni) c.rv[k] = readlane_u64(iv[k], rr);
+#pragma unroll
+        for (int k = 0; k < CF; ++k)
+          if (k < nf) c.rf[k] = readlane_u64(fv[k], rr);
+#pragma unroll
+        for (int w = 0; w < W; ++w) c.word[w] = readlane_u64(mk[w], rr);
+      };
+      auto apply = [&](const Rec &c) {
+        if (lane == 0)
+          __hip_atomic_fetch_add(&c.base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          const uint64_t word = readlane_u64(mk[w], rr);
           const int j = w * 64 + lane;
-          if ((word >> lane) & 1ull) {  // no-return LDS adds: one wave's adds apply in issue order
-            __hip_atomic_fetch_add(&base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if ((c.word[w] >> lane) & 1ull) {
+            __hip_atomic_fetch_add(&c.base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
-            for (int k = 0; k < kMaxCols; ++k)
+            for (int k = 0; k < CI; ++k)
               if (k < ni)
-                __hip_atomic_fetch_add(&base[(int64_t)(1 + k) * m + j], rv[k], __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(&c.base[(int64_t)(1 + k) * m + j], c.rv[k], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
-            for (int k = 0; k < kMaxCols; ++k)
+            for (int k = 0; k < CF; ++k)
               if (k < nf)
-                __hip_atomic_fetch_add((double *)&base[(int64_t)(1 + ni + k) * m + j],
-                                       __longlong_as_double((long long)rf[k]), __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add((double *)&c.base[(int64_t)(1 + ni + k) * m + j],
+                                       __longlong_as_double((long long)c.rf[k]), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
+      };
+      while (todo) {
+        const int r0 = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const bool two = todo != 0;
+        const int r1 = two ? __ffsll((unsigned long long)todo) - 1 : r0;
+        todo &= todo - 1;  // no-op when empty
+        Rec c0, c1;
+        fetch(r0, c0);
+        fetch(r1, c1);
+        apply(c0);
+        if (two) apply(c1);
       }
     }
     __syncthreads();
@@ -619,6 +654,33 @@ __global__ __launch_bounds__(256) void part_reduce_det(DevState st, int ni, int 
   }
 }
 
+using AggFn = void (*)(DevState, int, int, int64_t, int, int64_t, int64_t, const uint32_t *, const uint64_t *,
+                      const uint64_t *, const uint64_t *, const PartItem *, int64_t *, int);
+using AggDetFn = void (*)(DevState, int, int, int64_t, int, int64_t, int64_t, const uint32_t *, const uint64_t *,
+                         const uint64_t *, const uint64_t *, const PartItem *, int64_t *, uint64_t *);
+
+// Integer columns only (the non-deterministic form): specialised loops for up to three columns.
+template <int W>
+static AggFn agg_fn(int ni) {
+  switch (ni) {
+    case 0: return part_aggregate<W, 0, 0>;
+    case 1: return part_aggregate<W, 1, 0>;
+    case 2: return part_aggregate<W, 2, 0>;
+    case 3: return part_aggregate<W, 3, 0>;
+    default: return part_aggregate<W, -1, 0>;
+  }
+}
+
+// Float columns present: specialised loops for the common small mixes.
+template <int W>
+static AggDetFn agg_det_fn(int ni, int nf) {
+  if (nf == 1 && ni == 0) return part_aggregate_det<W, 0, 1>;
+  if (nf == 1 && ni == 1) return part_aggregate_det<W, 1, 1>;
+  if (nf == 1 && ni == 2) return part_aggregate_det<W, 2, 1>;
+  if (nf == 2 && ni == 0) return part_aggregate_det<W, 0, 2>;
+  return part_aggregate_det<W, -1, -1>;
+}
+
 hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
                            size_t scratch_bytes, bool fresh) {
   if (in.n_rows <= 0) return hipSuccess;
@@ -663,22 +725,36 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
     if ((e = launch_fill_i64(env, (int64_t *)count, (p.n_parts + 1) / 2, 0)) != hipSuccess)  // u32 counts in pairs
       return e;
     const bool few = p.n_parts <= kLdsParts;  // workgroup histograms and range reservations in LDS
-    if (few)
-      hipLaunchKernelGGL(part_route_lds, dim3(grid), dim3(256), 0, env.stream, in, st, env.status, row_slot, count,
-                         p.SB, p.n_parts);
-    else
+    // many partitions: fewer, larger workgroups, so that each sees more rows
+    // per partition and the global counters fewer atomics
+    const bool big = p.n_parts > kLdsPartsBig;
+    const int lgrid = big ? env.n_cu : grid, lblock = big ? 1024 : 256;
+    const size_t lds = (size_t)p.n_parts * 4;
+    if (few) {
+      if ((e = hipFuncSetAttribute((const void *)part_route_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds)) != hipSuccess)
+        return e;
+      hipLaunchKernelGGL(part_route_lds, dim3(lgrid), dim3(lblock), lds, env.stream, in, st, env.status, row_slot,
+                         count, p.SB, p.n_parts);
+    } else {
       hipLaunchKernelGGL(part_route, dim3(grid), dim3(256), 0, env.stream, in, st, env.status, row_slot, count,
                          p.SB);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, count, p.n_parts, p.chunk, off, cur, items,
                        meta, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (few) {
+      const void *sfn = in.W == 1 ? (const void *)part_scatter_lds<1> : (const void *)part_scatter_lds<2>;
+      if ((e = hipFuncSetAttribute(sfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+        return e;
+    }
     if (few && in.W == 1)
-      hipLaunchKernelGGL(part_scatter_lds<1>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
-                         cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+      hipLaunchKernelGGL(part_scatter_lds<1>, dim3(lgrid), dim3(lblock), lds, env.stream, in, env.status, row_slot,
+                         off, cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
     else if (few)
-      hipLaunchKernelGGL(part_scatter_lds<2>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off,
-                         cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+      hipLaunchKernelGGL(part_scatter_lds<2>, dim3(lgrid), dim3(lblock), lds, env.stream, in, env.status, row_slot,
+                         off, cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
     else if (in.W == 1)
       hipLaunchKernelGGL(part_scatter<1>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off, cur,
                          p.SB, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
@@ -687,8 +763,10 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
                          p.SB, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const void *fn = p.det ? (in.W == 1 ? (const void *)part_aggregate_det<1> : (const void *)part_aggregate_det<2>)
-                         : (in.W == 1 ? (const void *)part_aggregate<1> : (const void *)part_aggregate<2>);
+  const AggFn afn = p.det ? nullptr : (in.W == 1 ? agg_fn<1>(in.n_icols) : agg_fn<2>(in.n_icols));
+  const AggDetFn dfn = p.det ? (in.W == 1 ? agg_det_fn<1>(in.n_icols, in.n_fcols) : agg_det_fn<2>(in.n_icols, in.n_fcols))
+                             : nullptr;
+  const void *fn = p.det ? (const void *)dfn : (const void *)afn;
   if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes)) != hipSuccess) return e;
   int per_cu = 0;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kPartWaves, p.lds_bytes)) != hipSuccess)
@@ -696,14 +774,9 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
   const int agg_grid = std::max(1, env.n_cu * std::max(1, per_cu));
   if (p.det) {
     uint64_t *partial = (uint64_t *)(base + p.off_partial);
-    if (in.W == 1)
-      hipLaunchKernelGGL(part_aggregate_det<1>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes,
-                         env.stream, st, in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot,
-                         rec_mk, rec_iv, rec_fv, items, meta, partial);
-    else
-      hipLaunchKernelGGL(part_aggregate_det<2>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes,
-                         env.stream, st, in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot,
-                         rec_mk, rec_iv, rec_fv, items, meta, partial);
+    hipLaunchKernelGGL(dfn, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st, in.n_icols,
+                       in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv, rec_fv, items, meta,
+                       partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t threads = p.n_parts * (p.slot_words << p.SB);
     hipLaunchKernelGGL(part_reduce_det, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, env.stream, st,
@@ -711,14 +784,9 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
                        (const int64_t *)(base + p.off_pfirst), partial, fresh ? 1 : 0);
     return hipGetLastError();
   }
-  if (in.W == 1)
-    hipLaunchKernelGGL(part_aggregate<1>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st,
-                       in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv,
-                       rec_fv, items, meta, fresh ? 1 : 0);
-  else
-    hipLaunchKernelGGL(part_aggregate<2>, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st,
-                       in.n_icols, in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv,
-                       rec_fv, items, meta, fresh ? 1 : 0);
+  hipLaunchKernelGGL(afn, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st, in.n_icols,
+                     in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv, rec_fv, items, meta,
+                     fresh ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -146,7 +146,11 @@ __device__ __forceinline__ int64_t table_slot(int64_t key, int64_t *slot_keys, i
                                               uint32_t *status) {
   uint64_t h = mix64((uint64_t)key ^ kSlotSalt) & (uint64_t)(cap - 1);
   for (int64_t probe = 0; probe < cap; ++probe) {
-    const int64_t k = __hip_atomic_load(&slot_keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // A slot's key is written once (EMPTY -> key), so a cached copy that is not
+    // EMPTY is current: only an EMPTY one needs the coherent re-read.
+    int64_t k = slot_keys[h];
+    if (k == key) return (int64_t)h;
+    if (k == PAC_EMPTY_KEY) k = __hip_atomic_load(&slot_keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (k == key) return (int64_t)h;
     if (k == PAC_EMPTY_KEY) {
       unsigned long long expected = (unsigned long long)PAC_EMPTY_KEY;
