@@ -45,8 +45,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv"])
     ap.add_argument("--compare-steps", type=int, default=5, help="steps timed for the other GPU forms")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle baseline")
@@ -141,23 +141,30 @@ def main():
             ev[1].record(stream)
         return P.pac_finalize(ctx, state, cells_t, len(cells), m=64, mi_budget=1.0 / 128, noise_seed=seed)
 
-    def run(algo, steps, warmup):
+    def run(algo, steps, warmup, latency_steps=0):
         for _ in range(warmup):
             step(algo)
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        step_ms = []
+        # the K timed steps are issued back to back (one stream, in order) and
+        # bracketed by synchronisations
         t_start = time.perf_counter()
         for i in range(steps):
-            s0 = time.perf_counter()
             step(algo, evs[i])
-            torch.cuda.synchronize()
-            step_ms.append((time.perf_counter() - s0) * 1e3)
+        torch.cuda.synchronize()
         total = time.perf_counter() - t_start
         agg_ms = [a.elapsed_time(b) for a, b in evs]
+        # single-step latency (issue to completion), measured after the timed region
+        step_ms = []
+        for _ in range(latency_steps):
+            s0 = time.perf_counter()
+            step(algo)
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - s0) * 1e3)
         return total * 1e3 / steps, float(np.mean(agg_ms)), step_ms
 
-    ms_step, agg_ms, step_ms = run(args.algo, args.steps, args.warmup)
+    ms_step, agg_ms, step_ms = run(args.algo, args.steps, args.warmup, latency_steps=min(args.steps, 50))
+
     ctx.check()
     log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
 
@@ -219,8 +226,8 @@ def main():
                                f"({'shuffled' if args.shuffled else 'clustered by order'}), "
                                "6 groups, COUNT + SUM/AVG of 3 int64 cents columns, m=64, 42 released cells",
                    "algo": args.algo},
-        "step_latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
-                            "max": float(np.max(step_ms))},
+        "step_latency_ms": ({"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                             "max": float(np.max(step_ms))} if step_ms else None),
         "aggregate_rows_per_s": n / (agg_ms * 1e-3),
         "forms": {k: dict(v, aggregate_rows_per_s=n / (v["aggregate_ms"] * 1e-3),
                           alg_bytes=alg_kv if k == "mfma_kv" else alg_bytes,

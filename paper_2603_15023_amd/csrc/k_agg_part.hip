@@ -410,6 +410,91 @@ __global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *s
   }
 }
 
+// The records of one batch (bits of `todo`: lanes holding a live record), in
+// lane order, into the counters at region + slot * slot_words (lane = world).
+// Two records per iteration: the cross-lane reads of both are issued before
+// the LDS adds of the first.  No-return LDS adds of one wave apply in issue
+// order, so a wave-private region sums in record order.
+template <int W, int CI, int CF>
+__device__ __forceinline__ void part_records(uint64_t *region, int64_t slot_words, int A, int ni, int nf, uint32_t ls,
+                                             const uint64_t (&mk)[W], const uint64_t (&iv)[CI > 0 ? CI : 1],
+                                             const uint64_t (&fv)[CF > 0 ? CF : 1], uint64_t todo, int lane) {
+  constexpr int m = 64 * W;
+  struct Rec {
+    uint64_t *base;
+    uint64_t word[W], rv[CI > 0 ? CI : 1], rf[CF > 0 ? CF : 1];
+  };
+  auto fetch = [&](int rr, Rec &c) {
+    c.base = region + (int64_t)__builtin_amdgcn_readlane(ls, rr) * slot_words;
+#pragma unroll
+    for (int k = 0; k < CI; ++k)
+      if (k < ni) c.rv[k] = readlane_u64(iv[k], rr);
+#pragma unroll
+    for (int k = 0; k < CF; ++k)
+      if (k < nf) c.rf[k] = readlane_u64(fv[k], rr);
+#pragma unroll
+    for (int w = 0; w < W; ++w) c.word[w] = readlane_u64(mk[w], rr);
+  };
+  auto apply = [&](const Rec &c) {
+    if (lane == 0)
+      __hip_atomic_fetch_add(&c.base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int j = w * 64 + lane;
+      if ((c.word[w] >> lane) & 1ull) {
+        __hip_atomic_fetch_add(&c.base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int k = 0; k < CI; ++k)
+          if (k < ni)
+            __hip_atomic_fetch_add(&c.base[(int64_t)(1 + k) * m + j], c.rv[k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int k = 0; k < CF; ++k)
+          if (k < nf)
+            __hip_atomic_fetch_add((double *)&c.base[(int64_t)(1 + ni + k) * m + j],
+                                   __longlong_as_double((long long)c.rf[k]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  };
+  while (todo) {
+    const int r0 = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
+    const bool two = todo != 0;
+    const int r1 = two ? __ffsll((unsigned long long)todo) - 1 : r0;
+    todo &= todo - 1;  // no-op when empty
+    Rec c0, c1;
+    fetch(r0, c0);
+    fetch(r1, c1);
+    apply(c0);
+    if (two) apply(c1);
+  }
+}
+
+// One lane's record of a batch of 64 (record r if r < end, else a dummy
+// read of record `first` marked dead).
+template <int W, int CI, int CF>
+struct RecBatch {
+  uint32_t ls;
+  bool live;
+  uint64_t mk[W], iv[CI > 0 ? CI : 1], fv[CF > 0 ? CF : 1];
+  __device__ __forceinline__ void load(int64_t r, int64_t end, int64_t first, int64_t cap, int ni, int nf,
+                                       const uint32_t *rec_slot, const uint64_t *rec_mk, const uint64_t *rec_iv,
+                                       const uint64_t *rec_fv) {
+    live = r < end;
+    const int64_t i = live ? r : first;
+    ls = rec_slot[i];
+#pragma unroll
+    for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + i];
+#pragma unroll
+    for (int k = 0; k < CI; ++k)
+      if (k < ni) iv[k] = rec_iv[k * cap + i];
+#pragma unroll
+    for (int k = 0; k < CF; ++k)
+      if (k < nf) fv[k] = rec_fv[k * cap + i];
+  }
+};
+
 // 4. per-partition aggregation in LDS
 // NI / NF >= 0: the column counts are compile-time (no per-column branches in
 // the per-record loop); -1: taken from ni_rt / nf_rt.
@@ -438,53 +523,9 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
     for (int64_t i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0;
     __syncthreads();
     for (int64_t b = item.begin + 64 * wave; b < item.end; b += 64 * waves) {
-      const int64_t r = b + lane;
-      const bool live = r < item.end;
-      const int64_t rr_idx = live ? r : item.begin;
-      const uint32_t ls = rec_slot[rr_idx];
-      uint64_t mk[W], iv[CI > 0 ? CI : 1], fv[CF > 0 ? CF : 1];
-#pragma unroll
-      for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + rr_idx];
-#pragma unroll
-      for (int k = 0; k < CI; ++k)
-        if (k < ni) iv[k] = rec_iv[k * cap + rr_idx];
-#pragma unroll
-      for (int k = 0; k < CF; ++k)
-        if (k < nf) fv[k] = rec_fv[k * cap + rr_idx];
-      uint64_t todo = __ballot(live);
-      while (todo) {
-        const int rr = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const uint32_t sl = __builtin_amdgcn_readlane(ls, rr);
-        uint64_t *base = lds + (int64_t)sl * slot_words;
-        if (lane == 0) __hip_atomic_fetch_add(&base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        uint64_t rv[CI > 0 ? CI : 1], rf[CF > 0 ? CF : 1];
-#pragma unroll
-        for (int k = 0; k < CI; ++k)
-          if (k < ni) rv[k] = readlane_u64(iv[k], rr);
-#pragma unroll
-        for (int k = 0; k < CF; ++k)
-          if (k < nf) rf[k] = readlane_u64(fv[k], rr);
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          const uint64_t word = readlane_u64(mk[w], rr);
-          const int j = w * 64 + lane;
-          if ((word >> lane) & 1ull) {
-            __hip_atomic_fetch_add(&base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-            for (int k = 0; k < CI; ++k)
-              if (k < ni)
-                __hip_atomic_fetch_add(&base[(int64_t)(1 + k) * m + j], rv[k], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-            for (int k = 0; k < CF; ++k)
-              if (k < nf)
-                __hip_atomic_fetch_add((double *)&base[(int64_t)(1 + ni + k) * m + j],
-                                       __longlong_as_double((long long)rf[k]), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
-        }
-      }
+      RecBatch<W, CI, CF> c;
+      c.load(b + lane, item.end, item.begin, cap, ni, nf, rec_slot, rec_mk, rec_iv, rec_fv);
+      part_records<W, CI, CF>(lds, slot_words, A, ni, nf, c.ls, c.mk, c.iv, c.fv, __ballot(c.live), lane);
     }
     __syncthreads();
     // non-zero counters of this partition -> global state
@@ -538,72 +579,9 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
     const int64_t n = item.end - item.begin, q = (n + kPartWaves - 1) / kPartWaves;
     const int64_t b0 = item.begin + q * wave, b1 = min(item.end, b0 + q);
     for (int64_t b = b0; b < b1; b += 64) {
-      const int64_t r = b + lane;
-      const bool live = r < b1;
-      const int64_t ri = live ? r : b0;
-      const uint32_t ls = rec_slot[ri];
-      uint64_t mk[W], iv[CI > 0 ? CI : 1], fv[CF > 0 ? CF : 1];
-#pragma unroll
-      for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + ri];
-#pragma unroll
-      for (int k = 0; k < CI; ++k)
-        if (k < ni) iv[k] = rec_iv[k * cap + ri];
-#pragma unroll
-      for (int k = 0; k < CF; ++k)
-        if (k < nf) fv[k] = rec_fv[k * cap + ri];
-      uint64_t todo = __ballot(live);
-      // Records in order, two per iteration: the cross-lane reads of both are
-      // issued before the LDS adds of the first.  No-return LDS adds of one
-      // wave apply in issue order.
-      struct Rec {
-        uint64_t *base;
-        uint64_t word[W], rv[CI > 0 ? CI : 1], rf[CF > 0 ? CF : 1];
-      };
-      auto fetch = [&](int rr, Rec &c) {
-        c.base = mine + (int64_t)__builtin_amdgcn_readlane(ls, rr) * slot_words;
-#pragma unroll
-        for (int k = 0; k < CI; ++k)
-          if (k < ni) c.rv[k] = readlane_u64(iv[k], rr);
-#pragma unroll
-        for (int k = 0; k < CF; ++k)
-          if (k < nf) c.rf[k] = readlane_u64(fv[k], rr);
-#pragma unroll
-        for (int w = 0; w < W; ++w) c.word[w] = readlane_u64(mk[w], rr);
-      };
-      auto apply = [&](const Rec &c) {
-        if (lane == 0)
-          __hip_atomic_fetch_add(&c.base[(int64_t)A * m], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          const int j = w * 64 + lane;
-          if ((c.word[w] >> lane) & 1ull) {
-            __hip_atomic_fetch_add(&c.base[j], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-            for (int k = 0; k < CI; ++k)
-              if (k < ni)
-                __hip_atomic_fetch_add(&c.base[(int64_t)(1 + k) * m + j], c.rv[k], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-            for (int k = 0; k < CF; ++k)
-              if (k < nf)
-                __hip_atomic_fetch_add((double *)&c.base[(int64_t)(1 + ni + k) * m + j],
-                                       __longlong_as_double((long long)c.rf[k]), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-          }
-        }
-      };
-      while (todo) {
-        const int r0 = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const bool two = todo != 0;
-        const int r1 = two ? __ffsll((unsigned long long)todo) - 1 : r0;
-        todo &= todo - 1;  // no-op when empty
-        Rec c0, c1;
-        fetch(r0, c0);
-        fetch(r1, c1);
-        apply(c0);
-        if (two) apply(c1);
-      }
+      RecBatch<W, CI, CF> c;
+      c.load(b + lane, b1, b0, cap, ni, nf, rec_slot, rec_mk, rec_iv, rec_fv);
+      part_records<W, CI, CF>(mine, slot_words, A, ni, nf, c.ls, c.mk, c.iv, c.fv, __ballot(c.live), lane);
     }
     __syncthreads();
     // this work item's counters, the wave regions combined in wave order
