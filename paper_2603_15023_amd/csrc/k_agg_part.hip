@@ -67,6 +67,14 @@ constexpr int kPartWaves = 4;              // waves per workgroup of the aggrega
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Deterministic form, column mixes whose per-record loop keeps the counters in
+// registers: slots per partition (0: the LDS loop).  Must agree with agg_det_fn.
+static int det_reg_slots(const DevInput &in) {
+  const int ni = in.n_icols, nf = in.n_fcols;
+  const bool mix = (nf == 1 && ni <= 2) || (nf == 2 && ni == 0);
+  return mix ? (in.W == 1 ? 8 : 4) : 0;
+}
+
 static bool part_plan(const DevInput &in, PartPlan *pl) {
   PartPlan p{};
   p.n_slots = in.n_groups;
@@ -81,6 +89,10 @@ static bool part_plan(const DevInput &in, PartPlan *pl) {
   int64_t slots = target / per_slot;
   int SB = 0;
   while (((int64_t)2 << SB) <= slots) ++SB;
+  if (p.det && det_reg_slots(in)) {
+    SB = det_reg_slots(in) == 8 ? 3 : 2;
+    if (((int64_t)1 << SB) * per_slot > 160 * 1024) return false;
+  }
   p.SB = SB;
   p.lds_bytes = (int)(((int64_t)1 << SB) * per_slot);
   p.n_parts = (p.n_slots + ((int64_t)1 << SB) - 1) >> SB;
@@ -552,7 +564,10 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, i
 // w-th quarter of the partition's records, in record order, into its own LDS
 // region (lane = world: no two lanes touch one word); the regions are then
 // combined in wave order and the owning workgroup adds them to the state.
-template <int W, int NI, int NF>
+// S > 0 (common column mixes, S slots per partition): the quarter's counters
+// are kept in registers and stored to the region once, instead of LDS adds
+// per record.
+template <int W, int NI, int NF, int S>
 __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
     DevState st, int ni_rt, int nf_rt, int64_t n_slots, int SB, int64_t slot_words, int64_t cap,
     const uint32_t *rec_slot, const uint64_t *rec_mk, const uint64_t *rec_iv, const uint64_t *rec_fv,
@@ -574,14 +589,79 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
     const int64_t it = s_item;
     if (it >= n_items) break;
     const PartItem item = items[it];
-    for (int64_t i = threadIdx.x; i < words * kPartWaves; i += blockDim.x) lds[i] = 0;
-    __syncthreads();
     const int64_t n = item.end - item.begin, q = (n + kPartWaves - 1) / kPartWaves;
     const int64_t b0 = item.begin + q * wave, b1 = min(item.end, b0 + q);
-    for (int64_t b = b0; b < b1; b += 64) {
-      RecBatch<W, CI, CF> c;
-      c.load(b + lane, b1, b0, cap, ni, nf, rec_slot, rec_mk, rec_iv, rec_fv);
-      part_records<W, CI, CF>(mine, slot_words, A, ni, nf, c.ls, c.mk, c.iv, c.fv, __ballot(c.live), lane);
+    if constexpr (S > 0) {
+      // S slots per partition: the wave's counters live in registers (lane =
+      // world), records added slot by slot in record order -- the order of
+      // the LDS form, so the sums are the same -- and are stored to the
+      // wave's region (every word of it) at the end.
+      uint32_t cn[S][W], nr[S];
+      uint64_t is[S][W][CI > 0 ? CI : 1];
+      double fs[S][W][CF > 0 ? CF : 1];
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        nr[sl] = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          cn[sl][w] = 0;
+#pragma unroll
+          for (int k = 0; k < CI; ++k) is[sl][w][k] = 0;
+#pragma unroll
+          for (int k = 0; k < CF; ++k) fs[sl][w][k] = 0.0;
+        }
+      }
+      for (int64_t b = b0; b < b1; b += 64) {
+        RecBatch<W, CI, CF> c;
+        c.load(b + lane, b1, b0, cap, ni, nf, rec_slot, rec_mk, rec_iv, rec_fv);
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) {
+          uint64_t todo = __ballot(c.live && c.ls == (uint32_t)sl);
+          nr[sl] += (uint32_t)__popcll(todo);
+          while (todo) {
+            const int rr = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            uint64_t u[CI > 0 ? CI : 1];
+            double v[CF > 0 ? CF : 1];
+#pragma unroll
+            for (int k = 0; k < CI; ++k) u[k] = readlane_u64(c.iv[k], rr);
+#pragma unroll
+            for (int k = 0; k < CF; ++k) v[k] = __longlong_as_double((long long)readlane_u64(c.fv[k], rr));
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              const bool bit = (readlane_u64(c.mk[w], rr) >> lane) & 1ull;
+              cn[sl][w] += bit ? 1u : 0u;
+#pragma unroll
+              for (int k = 0; k < CI; ++k) is[sl][w][k] += bit ? u[k] : 0ull;
+#pragma unroll
+              for (int k = 0; k < CF; ++k) fs[sl][w][k] = bit ? fs[sl][w][k] + v[k] : fs[sl][w][k];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < S; ++sl) {
+        uint64_t *base = mine + (int64_t)sl * slot_words;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const int j = w * 64 + lane;
+          base[j] = cn[sl][w];
+#pragma unroll
+          for (int k = 0; k < CI; ++k) base[(int64_t)(1 + k) * m + j] = is[sl][w][k];
+#pragma unroll
+          for (int k = 0; k < CF; ++k)
+            base[(int64_t)(1 + CI + k) * m + j] = (uint64_t)__double_as_longlong(fs[sl][w][k]);
+        }
+        if (lane == 0) base[(int64_t)A * m] = nr[sl];
+      }
+    } else {
+      for (int64_t i = threadIdx.x; i < words * kPartWaves; i += blockDim.x) lds[i] = 0;
+      __syncthreads();
+      for (int64_t b = b0; b < b1; b += 64) {
+        RecBatch<W, CI, CF> c;
+        c.load(b + lane, b1, b0, cap, ni, nf, rec_slot, rec_mk, rec_iv, rec_fv);
+        part_records<W, CI, CF>(mine, slot_words, A, ni, nf, c.ls, c.mk, c.iv, c.fv, __ballot(c.live), lane);
+      }
     }
     __syncthreads();
     // this work item's counters, the wave regions combined in wave order
@@ -649,14 +729,16 @@ static AggFn agg_fn(int ni) {
   }
 }
 
-// Float columns present: specialised loops for the common small mixes.
+// Float columns present: the common small mixes keep their counters in
+// registers (det_reg_slots slots per partition); others use the LDS loop.
 template <int W>
 static AggDetFn agg_det_fn(int ni, int nf) {
-  if (nf == 1 && ni == 0) return part_aggregate_det<W, 0, 1>;
-  if (nf == 1 && ni == 1) return part_aggregate_det<W, 1, 1>;
-  if (nf == 1 && ni == 2) return part_aggregate_det<W, 2, 1>;
-  if (nf == 2 && ni == 0) return part_aggregate_det<W, 0, 2>;
-  return part_aggregate_det<W, -1, -1>;
+  constexpr int S = W == 1 ? 8 : 4;
+  if (nf == 1 && ni == 0) return part_aggregate_det<W, 0, 1, S>;
+  if (nf == 1 && ni == 1) return part_aggregate_det<W, 1, 1, S>;
+  if (nf == 1 && ni == 2) return part_aggregate_det<W, 2, 1, S>;
+  if (nf == 2 && ni == 0) return part_aggregate_det<W, 0, 2, S>;
+  return part_aggregate_det<W, -1, -1, 0>;
 }
 
 hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
