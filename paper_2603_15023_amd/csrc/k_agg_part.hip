@@ -97,7 +97,7 @@ static bool part_plan(const DevInput &in, PartPlan *pl) {
   p.lds_bytes = (int)(((int64_t)1 << SB) * per_slot);
   p.n_parts = (p.n_slots + ((int64_t)1 << SB) - 1) >> SB;
   p.cap = in.n_rows;
-  p.chunk = 16384;
+  p.chunk = p.det ? 65536 : 16384;  // deterministic: fewer items, a shorter ordered merge
   p.max_items = p.n_parts + p.cap / p.chunk + 1;
   if (p.det) {  // records land in row order: per-wave counts instead of atomic cursors
     const int64_t n_chunks = (in.n_rows + 63) / 64;
@@ -174,6 +174,8 @@ __global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, 
   const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= n_waves) return;
   const int64_t n_chunks = (in.n_rows + 63) >> 6, cpw = (n_chunks + n_waves - 1) / n_waves;
+  const bool few = n_parts <= 64;  // lane p counts partition p in a register
+  uint32_t cnt = 0;
   for (int64_t c = w * cpw; c < min(n_chunks, (w + 1) * cpw); ++c) {
     const int64_t r = c * 64 + lane;
     int64_t g = -1;
@@ -189,10 +191,14 @@ __global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, 
       const int leader = __ffsll((unsigned long long)todo) - 1;
       const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
       const uint64_t same = __ballot(part == p0) & todo;
-      if (lane == leader) mat[(int64_t)p0 * n_waves + w] += (uint32_t)__popcll(same);  // only this wave writes it
+      if (few)
+        cnt += lane == (int)p0 ? (uint32_t)__popcll(same) : 0u;
+      else if (lane == leader)
+        mat[(int64_t)p0 * n_waves + w] += (uint32_t)__popcll(same);  // only this wave writes it
       todo &= ~same;
     }
   }
+  if (few && lane < n_parts) mat[(int64_t)lane * n_waves + w] = cnt;
 }
 
 // Per partition (one workgroup each): exclusive prefix of the per-wave counts
@@ -386,6 +392,9 @@ __global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *s
   if (w >= n_waves) return;
   const int64_t n_chunks = (in.n_rows + 63) >> 6, cpw = (n_chunks + n_waves - 1) / n_waves;
   const uint32_t lmask = (1u << SB) - 1u;
+  // few partitions: lane p holds partition p's next position in registers
+  const bool few = n_parts <= 64;
+  int64_t next = few && lane < n_parts ? off[lane] + mat[(int64_t)lane * n_waves + w] : 0;
   for (int64_t c = w * cpw; c < min(n_chunks, (w + 1) * cpw); ++c) {
     const int64_t r = c * 64 + lane;
     const uint32_t s = r < in.n_rows ? row_slot[r] : kNoSlot;
@@ -396,14 +405,21 @@ __global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *s
       const int leader = __ffsll((unsigned long long)todo) - 1;
       const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
       const uint64_t same = __ballot(part == p0) & todo;
-      uint32_t base = 0;
-      if (lane == leader) {
-        uint32_t *e = &mat[(int64_t)p0 * n_waves + w];
-        base = *e;
-        *e = base + (uint32_t)__popcll(same);
+      const uint32_t n0 = (uint32_t)__popcll(same);
+      int64_t start;
+      if (few) {
+        start = (int64_t)readlane_u64((uint64_t)next, (int)p0);
+        next += lane == (int)p0 ? (int64_t)n0 : 0;
+      } else {
+        uint32_t base = 0;
+        if (lane == leader) {
+          uint32_t *e = &mat[(int64_t)p0 * n_waves + w];
+          base = *e;
+          *e = base + n0;
+        }
+        start = off[p0] + __builtin_amdgcn_readlane(base, leader);
       }
-      base = __builtin_amdgcn_readlane(base, leader);
-      if ((same >> lane) & 1ull) pos = off[p0] + base + __popcll(same & lanes_lt(lane));
+      if ((same >> lane) & 1ull) pos = start + __popcll(same & lanes_lt(lane));
       todo &= ~same;
     }
     if (pos >= 0) {
