@@ -72,6 +72,18 @@ def float_(args):
             alg = t.n_rows * (8 + 1 + cols[name].element_size())
             print(json.dumps({"workload": f"float 200M rows, 64 groups, {name}", "m": m, "algo": args.algo,
                               "ms": ms, "alg_bytes": alg, "hbm_frac": alg / (ms * 1e-3) / 8e12}), flush=True)
+        # input rounding of the FP32 copy: both columns in one aggregation (FP64 accumulation of each), per
+        # (group, world) cell relative error of the FP32-input sum against the FP64-input sum
+        spec = AggSpec(n_rows=t.n_rows, pu_keys=pu, gcols=[g], gcards=[64], n_groups=64,
+                       cols=[cols["v64"], cols["v32"]])
+        st = new_state(spec, m)
+        pac_group_aggregate(ctx, spec, st, m=m, query_key=gen.query_key(4), algo=args.algo)
+        fs = st["fsum"].cpu().numpy()
+        ok = st["count"].cpu().numpy() > 0
+        rel = np.abs(fs[:, 1, :] - fs[:, 0, :])[ok] / np.abs(fs[:, 0, :])[ok]
+        print(json.dumps({"workload": "float 200M rows, 64 groups: FP32 input vs FP64 input", "m": m,
+                          "cells": int(ok.sum()), "rel_err_max": float(rel.max()),
+                          "rel_err_median": float(np.median(rel))}), flush=True)
     ctx.close()
 
 
