@@ -377,6 +377,47 @@ def test_many_groups_partitioned(ctx, torch_mod, m, algo):
     assert np.all(np.abs(got["fsum"] - want["fsum"]) <= 1e-12 * mag + 1e-300)
 
 
+# Column mixes of the partitioned form: (int columns, float columns).  The
+# aggregation loops are compiled per mix (integer-only mixes up to 3 columns;
+# float mixes (0,1), (1,1), (2,1), (0,2) keep counters in registers); the
+# others take the generic loops.  Mixed-sign values; ragged row count; 300
+# dense groups from a group-source column modulo G.
+_PART_MIXES = [(0, 0), (1, 0), (3, 0), (5, 0), (0, 1), (2, 1), (0, 2), (1, 2), (0, 3), (3, 2)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("mix", _PART_MIXES)
+def test_partitioned_column_mixes(ctx, torch_mod, m, mix):
+    import paper_2603_15023_amd as P
+    ni, nf = mix
+    g = np.random.default_rng(1000 + 10 * ni + nf)
+    n, G, K = 70_001, 300, 0x5151 + ni
+    pu = g.integers(1, 3001, size=n, dtype=np.int64)
+    gsrc = g.integers(0, 10_000, size=n, dtype=np.uint32)
+    icols = [g.integers(-10**12, 10**12, size=n, dtype=np.int64) for _ in range(ni)]
+    fcols = [g.lognormal(0.0, 2.0, size=n) * g.choice([-1.0, 1.0], size=n) for _ in range(nf)]
+    dev = torch_mod.device("cuda")
+    spec = P.AggSpec(n_rows=n, pu_keys=torch_mod.from_numpy(pu).to(dev),
+                     gcols=[torch_mod.from_numpy(gsrc.view(np.int32)).to(dev)], gcards=[10_000], group_mod=G,
+                     n_groups=G, cols=[torch_mod.from_numpy(c).to(dev) for c in icols + fcols])
+    st = P.new_state(spec, m)
+    _say("partitioned column mix", mix, m)
+    P.pac_group_aggregate(ctx, spec, st, m=m, query_key=K, algo="partition")
+    assert ctx.status() == 0
+    got = {k: v.cpu().numpy() for k, v in st.items()}
+    kw = dict(pu_keys=pu, query_key=K, gcols=[gsrc], gcards=[10_000], group_mod=G, n_groups=G, int_cols=icols)
+    want = ON.onepass(n, m, float_cols=fcols, **kw)
+    compare_counters(dict(got, fsum=np.zeros((G, 0, m))), dict(want, fsum=np.zeros((G, 0, m))))
+    if nf:
+        mag = ON.onepass(n, m, float_cols=[np.abs(c) for c in fcols], **kw)["fsum"]
+        assert np.all(np.abs(got["fsum"] - want["fsum"]) <= 1e-12 * mag + 1e-300)
+        # the deterministic form: a second run gives the same bits
+        st2 = P.new_state(spec, m)
+        P.pac_group_aggregate(ctx, spec, st2, m=m, query_key=K, algo="partition")
+        assert np.array_equal(st2["fsum"].cpu().numpy().view(np.int64), got["fsum"].view(np.int64))
+
+
 def test_partitioned_skewed_sparse_keys(ctx, torch_mod):
     """Zipf-skewed sparse keys: the head group spans many work items of the partitioned form."""
     import paper_2603_15023_amd as P
