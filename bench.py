@@ -17,6 +17,7 @@ on one GPU.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -49,6 +50,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv"])
     ap.add_argument("--compare-steps", type=int, default=5, help="steps timed for the other GPU forms")
+    ap.add_argument("--no-pipeline", dest="pipeline", action="store_false",
+                    help="time the steps one after another on one stream only")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shuffled", action="store_true", help="fact rows in random order instead of by order")
@@ -116,6 +119,7 @@ def main():
                         stats=stats)
     spec_kv.pu_keys = torch.from_numpy(t.pu_key[t.o_pu]).to(dev)
     state = P.new_state(spec, 64)
+    state2 = P.new_state(spec, 64)  # the second counter set of the pipelined steps
     cells = []
     for g in range(6):
         cells.append((g, P._abi.PAC_CELL_COUNT, 0))
@@ -141,6 +145,56 @@ def main():
             ev[1].record(stream)
         return P.pac_finalize(ctx, state, cells_t, len(cells), m=64, mi_budget=1.0 / 128, noise_seed=seed)
 
+    # Pipelined steps (a stream of queries over the resident tables): step i's
+    # hash and counter clearing run on a preparation stream while step i - 1
+    # aggregates, and its release (a7, one wave) on a release stream while step
+    # i + 1 aggregates.  Masks and counters are double-buffered; a buffer is
+    # reused only after the step that last read it has released.
+    ctx_prep, ctx_rel = P.Context(0), P.Context(0)
+    s_prep, s_rel = torch.cuda.Stream(), torch.cuda.Stream()
+    sets = [state, state2]
+    mask_sets = [masks, torch.empty_like(masks)]
+    specs = [spec, dataclasses.replace(spec, masks=mask_sets[1])]
+    ev_prep = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_agg = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_rel = [torch.cuda.Event(), torch.cuda.Event()]
+    for e in ev_rel:
+        e.record(stream)
+
+    def step_pipelined(i, ev=None):
+        b = i % 2
+        st = sets[b]
+        s_prep.wait_event(ev_rel[b])
+        with torch.cuda.stream(s_prep):
+            P.pac_hash_mask(ctx_prep, pu_key, K, 64, out=mask_sets[b])
+            for v in st.values():
+                v.zero_()
+            ev_prep[b].record(s_prep)
+        stream.wait_event(ev_prep[b])
+        if ev is not None:
+            ev[0].record(stream)
+        P.pac_group_aggregate(ctx, specs[b], st, m=64, query_key=K, algo=args.algo, init=False)
+        if ev is not None:
+            ev[1].record(stream)
+        ev_agg[b].record(stream)
+        s_rel.wait_event(ev_agg[b])
+        with torch.cuda.stream(s_rel):
+            out = P.pac_finalize(ctx_rel, st, cells_t, len(cells), m=64, mi_budget=1.0 / 128, noise_seed=seed)
+            ev_rel[b].record(s_rel)
+        return out
+
+    def run_pipelined(steps, warmup):
+        for i in range(warmup):
+            step_pipelined(i)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t_start = time.perf_counter()
+        for i in range(steps):
+            step_pipelined(i, evs[i])
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+        return total * 1e3 / steps, float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
     def run(algo, steps, warmup, latency_steps=0):
         for _ in range(warmup):
             step(algo)
@@ -164,6 +218,10 @@ def main():
         return total * 1e3 / steps, float(np.mean(agg_ms)), step_ms
 
     ms_step, agg_ms, step_ms = run(args.algo, args.steps, args.warmup, latency_steps=min(args.steps, 50))
+    ms_step_seq = ms_step
+    if args.pipeline and args.algo != "mfma_kv":
+        ms_step, agg_ms = run_pipelined(args.steps, args.warmup)
+        log(f"pipelined: {ms_step:.3f} ms/step (sequential {ms_step_seq:.3f}), aggregate kernel {agg_ms:.3f} ms")
 
     ctx.check()
     log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
@@ -226,6 +284,8 @@ def main():
                                f"({'shuffled' if args.shuffled else 'clustered by order'}), "
                                "6 groups, COUNT + SUM/AVG of 3 int64 cents columns, m=64, 42 released cells",
                    "algo": args.algo},
+        "pipelined": bool(args.pipeline and args.algo != "mfma_kv"),
+        "ms_per_step_sequential": ms_step_seq,
         "step_latency_ms": ({"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                              "max": float(np.max(step_ms))} if step_ms else None),
         "aggregate_rows_per_s": n / (agg_ms * 1e-3),
@@ -239,6 +299,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    ctx_prep.close()
+    ctx_rel.close()
     ctx.close()
 
 
