@@ -30,13 +30,14 @@ class _In(C.Structure):
         ("group_keys", C.c_void_p), ("filter_col", C.c_void_p), ("filter_lt", C.c_uint32),
         ("n_icols", C.c_int32), ("icols", C.c_void_p * MAX_COLS), ("icol_bytes", C.c_int32 * MAX_COLS),
         ("n_fcols", C.c_int32), ("fcols", C.c_void_p * MAX_COLS), ("fcol_bytes", C.c_int32 * MAX_COLS),
-        ("G", C.c_int64),
+        ("G", C.c_int64), ("minmax", C.c_int32),
     ]
 
 
 class _Out(C.Structure):
     _fields_ = [("count", C.c_void_p), ("isum", C.c_void_p), ("fsum", C.c_void_p), ("nrows", C.c_void_p),
-                ("keys", C.c_void_p), ("n_groups_out", C.c_int64), ("bad_rows", C.c_int64)]
+                ("keys", C.c_void_p), ("n_groups_out", C.c_int64), ("bad_rows", C.c_int64),
+                ("imin", C.c_void_p), ("imax", C.c_void_p), ("fmin", C.c_void_p), ("fmax", C.c_void_p)]
 
 
 def build(force: bool = True) -> str:
@@ -89,8 +90,11 @@ def onepass(n_rows: int, m: int = 64, *, masks: Optional[np.ndarray] = None,
             group_mod: int = 0, group_keys: Optional[np.ndarray] = None, n_groups: int = 1,
             filter_col: Optional[np.ndarray] = None, filter_lt: int = 0,
             int_cols: Sequence[np.ndarray] = (), float_cols: Sequence[np.ndarray] = (),
-            threads: Optional[int] = None) -> Dict[str, np.ndarray]:
-    """Per-world counters of the C oracle; arrays are used in place (no copies of big columns)."""
+            threads: Optional[int] = None, minmax: bool = False) -> Dict[str, np.ndarray]:
+    """Per-world counters of the C oracle; arrays are used in place (no copies of big columns).
+
+    ``minmax`` adds imin/imax [G][n_int][m] and fmin/fmax [G][n_float][m] (identity
+    INT64_MAX / INT64_MIN, +inf / -inf for a world without rows)."""
     keep = []
 
     def c(a, dt):
@@ -136,12 +140,20 @@ def onepass(n_rows: int, m: int = 64, *, masks: Optional[np.ndarray] = None,
         inp.fcols[i], inp.fcol_bytes[i] = _ptr(a), a.dtype.itemsize
     G = int(n_groups)
     inp.G = G
+    inp.minmax = int(minmax)
     out_count = np.zeros((G, m), dtype=np.int64)
     out_isum = np.zeros((G, len(int_cols), m), dtype=np.int64)
     out_fsum = np.zeros((G, len(float_cols), m), dtype=np.float64)
     out_nrows = np.zeros(G, dtype=np.int64)
     out_keys = np.zeros(G, dtype=np.int64)
-    out = _Out(_ptr(out_count), _ptr(out_isum), _ptr(out_fsum), _ptr(out_nrows), _ptr(out_keys), 0, 0)
+    mm = {}
+    if minmax:
+        mm = {"imin": np.zeros((G, len(int_cols), m), dtype=np.int64),
+              "imax": np.zeros((G, len(int_cols), m), dtype=np.int64),
+              "fmin": np.zeros((G, len(float_cols), m), dtype=np.float64),
+              "fmax": np.zeros((G, len(float_cols), m), dtype=np.float64)}
+    out = _Out(_ptr(out_count), _ptr(out_isum), _ptr(out_fsum), _ptr(out_nrows), _ptr(out_keys), 0, 0,
+               *[_ptr(mm.get(k)) for k in ("imin", "imax", "fmin", "fmax")])
     rc = lib().oracle_onepass(C.byref(inp), threads or default_threads(), C.byref(out))
     if rc != 0:
         raise RuntimeError(f"oracle_onepass failed: {rc}")
@@ -150,4 +162,6 @@ def onepass(n_rows: int, m: int = 64, *, masks: Optional[np.ndarray] = None,
            "bad_rows": out.bad_rows}
     if group_keys is not None:
         res["keys"] = out_keys[:ng]
+    for k, v in mm.items():
+        res[k] = v[:ng]
     return res

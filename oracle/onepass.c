@@ -11,11 +11,14 @@
  *     for every world j:  if pu[j] = 1:  count[g][j] += 1,
  *                                         isum[g][c][j] += v_c(t)   (mod 2^64)
  *                                         fsum[g][c][j] += f_c(t)   (Neumaier)
+ *                                         with minmax: imin/imax[g][c][j], fmin/fmax[g][c][j]
+ *                                         become min/max(., value)  (pac_min / pac_max)
  * pu is pac_hash_K of the PU key reached through the foreign-key chain
  * (Sec. 2, Relational Privacy Unit), or a precomputed mask row.
  * Float sums use Neumaier's compensated summation so that the result is
  * within a few ulps of the correctly rounded sum.
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -52,6 +55,7 @@ typedef struct {
   const void *fcols[OR_MAX_COLS];
   int32_t fcol_bytes[OR_MAX_COLS]; /* 4 or 8 */
   int64_t G;                       /* dense: number of groups; sparse: capacity */
+  int32_t minmax;                  /* also per-world MIN and MAX of every column */
 } oracle_in;
 
 typedef struct {
@@ -62,6 +66,8 @@ typedef struct {
   int64_t *keys;    /* sparse mode: group key of each output group, ascending */
   int64_t n_groups_out;
   int64_t bad_rows; /* rows whose link index or group value is out of range */
+  int64_t *imin, *imax; /* with minmax: [G][n_icols][m]; identity INT64_MAX / INT64_MIN */
+  double *fmin, *fmax;  /* with minmax: [G][n_fcols][m]; identity +inf / -inf        */
 } oracle_out;
 
 /* ---- splitmix64 (Steele, Lea, Flood 2014) ------------------------------ */
@@ -171,6 +177,8 @@ typedef struct {
   int64_t g_stride, g_rem; /* this thread owns groups with g % g_stride == g_rem */
   int64_t *count, *isum, *nrows;
   double *fsum, *fcomp;
+  int64_t *imin, *imax; /* minmax only */
+  double *fmin, *fmax;
   int64_t bad;
 } job;
 
@@ -215,6 +223,26 @@ static void *run_job(void *arg) {
       uint64_t v = (uint64_t)load_i(in->icols[c], in->icol_bytes[c], r);
       uint64_t *s = (uint64_t *)(jb->isum + (g * ni + c) * m);
       for (int j = 0; j < m; ++j) s[j] += v & (0 - ((mask[j >> 6] >> (j & 63)) & 1u));
+    }
+    if (in->minmax) {
+      for (int64_t c = 0; c < ni; ++c) {
+        int64_t v = load_i(in->icols[c], in->icol_bytes[c], r);
+        int64_t *lo = jb->imin + (g * ni + c) * m, *hi = jb->imax + (g * ni + c) * m;
+        for (int j = 0; j < m; ++j)
+          if ((mask[j >> 6] >> (j & 63)) & 1u) {
+            if (v < lo[j]) lo[j] = v;
+            if (v > hi[j]) hi[j] = v;
+          }
+      }
+      for (int64_t c = 0; c < nf; ++c) {
+        double v = load_f(in->fcols[c], in->fcol_bytes[c], r);
+        double *lo = jb->fmin + (g * nf + c) * m, *hi = jb->fmax + (g * nf + c) * m;
+        for (int j = 0; j < m; ++j)
+          if ((mask[j >> 6] >> (j & 63)) & 1u) {
+            if (v < lo[j]) lo[j] = v;
+            if (v > hi[j]) hi[j] = v;
+          }
+      }
     }
     for (int64_t c = 0; c < nf; ++c) {
       double v = load_f(in->fcols[c], in->fcol_bytes[c], r);
@@ -289,6 +317,7 @@ int oracle_onepass(const oracle_in *in, int nthreads, oracle_out *out) {
     if (split_groups && t > 0) {  /* share the output arrays: group slices are disjoint */
       jb->count = jobs[0].count; jb->isum = jobs[0].isum; jb->nrows = jobs[0].nrows;
       jb->fsum = jobs[0].fsum; jb->fcomp = jobs[0].fcomp;
+      jb->imin = jobs[0].imin; jb->imax = jobs[0].imax; jb->fmin = jobs[0].fmin; jb->fmax = jobs[0].fmax;
     } else {
       jb->count = (int64_t *)calloc((size_t)G * m + 1, 8);
       jb->isum = (int64_t *)calloc((size_t)G * ni * m + 1, 8);
@@ -296,6 +325,18 @@ int oracle_onepass(const oracle_in *in, int nthreads, oracle_out *out) {
       jb->fsum = (double *)calloc((size_t)G * nf * m + 1, 8);
       jb->fcomp = (double *)calloc((size_t)G * nf * m + 1, 8);
       if (!jb->count || !jb->isum || !jb->nrows || !jb->fsum || !jb->fcomp) rc = -2;
+      if (in->minmax) {
+        jb->imin = (int64_t *)malloc(((size_t)G * ni * m + 1) * 8);
+        jb->imax = (int64_t *)malloc(((size_t)G * ni * m + 1) * 8);
+        jb->fmin = (double *)malloc(((size_t)G * nf * m + 1) * 8);
+        jb->fmax = (double *)malloc(((size_t)G * nf * m + 1) * 8);
+        if (!jb->imin || !jb->imax || !jb->fmin || !jb->fmax) {
+          rc = -2;
+        } else {
+          for (int64_t i = 0; i < G * ni * m; ++i) { jb->imin[i] = INT64_MAX; jb->imax[i] = INT64_MIN; }
+          for (int64_t i = 0; i < G * nf * m; ++i) { jb->fmin[i] = INFINITY; jb->fmax[i] = -INFINITY; }
+        }
+      }
     }
   }
   if (rc == 0) {
@@ -325,11 +366,27 @@ int oracle_onepass(const oracle_in *in, int nthreads, oracle_out *out) {
     }
     for (int64_t i = 0; i < G * nf * m; ++i) out->fsum[i] += comp[i];
     free(comp);
+    if (in->minmax) {
+      for (int64_t i = 0; i < G * ni * m; ++i) { out->imin[i] = INT64_MAX; out->imax[i] = INT64_MIN; }
+      for (int64_t i = 0; i < G * nf * m; ++i) { out->fmin[i] = INFINITY; out->fmax[i] = -INFINITY; }
+      for (int t = 0; t < n_priv; ++t) {
+        job *jb = &jobs[t];
+        for (int64_t i = 0; i < G * ni * m; ++i) {
+          if (jb->imin[i] < out->imin[i]) out->imin[i] = jb->imin[i];
+          if (jb->imax[i] > out->imax[i]) out->imax[i] = jb->imax[i];
+        }
+        for (int64_t i = 0; i < G * nf * m; ++i) {
+          if (jb->fmin[i] < out->fmin[i]) out->fmin[i] = jb->fmin[i];
+          if (jb->fmax[i] > out->fmax[i]) out->fmax[i] = jb->fmax[i];
+        }
+      }
+    }
     for (int t = 0; t < nthreads; ++t) out->bad_rows += jobs[t].bad;
   }
   int n_alloc = split_groups ? 1 : nthreads;
   for (int t = 0; t < n_alloc; ++t) {
     free(jobs[t].count); free(jobs[t].isum); free(jobs[t].nrows); free(jobs[t].fsum); free(jobs[t].fcomp);
+    free(jobs[t].imin); free(jobs[t].imax); free(jobs[t].fmin); free(jobs[t].fmax);
   }
   free(jobs); free(th); free(gid);
   return rc;

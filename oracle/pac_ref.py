@@ -153,16 +153,23 @@ def _exact_group_sum(group: np.ndarray, values: np.ndarray, sel: np.ndarray, G: 
     return total.view(np.int64)
 
 
+INT64_MIN, INT64_MAX = -(1 << 63), (1 << 63) - 1
+
+
 def pac_agg_counters(pu: np.ndarray, group: np.ndarray, G: int, int_cols: Sequence[np.ndarray] = (),
-                     float_cols: Sequence[np.ndarray] = (), exact_float: bool = False) -> Dict[str, np.ndarray]:
+                     float_cols: Sequence[np.ndarray] = (), exact_float: bool = False,
+                     minmax: bool = False) -> Dict[str, np.ndarray]:
     """Per-group, per-world counters of the stochastic aggregates.
 
     For group g and world j (pac_agg's definition, r_j = agg over the rows
-    whose pu[j] = 1):
+    whose pu[j] = 1, agg in {sum, count, avg, min, max}):
         count[g][j]   = |{t in g : pu[j] = 1}|
         isum[g][c][j] = sum of int column c over those rows (exact, mod 2^64)
         fsum[g][c][j] = sum of float column c over those rows
         nrows[g]      = |{t in g}|  (rows reaching the aggregate)
+    and with ``minmax`` the per-world minimum and maximum of every column:
+        imin/imax[g][c][j], fmin/fmax[g][c][j]; a world without rows holds the
+        identity (INT64_MAX / INT64_MIN, +inf / -inf).
     Rows with group < 0 are filtered out.  ``exact_float`` uses math.fsum
     (correctly rounded) instead of a plain float64 accumulation.
     """
@@ -173,10 +180,26 @@ def pac_agg_counters(pu: np.ndarray, group: np.ndarray, G: int, int_cols: Sequen
     count = np.zeros((G, m), dtype=np.int64)
     isum = np.zeros((G, len(int_cols), m), dtype=np.int64)
     fsum = np.zeros((G, len(float_cols), m), dtype=np.float64)
+    if minmax:
+        imin = np.full((G, len(int_cols), m), INT64_MAX, dtype=np.int64)
+        imax = np.full((G, len(int_cols), m), INT64_MIN, dtype=np.int64)
+        fmin = np.full((G, len(float_cols), m), np.inf)
+        fmax = np.full((G, len(float_cols), m), -np.inf)
     for j in range(m):
         bit = ((pu[:, j // 64] >> np.uint64(j % 64)) & np.uint64(1)).astype(bool)
         sel = bit & valid
         count[:, j] = np.bincount(gv[sel], minlength=G)
+        if minmax:
+            for c, col in enumerate(int_cols):
+                lo, hi = imin[:, c, j].copy(), imax[:, c, j].copy()
+                np.minimum.at(lo, gv[sel], col[sel].astype(np.int64))
+                np.maximum.at(hi, gv[sel], col[sel].astype(np.int64))
+                imin[:, c, j], imax[:, c, j] = lo, hi
+            for c, col in enumerate(float_cols):
+                lo, hi = fmin[:, c, j].copy(), fmax[:, c, j].copy()
+                np.minimum.at(lo, gv[sel], col[sel].astype(np.float64))
+                np.maximum.at(hi, gv[sel], col[sel].astype(np.float64))
+                fmin[:, c, j], fmax[:, c, j] = lo, hi
         for c, col in enumerate(int_cols):
             isum[:, c, j] = _exact_group_sum(gv, col, sel, G)
         for c, col in enumerate(float_cols):
@@ -186,7 +209,10 @@ def pac_agg_counters(pu: np.ndarray, group: np.ndarray, G: int, int_cols: Sequen
             else:
                 fsum[:, c, j] = np.bincount(gv[sel], weights=col[sel].astype(np.float64), minlength=G)
     nrows = np.bincount(gv[valid], minlength=G).astype(np.int64)
-    return {"count": count, "isum": isum, "fsum": fsum, "nrows": nrows}
+    out = {"count": count, "isum": isum, "fsum": fsum, "nrows": nrows}
+    if minmax:
+        out.update(imin=imin, imax=imax, fmin=fmin, fmax=fmax)
+    return out
 
 
 def or_accumulator(pu: np.ndarray, group: np.ndarray, G: int) -> np.ndarray:
@@ -203,10 +229,28 @@ def or_accumulator(pu: np.ndarray, group: np.ndarray, G: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # brute force: m executions on m sampled databases  (Sec. 4.1 compile procedure)
 # ---------------------------------------------------------------------------
+def _minmax_lists(G: int, m: int, n_int: int, n_float: int) -> Dict[str, list]:
+    """Per-world MIN/MAX outputs of a brute-force run, every world at the identity."""
+    return {"imin": [[[INT64_MAX] * m for _ in range(n_int)] for _ in range(G)],
+            "imax": [[[INT64_MIN] * m for _ in range(n_int)] for _ in range(G)],
+            "fmin": [[[math.inf] * m for _ in range(n_float)] for _ in range(G)],
+            "fmax": [[[-math.inf] * m for _ in range(n_float)] for _ in range(G)]}
+
+
+def _group_minmax(out: Dict[str, list], g: int, j: int, rs: List[int], int_cols, float_cols) -> None:
+    """MIN and MAX of every column over the rows rs of group g in world j (the plain aggregate)."""
+    for c, col in enumerate(int_cols):
+        out["imin"][g][c][j] = min(int(col[r]) for r in rs)
+        out["imax"][g][c][j] = max(int(col[r]) for r in rs)
+    for c, col in enumerate(float_cols):
+        out["fmin"][g][c][j] = min(float(col[r]) for r in rs)
+        out["fmax"][g][c][j] = max(float(col[r]) for r in rs)
+
+
 def brute_force_star(pu_key: np.ndarray, o_pu: np.ndarray, f_order: np.ndarray, group: np.ndarray,
                      G: int, int_cols: Sequence[np.ndarray], float_cols: Sequence[np.ndarray],
                      query_key: int, m: int = 64, balanced: bool = False,
-                     row_filter: Optional[np.ndarray] = None) -> Dict[str, list]:
+                     row_filter: Optional[np.ndarray] = None, minmax: bool = False) -> Dict[str, list]:
     """Execute the plain grouped query once per sampled database instance.
 
     Step (1): S_j = sigma_{pac_hash_K(pk)[j] = 1}(PU); every relation with a
@@ -224,6 +268,7 @@ def brute_force_star(pu_key: np.ndarray, o_pu: np.ndarray, f_order: np.ndarray, 
     out_count = [[0] * m for _ in range(G)]
     out_isum = [[[0] * m for _ in int_cols] for _ in range(G)]
     out_fsum = [[[0.0] * m for _ in float_cols] for _ in range(G)]
+    mm = _minmax_lists(G, m, len(int_cols), len(float_cols)) if minmax else None
     for j in range(m):
         S_j = {u for u in range(n_pu) if world_bit(hashes[u], j)}            # sampled PU instance
         orders_j = {o for o in range(o_pu.shape[0]) if int(o_pu[o]) in S_j}   # orders join S_j
@@ -242,18 +287,21 @@ def brute_force_star(pu_key: np.ndarray, o_pu: np.ndarray, f_order: np.ndarray, 
                 out_isum[g][c][j] = ((s + (1 << 63)) % (1 << 64)) - (1 << 63)   # int64 wrap
             for c, col in enumerate(float_cols):
                 out_fsum[g][c][j] = math.fsum(float(col[r]) for r in rs)
-    return {"count": out_count, "isum": out_isum, "fsum": out_fsum}
+            if mm is not None:
+                _group_minmax(mm, g, j, rs, int_cols, float_cols)
+    return dict({"count": out_count, "isum": out_isum, "fsum": out_fsum}, **(mm or {}))
 
 
 def brute_force_flat(pu_key_rows: np.ndarray, group: np.ndarray, G: int, int_cols: Sequence[np.ndarray],
                      float_cols: Sequence[np.ndarray], query_key: int, m: int = 64,
-                     balanced: bool = False) -> Dict[str, list]:
+                     balanced: bool = False, minmax: bool = False) -> Dict[str, list]:
     """As ``brute_force_star`` for a fact table that carries the PU key itself."""
     keys = sorted({int(k) for k in pu_key_rows})
     hashes = {k: pac_hash(k, query_key, m, balanced) for k in keys}
     out_count = [[0] * m for _ in range(G)]
     out_isum = [[[0] * m for _ in int_cols] for _ in range(G)]
     out_fsum = [[[0.0] * m for _ in float_cols] for _ in range(G)]
+    mm = _minmax_lists(G, m, len(int_cols), len(float_cols)) if minmax else None
     for j in range(m):
         S_j = {k for k in keys if world_bit(hashes[k], j)}
         groups: Dict[int, List[int]] = {}
@@ -267,7 +315,9 @@ def brute_force_flat(pu_key_rows: np.ndarray, group: np.ndarray, G: int, int_col
                 out_isum[g][c][j] = ((s + (1 << 63)) % (1 << 64)) - (1 << 63)
             for c, col in enumerate(float_cols):
                 out_fsum[g][c][j] = math.fsum(float(col[r]) for r in rs)
-    return {"count": out_count, "isum": out_isum, "fsum": out_fsum}
+            if mm is not None:
+                _group_minmax(mm, g, j, rs, int_cols, float_cols)
+    return dict({"count": out_count, "isum": out_isum, "fsum": out_fsum}, **(mm or {}))
 
 
 # ---------------------------------------------------------------------------
@@ -327,6 +377,7 @@ def null_uniform(seed: int, cell: int) -> float:
 # release: cell vectors, NULL coin, pac_noised, posterior  (Sec. 4.1, Sec. 3.2, Sec. 5)
 # ---------------------------------------------------------------------------
 KIND_COUNT, KIND_SUM_I, KIND_SUM_F, KIND_AVG_I, KIND_AVG_F = 0, 1, 2, 3, 4
+KIND_MIN_I, KIND_MAX_I, KIND_MIN_F, KIND_MAX_F = 5, 6, 7, 8
 FLAG_SCALE2 = 1           # release count/sum times 2 (Sec. 2: each world sees about half the rows)
 FLAG_AVG_TOTALCOUNT = 2   # AVG_j = 2 * S_j / n_g instead of S_j / CNT_j
 FLAG_STRICT_DIVERSITY = 4
@@ -337,6 +388,12 @@ CELL_NULL, CELL_DIVERSITY, CELL_ZERO_VARIANCE = 1, 2, 4
 def cell_vector(counters: Dict[str, np.ndarray], group: int, kind: int, col: int, flags: int) -> np.ndarray:
     """y_j for one released cell, from the per-world counters (List of m results)."""
     cnt = counters["count"][group].astype(np.float64)
+    if kind in (KIND_MIN_I, KIND_MAX_I, KIND_MIN_F, KIND_MAX_F):
+        # pac_min / pac_max: the world's extreme value; reading: a world with no
+        # row counts as 0 (Sec. 3.2 NULLs), and no x2 scaling (it applies to
+        # COUNT and SUM only)
+        key = {KIND_MIN_I: "imin", KIND_MAX_I: "imax", KIND_MIN_F: "fmin", KIND_MAX_F: "fmax"}[kind]
+        return np.where(cnt > 0, counters[key][group][col].astype(np.float64), 0.0)
     if kind == KIND_COUNT:
         y = cnt.copy()
     elif kind in (KIND_SUM_I, KIND_AVG_I):

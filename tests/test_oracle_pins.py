@@ -262,3 +262,86 @@ def test_workload_generators_are_deterministic():
     assert a.cols["v1"].min() >= 100 and a.cols["v1"].max() <= 10_000_000
     c = gen.config1_flat(n=1000)
     assert c.cols["value"].min() >= 1 and c.cols["value"].max() <= 50
+
+
+# ----------------------------------------------------------------------------- pac_min / pac_max
+@pytest.mark.parametrize("m", [64, 128])
+def test_minmax_onepass_equals_m_executions_star(m):
+    """Sec. 4.2: r_j = min / max over the rows with pu[j] = 1 -- the per-world
+    counters equal the plain MIN/MAX of the m sampled databases."""
+    t = gen.tiny_star(21, n_pu=25, n_orders=60, n_rows=220, n_cols=2, float_cols=1, with_sel=True)
+    K, lt = 0x4321, 3 << 30
+    pu, group, G = _star_inputs(t, K, m, filter_lt=lt)
+    ints, flts = [t.cols["v0"], t.cols["v1"]], [t.cols["f0"]]
+    one = R.pac_agg_counters(pu, group, G, ints, flts, minmax=True)
+    bf = R.brute_force_star(t.pu_key, t.o_pu, t.f_order, R.dense_group(t.gcols, t.gcards), G, ints, flts, K, m,
+                            row_filter=t.sel < lt, minmax=True)
+    for k in ("imin", "imax"):
+        assert np.array_equal(one[k], np.array(bf[k], dtype=np.int64)), k
+    for k in ("fmin", "fmax"):
+        assert np.array_equal(one[k], np.array(bf[k])), k
+
+
+def test_minmax_flat_and_c_oracle_agree(oracle_native):
+    t = gen.tiny_flat(5, n_rows=400, n_keys=30, n_groups=4, value_range=(-10**15, 10**15))
+    K = 77
+    pu = R.pu_of_rows_flat(t.pu_key, K, 64)
+    group = R.dense_group(t.gcols, t.gcards)
+    f = np.random.default_rng(5).normal(size=t.n_rows) * 1e3
+    one = R.pac_agg_counters(pu, group, 4, [t.cols["v"]], [f], minmax=True)
+    bf = R.brute_force_flat(t.pu_key, group, 4, [t.cols["v"]], [f], K, 64, minmax=True)
+    c = oracle_native.onepass(t.n_rows, 64, pu_keys=t.pu_key, query_key=K, gcols=t.gcols, gcards=t.gcards,
+                              n_groups=4, int_cols=[t.cols["v"]], float_cols=[f], minmax=True, threads=3)
+    for k in ("imin", "imax", "fmin", "fmax"):
+        assert np.array_equal(one[k], np.array(bf[k], dtype=one[k].dtype)), k
+        assert np.array_equal(one[k], c[k]), k
+
+
+def test_minmax_special_masks_and_invariants():
+    g = np.random.default_rng(3)
+    n, G = 500, 6
+    group = g.integers(0, G, size=n)
+    v = g.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64)
+    f = g.standard_t(3, size=n)
+    plain = {"imin": np.array([v[group == k].min() for k in range(G)]),
+             "imax": np.array([v[group == k].max() for k in range(G)]),
+             "fmin": np.array([f[group == k].min() for k in range(G)]),
+             "fmax": np.array([f[group == k].max() for k in range(G)])}
+    # all-ones masks: every world is the whole table (the plain GROUP BY MIN / MAX)
+    c = R.pac_agg_counters(np.full((n, 1), np.uint64((1 << 64) - 1)), group, G, [v], [f], minmax=True)
+    for k, want in plain.items():
+        assert np.all(c[k][:, 0, :] == want[:, None]), k
+    # zero masks: no world sees a row, every entry stays at the identity
+    c0 = R.pac_agg_counters(np.zeros((n, 1), dtype=np.uint64), group, G, [v], [f], minmax=True)
+    assert np.all(c0["imin"] == R.INT64_MAX) and np.all(c0["imax"] == R.INT64_MIN)
+    assert np.all(c0["fmin"] == np.inf) and np.all(c0["fmax"] == -np.inf)
+    # a single world: only it holds the plain result
+    cj = R.pac_agg_counters(np.full((n, 1), np.uint64(1 << 40)), group, G, [v], [f], minmax=True)
+    assert np.all(cj["imax"][:, 0, 40] == plain["imax"]) and np.all(np.delete(cj["imax"], 40, axis=2) == R.INT64_MIN)
+    # random masks: min <= max where a world has rows; the extremes over the worlds
+    # are the extremes over the rows that reach any world; complement masks
+    # together cover every row
+    pu = R.pac_hash_np(g.integers(1, 60, size=n), 9, 64)
+    c = R.pac_agg_counters(pu, group, G, [v], [f], minmax=True)
+    cc = R.pac_agg_counters(~pu, group, G, [v], [f], minmax=True)
+    has = c["count"] > 0
+    assert np.all(c["imin"][:, 0, :][has] <= c["imax"][:, 0, :][has])
+    assert np.all(c["imin"][:, 0, :][~has] == R.INT64_MAX)
+    for k in range(G):
+        sel = (group == k) & (pu[:, 0] != 0)
+        assert c["imax"][k, 0].max() == v[sel].max() and c["fmin"][k, 0].min() == f[sel].min()
+    assert np.all(np.minimum(c["imin"], cc["imin"]) == plain["imin"][:, None, None])
+    assert np.all(np.maximum(c["fmax"], cc["fmax"]) == plain["fmax"][:, None, None])
+
+
+def test_minmax_cell_vector_zero_for_empty_worlds_and_unscaled():
+    cnt = np.array([[2, 0, 1, 0]])
+    counters = {"count": cnt, "nrows": np.array([3]),
+                "imin": np.array([[[5, R.INT64_MAX, -7, R.INT64_MAX]]]),
+                "imax": np.array([[[9, R.INT64_MIN, -7, R.INT64_MIN]]]),
+                "fmin": np.array([[[0.5, np.inf, -2.0, np.inf]]]),
+                "fmax": np.array([[[1.5, -np.inf, -2.0, -np.inf]]])}
+    assert np.array_equal(R.cell_vector(counters, 0, R.KIND_MIN_I, 0, R.FLAG_SCALE2), [5.0, 0.0, -7.0, 0.0])
+    assert np.array_equal(R.cell_vector(counters, 0, R.KIND_MAX_I, 0, R.FLAG_SCALE2), [9.0, 0.0, -7.0, 0.0])
+    assert np.array_equal(R.cell_vector(counters, 0, R.KIND_MIN_F, 0, 0), [0.5, 0.0, -2.0, 0.0])
+    assert np.array_equal(R.cell_vector(counters, 0, R.KIND_MAX_F, 0, R.FLAG_SCALE2), [1.5, 0.0, -2.0, 0.0])
