@@ -138,6 +138,17 @@ typedef struct {
   int64_t *nrows;       /* [G]               rows of g reaching the aggregate */
   int64_t *slot_keys;   /* sparse: [n_groups] key of each slot or PAC_EMPTY_KEY */
   int64_t *n_used;      /* sparse: [1] number of occupied slots                */
+  /* pac_min / pac_max (Sec. 4.2, agg in {min, max}; Sec. 5 lists them with the
+   * other stochastic aggregates): optional, all NULL to skip.  When any is
+   * non-NULL, imin and imax are required with int columns and fmin and fmax
+   * with float columns; only the plain form computes them (AUTO picks it;
+   * another explicit form returns PAC_ERR_UNSUPPORTED).  Accumulate semantics
+   * with min / max; a world that received no row holds the identity
+   * (INT64_MAX, INT64_MIN, +inf, -inf), which PAC_AGG_INIT writes. */
+  int64_t *imin;        /* [G][n_int][m]     per-world minimum of int columns  */
+  int64_t *imax;        /* [G][n_int][m]     per-world maximum of int columns  */
+  double *fmin;         /* [G][n_float][m]   per-world minimum of float columns */
+  double *fmax;         /* [G][n_float][m]   per-world maximum of float columns */
 } pac_agg_state;
 
 #define PAC_ALGO_AUTO 0u
@@ -161,12 +172,15 @@ int pac_group_aggregate_batch(pac_ctx *ctx, void *stream, const pac_agg_input *i
 
 /* ---- a7: release (Sec. 4.1 noise function pac_noised; Sec. 3.2 NULLs;
  * Sec. 5 Diversity Check; Sec. 2 adaptive composition) -------------------- */
+/* MIN / MAX cells release the world's extreme (a world without rows as 0,
+ * Sec. 3.2 NULLs) and are never scaled by PAC_FIN_SCALE2. */
 enum pac_cell_kind { PAC_CELL_COUNT = 0, PAC_CELL_SUM_I = 1, PAC_CELL_SUM_F = 2, PAC_CELL_AVG_I = 3,
-                     PAC_CELL_AVG_F = 4 };
+                     PAC_CELL_AVG_F = 4, PAC_CELL_MIN_I = 5, PAC_CELL_MAX_I = 6, PAC_CELL_MIN_F = 7,
+                     PAC_CELL_MAX_F = 8 };
 typedef struct {
   int64_t group;  /* group index (dense id or sparse slot) */
   int32_t kind;   /* pac_cell_kind */
-  int32_t col;    /* index among the int (SUM_I/AVG_I) or float (SUM_F/AVG_F) columns */
+  int32_t col;    /* index among the int (*_I kinds) or float (*_F kinds) columns */
 } pac_cell;
 
 #define PAC_FIN_SCALE2 1u            /* release count/sum times 2 (each world sees about half of the rows) */

@@ -23,6 +23,7 @@ PAC_AGG_INIT = 1
 PAC_EMPTY_KEY = -(1 << 63)
 PAC_STATUS_BAD_GROUP, PAC_STATUS_BAD_LINK, PAC_STATUS_TABLE_FULL, PAC_STATUS_DIVERSITY = 1, 2, 4, 8
 PAC_CELL_COUNT, PAC_CELL_SUM_I, PAC_CELL_SUM_F, PAC_CELL_AVG_I, PAC_CELL_AVG_F = 0, 1, 2, 3, 4
+PAC_CELL_MIN_I, PAC_CELL_MAX_I, PAC_CELL_MIN_F, PAC_CELL_MAX_F = 5, 6, 7, 8
 PAC_FIN_SCALE2, PAC_FIN_AVG_TOTALCOUNT, PAC_FIN_STRICT_DIVERSITY, PAC_FIN_FIXED_PRIOR, PAC_FIN_PRIOR_IN = 1, 2, 4, 8, 16
 PAC_CELL_NULL, PAC_CELL_DIVERSITY, PAC_CELL_ZERO_VARIANCE = 1, 2, 4
 
@@ -44,7 +45,8 @@ class AggInput(C.Structure):
 
 class AggState(C.Structure):
     _fields_ = [("count", C.c_void_p), ("isum", C.c_void_p), ("fsum", C.c_void_p), ("nrows", C.c_void_p),
-                ("slot_keys", C.c_void_p), ("n_used", C.c_void_p)]
+                ("slot_keys", C.c_void_p), ("n_used", C.c_void_p),
+                ("imin", C.c_void_p), ("imax", C.c_void_p), ("fmin", C.c_void_p), ("fmax", C.c_void_p)]
 
 
 class Cell(C.Structure):

@@ -156,8 +156,10 @@ class AggSpec:
         return s
 
 
-def new_state(spec: AggSpec, m: int = 64, device=None) -> Dict[str, torch.Tensor]:
-    """Allocates (uninitialised) device counters for ``spec``; pass PAC_AGG_INIT on first use."""
+def new_state(spec: AggSpec, m: int = 64, device=None, minmax: bool = False) -> Dict[str, torch.Tensor]:
+    """Allocates (uninitialised) device counters for ``spec``; pass PAC_AGG_INIT on first use.
+
+    ``minmax`` adds the per-world MIN / MAX arrays (imin, imax, fmin, fmax)."""
     dev = device if device is not None else torch.device("cuda")
     G = int(spec.n_groups)
     st = {
@@ -169,6 +171,10 @@ def new_state(spec: AggSpec, m: int = 64, device=None) -> Dict[str, torch.Tensor
     if spec.group_keys is not None:
         st["slot_keys"] = torch.empty((G,), dtype=torch.int64, device=dev)
         st["n_used"] = torch.empty((1,), dtype=torch.int64, device=dev)
+    if minmax:
+        for k, dt, n in (("imin", torch.int64, spec.n_int), ("imax", torch.int64, spec.n_int),
+                         ("fmin", torch.float64, spec.n_float), ("fmax", torch.float64, spec.n_float)):
+            st[k] = torch.empty((G, max(n, 0), m), dtype=dt, device=dev)
     return st
 
 
@@ -180,6 +186,9 @@ def _state_c(st: Dict[str, torch.Tensor]) -> A.AggState:
     s.fsum = _ptr(st["fsum"]) if st["fsum"].numel() else None
     s.slot_keys = _ptr(st.get("slot_keys"))
     s.n_used = _ptr(st.get("n_used"))
+    for k in ("imin", "imax", "fmin", "fmax"):  # MIN / MAX arrays, if the state has them
+        if k in st:
+            setattr(s, k, _ptr(st[k]) if st[k].numel() else None)
     return s
 
 
@@ -207,7 +216,8 @@ def pac_group_aggregate_batch(ctx: Context, specs: Sequence[AggSpec], states: Se
 
 
 CELL_KINDS = {"count": A.PAC_CELL_COUNT, "sum_i": A.PAC_CELL_SUM_I, "sum_f": A.PAC_CELL_SUM_F,
-              "avg_i": A.PAC_CELL_AVG_I, "avg_f": A.PAC_CELL_AVG_F}
+              "avg_i": A.PAC_CELL_AVG_I, "avg_f": A.PAC_CELL_AVG_F, "min_i": A.PAC_CELL_MIN_I,
+              "max_i": A.PAC_CELL_MAX_I, "min_f": A.PAC_CELL_MIN_F, "max_f": A.PAC_CELL_MAX_F}
 
 
 def cells_tensor(cells: Sequence[Tuple[int, int, int]], device=None) -> torch.Tensor:

@@ -15,6 +15,15 @@
 // Cost: about (2 + 2*ints + 2*floats) readlanes plus one LDS read-add-write
 // per counter per row: VALU/LDS bound, several times the HBM time.  It is the
 // baseline the ballot and matrix-core forms are measured against.
+//
+// It is also the form of pac_min / pac_max (Sec. 4.2, agg in {min, max}):
+// with a MIN/MAX state, each group's region carries per-world minimum and
+// maximum words of every column after the sums, updated by LDS min/max
+// atomics under the same predicate.  Min and max are exact in any order.  The
+// paper's bound pruning (Sec. 5: skip values that cannot improve the worst of
+// the 64 extremes) saves 64 scalar compare-and-selects per value on a CPU;
+// here the 64 worlds are the lanes of one predicated LDS instruction, so there
+// is nothing to prune.
 #include <algorithm>
 
 #include "pac_internal.h"
@@ -30,9 +39,22 @@ __global__ __launch_bounds__(256) void agg_plain_lds(DevInput in, DevState st, u
   constexpr int m = 64 * W;
   const int ni = in.n_icols, nf = in.n_fcols, A = 1 + ni + nf;
   const int64_t G = in.n_groups;
-  const int64_t gstride = (int64_t)A * m + 1;  // per-group slots: A*m counters + nrows
+  const bool mm = st.minmax != 0;
+  // per-group slots: A*m counters + nrows, then (MIN/MAX) imin, imax [ni][m], fmin, fmax [nf][m]
+  const int64_t mm_off = (int64_t)A * m + 1;
+  const int64_t gstride = mm_off + (mm ? (int64_t)2 * (ni + nf) * m : 0);
   const int64_t region = G * gstride;
-  for (int64_t i = threadIdx.x; i < region * waves_per_block; i += blockDim.x) lds[i] = 0;
+  for (int64_t i = threadIdx.x; i < region * waves_per_block; i += blockDim.x) {
+    const int64_t off = (i % region) % gstride;
+    uint64_t v = 0;
+    if (off >= mm_off) {
+      const int64_t sec = (off - mm_off) / m;
+      v = sec < ni ? (uint64_t)INT64_MAX
+                   : sec < 2 * ni ? (uint64_t)INT64_MIN
+                                  : (uint64_t)__double_as_longlong(sec < 2 * ni + nf ? INFINITY : -INFINITY);
+    }
+    lds[i] = v;
+  }
   __syncthreads();
   uint64_t *my = lds + (int64_t)wave * region;
   const int64_t n_chunks = (in.n_rows + 63) >> 6;
@@ -71,6 +93,26 @@ __global__ __launch_bounds__(256) void agg_plain_lds(DevInput in, DevState st, u
                 __hip_atomic_fetch_add((double *)&base[(int64_t)(1 + ni + c) * m + j],
                                        __longlong_as_double((long long)rf[c]), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (mm) {
+              long long *mi = (long long *)(base + mm_off);
+#pragma unroll
+              for (int c = 0; c < kMaxCols; ++c)
+                if (c < ni) {
+                  __hip_atomic_fetch_min(&mi[(int64_t)c * m + j], (long long)rv[c], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                  __hip_atomic_fetch_max(&mi[(int64_t)(ni + c) * m + j], (long long)rv[c], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+              double *mf = (double *)(base + mm_off + (int64_t)2 * ni * m);
+#pragma unroll
+              for (int c = 0; c < kMaxCols; ++c)
+                if (c < nf) {
+                  const double x = __longlong_as_double((long long)rf[c]);
+                  __hip_atomic_fetch_min(&mf[(int64_t)c * m + j], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                  __hip_atomic_fetch_max(&mf[(int64_t)(nf + c) * m + j], x, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
           }
         }
       }
@@ -80,6 +122,33 @@ __global__ __launch_bounds__(256) void agg_plain_lds(DevInput in, DevState st, u
   // flush: sum the wave regions (fixed order), ints by atomics, floats as block partials
   for (int64_t i = threadIdx.x; i < region; i += blockDim.x) {
     const int64_t g = i / gstride, off = i % gstride;
+    if (off > (int64_t)A * m) {  // MIN / MAX: extreme over the waves, then to the state if any row came
+      const int64_t sec = (off - mm_off) / m, j = (off - mm_off) % m;
+      if (sec < 2 * ni) {
+        const bool is_min = sec < ni;
+        const int64_t c = is_min ? sec : sec - ni;
+        long long x = (long long)lds[i];
+        for (int w = 1; w < waves_per_block; ++w) {
+          const long long y = (long long)lds[(int64_t)w * region + i];
+          x = is_min ? (y < x ? y : x) : (y > x ? y : x);
+        }
+        long long *dst = (long long *)(is_min ? st.imin : st.imax) + (g * ni + c) * m + j;
+        if (is_min && x != INT64_MAX) __hip_atomic_fetch_min(dst, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!is_min && x != INT64_MIN) __hip_atomic_fetch_max(dst, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const bool is_min = sec < 2 * ni + nf;
+        const int64_t c = is_min ? sec - 2 * ni : sec - 2 * ni - nf;
+        double x = __longlong_as_double((long long)lds[i]);
+        for (int w = 1; w < waves_per_block; ++w) {
+          const double y = __longlong_as_double((long long)lds[(int64_t)w * region + i]);
+          x = is_min ? (y < x ? y : x) : (y > x ? y : x);
+        }
+        double *dst = (is_min ? st.fmin : st.fmax) + (g * nf + c) * m + j;
+        if (is_min && x != INFINITY) __hip_atomic_fetch_min(dst, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!is_min && x != -INFINITY) __hip_atomic_fetch_max(dst, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      continue;
+    }
     if (off == (int64_t)A * m) {
       uint64_t s = 0;
       for (int w = 0; w < waves_per_block; ++w) s += lds[(int64_t)w * region + i];
@@ -150,15 +219,35 @@ __global__ __launch_bounds__(256) void agg_plain_global(DevInput in, DevState st
 #pragma unroll
           for (int c = 0; c < kMaxCols; ++c)
             if (c < nf) atomicAdd(&st.fsum[(gg * nf + c) * m + j], __longlong_as_double((long long)rf[c]));
+          if (st.minmax) {
+#pragma unroll
+            for (int c = 0; c < kMaxCols; ++c)
+              if (c < ni) {
+                const int64_t o = (gg * ni + c) * m + j;
+                __hip_atomic_fetch_min((long long *)&st.imin[o], (long long)rv[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max((long long *)&st.imax[o], (long long)rv[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+              }
+#pragma unroll
+            for (int c = 0; c < kMaxCols; ++c)
+              if (c < nf) {
+                const int64_t o = (gg * nf + c) * m + j;
+                const double x = __longlong_as_double((long long)rf[c]);
+                __hip_atomic_fetch_min(&st.fmin[o], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&st.fmax[o], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              }
+          }
         }
       }
     }
   }
 }
 
-static int64_t plain_region_bytes(const DevInput &in) {
+static int64_t plain_region_bytes(const DevInput &in, bool minmax = false) {
   const int64_t A = 1 + in.n_icols + in.n_fcols;
-  return in.n_groups * (A * in.m + 1) * 8;
+  const int64_t mm = minmax ? 2 * (int64_t)(in.n_icols + in.n_fcols) * in.m : 0;
+  return in.n_groups * (A * in.m + 1 + mm) * 8;
 }
 
 static constexpr int64_t kLdsBudget = 160 * 1024;
@@ -170,9 +259,9 @@ struct PlainPlan {
   int64_t lds_bytes;
 };
 
-static PlainPlan plain_plan(const LaunchEnv &env, const DevInput &in) {
+static PlainPlan plain_plan(const LaunchEnv &env, const DevInput &in, bool minmax) {
   PlainPlan p{};
-  const int64_t region = plain_region_bytes(in);
+  const int64_t region = plain_region_bytes(in, minmax);
   const int64_t n_chunks = (in.n_rows + 63) / 64;
   p.lds = !in.group_keys && region <= kLdsBudget;
   if (p.lds) {
@@ -195,8 +284,8 @@ bool plain_fits_lds(const DevInput &in) { return !in.group_keys && plain_region_
 // Whether four wave-private regions fit (enough waves per CU to hide latency).
 bool plain_fits_lds4(const DevInput &in) { return !in.group_keys && 4 * plain_region_bytes(in) <= kLdsBudget; }
 
-size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in) {
-  const PlainPlan p = plain_plan(env, in);
+size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in, bool minmax) {
+  const PlainPlan p = plain_plan(env, in, minmax);
   if (!p.lds || in.n_fcols == 0) return 0;
   return (size_t)p.blocks * (size_t)in.n_groups * in.n_fcols * in.m * sizeof(double);
 }
@@ -204,13 +293,13 @@ size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in) {
 hipError_t launch_agg_plain(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
                             size_t scratch_bytes) {
   if (in.n_rows <= 0) return hipSuccess;
-  const PlainPlan p = plain_plan(env, in);
+  const PlainPlan p = plain_plan(env, in, st.minmax != 0);
   if (p.lds) {
     const void *fn = in.W == 1 ? (const void *)agg_plain_lds<1> : (const void *)agg_plain_lds<2>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
     if (e != hipSuccess) return e;
     double *fpart = (double *)scratch;
-    if (in.n_fcols > 0 && scratch_bytes < plain_scratch_bytes(env, in)) return hipErrorInvalidValue;
+    if (in.n_fcols > 0 && scratch_bytes < plain_scratch_bytes(env, in, st.minmax != 0)) return hipErrorInvalidValue;
     if (in.W == 1)
       hipLaunchKernelGGL(agg_plain_lds<1>, dim3(p.blocks), dim3(64 * p.wpb), (size_t)p.lds_bytes, env.stream, in, st,
                          env.status, fpart, p.wpb);

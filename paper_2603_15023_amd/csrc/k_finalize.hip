@@ -4,8 +4,9 @@
 // The posterior P over the m worlds changes after every released cell, so
 // the chain over cells is sequential by definition.  Everything that does not
 // depend on P runs first, in parallel, one wavefront per cell (phase 1): the
-// world vector y of the cell (COUNT / SUM / AVG of the per-world counters,
-// doubled for COUNT/SUM), the number of worlds that received a row, the
+// world vector y of the cell (COUNT / SUM / AVG / MIN / MAX of the per-world
+// counters, doubled for COUNT/SUM, a world without rows as 0 for AVG / MIN /
+// MAX), the number of worlds that received a row, the
 // diversity flag and the cell's random draws.  Phase 2 is one wavefront that
 // streams those vectors in cell order (several cells in flight) and applies
 // the noise rule and the Bayesian update with DPP wave reductions.
@@ -63,10 +64,15 @@ __global__ __launch_bounds__(256) void cell_vectors_kernel(DevState st, const pa
   const int64_t c = c0 + ci;
   const pac_cell cell = cells[c];
   const int64_t g = cell.group;
-  const int ncol = (cell.kind == PAC_CELL_SUM_I || cell.kind == PAC_CELL_AVG_I) ? fp.n_int
-                   : (cell.kind == PAC_CELL_SUM_F || cell.kind == PAC_CELL_AVG_F) ? fp.n_float : 1;
-  if (g < 0 || g >= fp.n_groups || cell.kind < 0 || cell.kind > PAC_CELL_AVG_F ||
-      (cell.kind != PAC_CELL_COUNT && (cell.col < 0 || cell.col >= ncol))) {
+  const bool ext_i = cell.kind == PAC_CELL_MIN_I || cell.kind == PAC_CELL_MAX_I;
+  const bool ext_f = cell.kind == PAC_CELL_MIN_F || cell.kind == PAC_CELL_MAX_F;
+  const int ncol = (cell.kind == PAC_CELL_SUM_I || cell.kind == PAC_CELL_AVG_I || ext_i) ? fp.n_int
+                   : (cell.kind == PAC_CELL_SUM_F || cell.kind == PAC_CELL_AVG_F || ext_f) ? fp.n_float : 1;
+  const int64_t *ext_ip = cell.kind == PAC_CELL_MIN_I ? st.imin : st.imax;
+  const double *ext_fp = cell.kind == PAC_CELL_MIN_F ? st.fmin : st.fmax;
+  if (g < 0 || g >= fp.n_groups || cell.kind < 0 || cell.kind > PAC_CELL_MAX_F ||
+      (cell.kind != PAC_CELL_COUNT && (cell.col < 0 || cell.col >= ncol)) || (ext_i && !ext_ip) ||
+      (ext_f && !ext_fp)) {
     if (lane == 0) {
       atomicOr(status, PAC_STATUS_BAD_GROUP);
       meta[ci] = CellMeta{0.0, PAC_CELL_NULL, 1u};
@@ -86,9 +92,15 @@ __global__ __launch_bounds__(256) void cell_vectors_kernel(DevState st, const pa
       case PAC_CELL_COUNT: v = (double)cnt; break;
       case PAC_CELL_SUM_I:
       case PAC_CELL_AVG_I: v = (double)st.isum[(g * fp.n_int + cell.col) * m + j]; break;
+      case PAC_CELL_MIN_I:
+      case PAC_CELL_MAX_I: v = cnt > 0 ? (double)ext_ip[(g * fp.n_int + cell.col) * m + j] : 0.0; break;
+      case PAC_CELL_MIN_F:
+      case PAC_CELL_MAX_F: v = cnt > 0 ? ext_fp[(g * fp.n_float + cell.col) * m + j] : 0.0; break;
       default: v = st.fsum[(g * fp.n_float + cell.col) * m + j]; break;
     }
-    if (cell.kind == PAC_CELL_AVG_I || cell.kind == PAC_CELL_AVG_F) {
+    if (ext_i || ext_f) {
+      // the world's extreme as it is: no x2 scaling
+    } else if (cell.kind == PAC_CELL_AVG_I || cell.kind == PAC_CELL_AVG_F) {
       if (fp.flags & PAC_FIN_AVG_TOTALCOUNT) {
         const double nr = (double)st.nrows[g];
         v = nr > 0.0 ? (2.0 * v) / nr : 0.0;

@@ -184,10 +184,20 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
   ds->nrows = st->nrows;
   ds->slot_keys = st->slot_keys;
   ds->n_used = st->n_used;
+  ds->imin = st->imin;
+  ds->imax = st->imax;
+  ds->fmin = st->fmin;
+  ds->fmax = st->fmax;
+  ds->minmax = (st->imin || st->imax || st->fmin || st->fmax) ? 1 : 0;
+  if (ds->minmax && d->n_icols > 0 && !(st->imin && st->imax))
+    return fail(PAC_ERR_INVALID, "state.imin and state.imax required for MIN/MAX of int columns");
+  if (ds->minmax && d->n_fcols > 0 && !(st->fmin && st->fmax))
+    return fail(PAC_ERR_INVALID, "state.fmin and state.fmax required for MIN/MAX of float columns");
   return PAC_OK;
 }
 
-uint32_t choose_algo(const pac::DevInput &d) {
+uint32_t choose_algo(const pac::DevInput &d, const pac::DevState &ds) {
+  if (ds.minmax) return PAC_ALGO_PLAIN;  // per-world MIN / MAX: the plain form only
   // counters that do not fit in LDS (many groups, sparse keys): partition the rows by group
   if (!pac::plain_fits_lds(d) && pac::part_supported(d) && d.n_rows >= 4096) return PAC_ALGO_PARTITION;
   // float columns whose wave-private regions would leave fewer than four waves per workgroup
@@ -218,14 +228,19 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
     if (e == hipSuccess) e = pac::launch_fill_i64(env, ds.nrows, G, 0);
     if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.slot_keys, G, PAC_EMPTY_KEY);
     if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.n_used, 1, 0);
+    if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imin, G * d.n_icols * m, INT64_MAX);
+    if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imax, G * d.n_icols * m, INT64_MIN);
+    if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmin, G * d.n_fcols * m, INFINITY);
+    if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmax, G * d.n_fcols * m, -INFINITY);
     if (e != hipSuccess) return hip_fail(e, "state init");
   }
   if (d.n_rows == 0) return PAC_OK;
-  if (algo == PAC_ALGO_AUTO) algo = choose_algo(d);
+  if (algo == PAC_ALGO_AUTO) algo = choose_algo(d, ds);
+  if (ds.minmax && algo != PAC_ALGO_PLAIN) return fail(PAC_ERR_UNSUPPORTED, "MIN/MAX counters need the plain form");
   hipError_t e = hipSuccess;
   switch (algo) {
     case PAC_ALGO_PLAIN: {
-      const size_t need = pac::plain_scratch_bytes(env, d);
+      const size_t need = pac::plain_scratch_bytes(env, d, ds.minmax != 0);
       if (need) {
         rc = ensure_scratch(ctx, need);
         if (rc != PAC_OK) return rc;
@@ -384,7 +399,8 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
   if (n_int > 0 && !state->isum) return fail(PAC_ERR_INVALID, "state.isum missing");
   if (n_float > 0 && !state->fsum) return fail(PAC_ERR_INVALID, "state.fsum missing");
   DeviceGuard guard(ctx->device);
-  pac::DevState ds{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used};
+  pac::DevState ds{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used,
+                   state->imin,  state->imax, state->fmin, state->fmax,  0};
   pac::FinParams fp{params->mi_budget, params->noise_seed, params->j_star, params->flags, m, n_int, n_float, n_cells, n_groups};
   pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
   const int rc = ensure_scratch(ctx, pac::finalize_scratch_bytes(m, n_cells));

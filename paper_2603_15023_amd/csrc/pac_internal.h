@@ -54,6 +54,9 @@ struct DevState {
   int64_t *nrows;
   int64_t *slot_keys;
   int64_t *n_used;
+  int64_t *imin, *imax;  // per-world MIN / MAX (plain form only); `minmax` says whether they are wanted
+  double *fmin, *fmax;
+  int32_t minmax;
 };
 
 // ---------------------------------------------------------------- hashing
@@ -249,7 +252,7 @@ hipError_t launch_fill_i64(const LaunchEnv &env, int64_t *p, int64_t n, int64_t 
 hipError_t launch_fill_f64(const LaunchEnv &env, double *p, int64_t n, double v);
 hipError_t launch_agg_plain(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
                             size_t scratch_bytes);
-size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in);
+size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in, bool minmax);
 hipError_t launch_agg_ballot(const LaunchEnv &env, const DevInput &in, const DevState &st);
 bool ballot_supported(const DevInput &in);
 hipError_t launch_agg_mfma(const LaunchEnv &env, const DevInput &in, const DevState &st);
