@@ -3,6 +3,7 @@
     python -m paper_2603_15023_amd.bench_workloads zipf   [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads float  [--reps 3] [--algo auto]
     python -m paper_2603_15023_amd.bench_workloads serve  [--queries 64] [--slots 4] [--load 0.7]
+    python -m paper_2603_15023_amd.bench_workloads minmax [--reps 3] [--oracle-rows 20000000]
 
 zipf:  100M rows, 2M PU keys per row, group keys Zipf(1.1) over 1M ranks
        (HBM hash table), SUM int64 + COUNT, m = 64.
@@ -10,6 +11,9 @@ float: 200M rows, 4M PU keys per row, 64 uniform groups, lognormal(0, 2)
        FP64 values and their FP32 copy; m = 64 and 128.
 serve: the served workload (100M-row resident star schema, queries of mixed
        selectivity, group count and aggregates) through the slot server.
+minmax: the float table's rows with 8 groups (its group column mod 8): COUNT,
+       SUM, MIN and MAX of the FP64 column per world, m = 64, against the same
+       query without MIN/MAX, and the C oracle timed on a row prefix.
 
 Each prints one JSON line per configuration: milliseconds per aggregation
 (mean of --reps after one warm-up) and the algorithmic bytes of the input.
@@ -87,6 +91,34 @@ def float_(args):
     ctx.close()
 
 
+def minmax(args):
+    from workloads import gen
+    t = gen.config4_float()
+    dev = torch.device("cuda")
+    ctx = Context(0)
+    pu, g = torch.from_numpy(t.pu_key).to(dev), torch.from_numpy(t.gcols[0]).to(dev)
+    v = torch.from_numpy(t.cols["v64"]).to(dev)
+    spec = AggSpec(n_rows=t.n_rows, pu_keys=pu, gcols=[g], gcards=[64], group_mod=8, n_groups=8, cols=[v])
+    alg = t.n_rows * 17
+    K = gen.query_key(4)
+    for mm in (False, True):
+        st = new_state(spec, 64, minmax=mm)
+        ms = _time(ctx, spec, st, 64, K, args.algo, args.reps)
+        print(json.dumps({"workload": "float 200M rows, 8 groups: COUNT, SUM" + (", MIN, MAX" if mm else ""),
+                          "m": 64, "ms": ms, "rows_per_s": t.n_rows / (ms * 1e-3), "alg_bytes": alg,
+                          "hbm_frac": alg / (ms * 1e-3) / 8e12}), flush=True)
+    ctx.close()
+    if args.oracle_rows > 0:
+        from oracle import native as ON
+        n = min(args.oracle_rows, t.n_rows)
+        t0 = time.perf_counter()
+        ON.onepass(n, 64, pu_keys=t.pu_key, query_key=K, gcols=[t.gcols[0][:n]], gcards=[64], group_mod=8,
+                   n_groups=8, float_cols=[t.cols["v64"][:n]], minmax=True)
+        el = time.perf_counter() - t0
+        print(json.dumps({"workload": "C oracle, same query with MIN/MAX", "rows": n, "s": el,
+                          "rows_per_s": n / el, "threads": ON.default_threads()}), flush=True)
+
+
 def serve(args):
     from workloads import gen
     from .serve import ResidentStar, Server, latency_summary
@@ -105,14 +137,15 @@ def serve(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["zipf", "float", "serve"])
+    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax"])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--queries", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--load", type=float, default=0.7)
+    ap.add_argument("--oracle-rows", type=int, default=20_000_000)
     args = ap.parse_args(argv)
-    {"zipf": zipf, "float": float_, "serve": serve}[args.what](args)
+    {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax}[args.what](args)
 
 
 if __name__ == "__main__":
