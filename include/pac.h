@@ -141,8 +141,8 @@ typedef struct {
   /* pac_min / pac_max (Sec. 4.2, agg in {min, max}; Sec. 5 lists them with the
    * other stochastic aggregates): optional, all NULL to skip.  When any is
    * non-NULL, imin and imax are required with int columns and fmin and fmax
-   * with float columns; only the plain form computes them (AUTO picks it;
-   * another explicit form returns PAC_ERR_UNSUPPORTED).  Accumulate semantics
+   * with float columns; the plain and register forms compute them (AUTO picks
+   * one; another explicit form returns PAC_ERR_UNSUPPORTED).  Accumulate semantics
    * with min / max; a world that received no row holds the identity
    * (INT64_MAX, INT64_MIN, +inf, -inf), which PAC_AGG_INIT writes. */
   int64_t *imin;        /* [G][n_int][m]     per-world minimum of int columns  */
@@ -156,6 +156,8 @@ typedef struct {
 #define PAC_ALGO_BALLOT 2u  /* ballot transpose of world bits, popcounts of bit-sliced values (ints) */
 #define PAC_ALGO_MFMA_I8 3u /* int8 matrix cores on byte digits, exact int32 -> int64 recombination */
 #define PAC_ALGO_PARTITION 4u /* many groups: rows radix-partitioned by group slot, each partition in LDS */
+#define PAC_ALGO_REGISTER 5u  /* few groups (<= 8 at m = 64, <= 4 at m = 128): the plain form with every counter
+                                 in registers; up to 3 columns (2 with MIN/MAX) */
 #define PAC_AGG_INIT 1u     /* clear the state (and the sparse table) before aggregating */
 
 /* m in {64, 128}; query_key is used by the fused hash.  Returns

@@ -197,7 +197,9 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
 }
 
 uint32_t choose_algo(const pac::DevInput &d, const pac::DevState &ds) {
-  if (ds.minmax) return PAC_ALGO_PLAIN;  // per-world MIN / MAX: the plain form only
+  // float columns or per-world MIN / MAX over a few groups: counters in registers
+  if ((d.n_fcols > 0 || ds.minmax) && pac::reg_supported(d, ds.minmax != 0)) return PAC_ALGO_REGISTER;
+  if (ds.minmax) return PAC_ALGO_PLAIN;  // MIN / MAX otherwise: the plain form
   // counters that do not fit in LDS (many groups, sparse keys): partition the rows by group
   if (!pac::plain_fits_lds(d) && pac::part_supported(d) && d.n_rows >= 4096) return PAC_ALGO_PARTITION;
   // float columns whose wave-private regions would leave fewer than four waves per workgroup
@@ -236,7 +238,8 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
   }
   if (d.n_rows == 0) return PAC_OK;
   if (algo == PAC_ALGO_AUTO) algo = choose_algo(d, ds);
-  if (ds.minmax && algo != PAC_ALGO_PLAIN) return fail(PAC_ERR_UNSUPPORTED, "MIN/MAX counters need the plain form");
+  if (ds.minmax && algo != PAC_ALGO_PLAIN && algo != PAC_ALGO_REGISTER)
+    return fail(PAC_ERR_UNSUPPORTED, "MIN/MAX counters need the plain or register form");
   hipError_t e = hipSuccess;
   switch (algo) {
     case PAC_ALGO_PLAIN: {
@@ -265,6 +268,15 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
       rc = ensure_scratch(ctx, pac::part_scratch_bytes(d));
       if (rc != PAC_OK) return rc;
       e = pac::launch_agg_part(env, d, ds, ctx->scratch, ctx->scratch_bytes, (flags & PAC_AGG_INIT) != 0);
+      break;
+    }
+    case PAC_ALGO_REGISTER: {
+      if (!pac::reg_supported(d, ds.minmax != 0))
+        return fail(PAC_ERR_UNSUPPORTED, "register form needs dense groups (<= 8 at m = 64, <= 4 at m = 128) and "
+                                         "1-3 value columns (1-2 with MIN/MAX)");
+      rc = ensure_scratch(ctx, pac::reg_scratch_bytes(d, ds.minmax != 0));
+      if (rc != PAC_OK) return rc;
+      e = pac::launch_agg_reg(env, d, ds, ctx->scratch, ctx->scratch_bytes);
       break;
     }
     default:

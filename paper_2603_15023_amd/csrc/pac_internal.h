@@ -263,6 +263,10 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
 bool part_supported(const DevInput &in);
 size_t part_scratch_bytes(const DevInput &in);
 bool plain_fits_lds(const DevInput &in);
+bool reg_supported(const DevInput &in, bool minmax);
+size_t reg_scratch_bytes(const DevInput &in, bool minmax);
+hipError_t launch_agg_reg(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
+                          size_t scratch_bytes);
 bool plain_fits_lds4(const DevInput &in);
 bool star_supported(const DevInput &in);
 

@@ -164,3 +164,42 @@ def test_minmax_release_matches_oracle(ctx, torch_mod, m):
     assert np.array_equal(nulls.cpu().numpy(), wn) and np.array_equal(cflags.cpu().numpy(), wf)
     np.testing.assert_allclose(vals.cpu().numpy(), wv, rtol=1e-12, atol=0)
     np.testing.assert_allclose(post.cpu().numpy(), wp, rtol=1e-9, atol=1e-300)
+
+
+# Register form (few groups): every compiled column mix, with and without
+# MIN/MAX, against the oracle; float sums within 1e-12 of the sum of
+# magnitudes (their order differs from the oracle's), bit-identical on a rerun.
+_REG_MIXES = [(1, 0, True), (2, 0, True), (0, 1, False), (0, 1, True), (1, 1, True), (0, 2, True),
+              (2, 1, False), (1, 2, False)]
+
+
+@pytest.mark.parametrize("m,G", [(64, 1), (64, 8), (128, 4)])
+@pytest.mark.parametrize("mix", _REG_MIXES)
+def test_register_form_mixes(ctx, torch_mod, m, G, mix):
+    import paper_2603_15023_amd as P
+    ni, nf, mm = mix
+    g = np.random.default_rng(700 + 10 * ni + nf + G)
+    n, K = 90_007, 0x3C3C + G
+    pu = g.integers(1, 2001, size=n, dtype=np.int64)
+    gsrc = g.integers(0, 1000, size=n, dtype=np.uint32)
+    icols = [g.integers(-10**13, 10**13, size=n, dtype=np.int64) for _ in range(ni)]
+    fcols = [g.lognormal(0.0, 2.0, size=n) * g.choice([-1.0, 1.0], size=n) for _ in range(nf)]
+    dev = torch_mod.device("cuda")
+    spec = P.AggSpec(n_rows=n, pu_keys=torch_mod.from_numpy(pu).to(dev),
+                     gcols=[torch_mod.from_numpy(gsrc.view(np.int32)).to(dev)], gcards=[1000], group_mod=G,
+                     n_groups=G, cols=[torch_mod.from_numpy(c).to(dev) for c in icols + fcols])
+    _say("register form", mix, m, G)
+    runs = []
+    for _ in range(2):
+        st = P.new_state(spec, m, minmax=mm)
+        P.pac_group_aggregate(ctx, spec, st, m=m, query_key=K, algo="register")
+        assert ctx.status() == 0
+        runs.append({k: v.cpu().numpy() for k, v in st.items()})
+    got = runs[0]
+    kw = dict(pu_keys=pu, query_key=K, gcols=[gsrc], gcards=[1000], group_mod=G, n_groups=G, int_cols=icols)
+    want = ON.onepass(n, m, float_cols=fcols, minmax=mm, **kw)
+    _check(got, want, keys=("count", "nrows", "isum") + (MM_KEYS if mm else ()))
+    if nf:
+        mag = ON.onepass(n, m, float_cols=[np.abs(c) for c in fcols], **kw)["fsum"]
+        assert np.all(np.abs(got["fsum"] - want["fsum"]) <= 1e-12 * mag + 1e-300)
+        assert np.array_equal(runs[1]["fsum"].view(np.int64), got["fsum"].view(np.int64))
