@@ -321,6 +321,98 @@ def brute_force_flat(pu_key_rows: np.ndarray, group: np.ndarray, G: int, int_col
 
 
 # ---------------------------------------------------------------------------
+# post-aggregation: world values and pac_select  (Sec. 4.2 vector-lifted
+# expressions and PAC Selection; Sec. 3.2 categorical rewrites)
+# ---------------------------------------------------------------------------
+SEL_LT, SEL_LE, SEL_EQ, SEL_NE, SEL_GT, SEL_GE = 0, 1, 2, 3, 4, 5
+
+
+def world_values(counters: Dict[str, np.ndarray], kind: int, col: int = 0) -> np.ndarray:
+    """[G][m] raw per-world aggregate of every group (the j-th sub-sample's result, no x2).
+
+    reading: in world j an aggregate over no rows is SQL NULL, represented as
+    NaN, except COUNT, which is 0.
+    """
+    cnt = counters["count"]
+    if kind == KIND_COUNT:
+        return cnt.astype(np.float64)
+    key = {KIND_SUM_I: "isum", KIND_AVG_I: "isum", KIND_SUM_F: "fsum", KIND_AVG_F: "fsum", KIND_MIN_I: "imin",
+           KIND_MAX_I: "imax", KIND_MIN_F: "fmin", KIND_MAX_F: "fmax"}[kind]
+    y = counters[key][:, col, :].astype(np.float64)
+    if kind in (KIND_AVG_I, KIND_AVG_F):
+        y = y / np.where(cnt > 0, cnt, 1).astype(np.float64)
+    return np.where(cnt > 0, y, np.nan)
+
+
+def _compare(v: float, op: int, t: float) -> bool:
+    """SQL comparison: false when the world's value is NULL (NaN)."""
+    if math.isnan(t):
+        return False
+    return {SEL_LT: v < t, SEL_LE: v <= t, SEL_EQ: v == t, SEL_NE: v != t, SEL_GT: v > t, SEL_GE: v >= t}[op]
+
+
+def pac_select_cmp(pu: np.ndarray, group: np.ndarray, values: np.ndarray, wv: np.ndarray, op: int,
+                   scale: float = 1.0, offset: float = 0.0) -> np.ndarray:
+    """pac_select(pu, p) with p_j = (value op scale * wv[group][j] + offset) (the fused comparison form).
+
+    Bit j of the result is set iff bit j of pu is set and the row satisfies the
+    predicate on the j-th sub-sample's aggregate of its group.  Rows with
+    group < 0 (filtered, or no such group) get an all-zero vector.
+    Written as a loop over rows and worlds; small inputs.
+    """
+    n, W = pu.shape
+    out = np.zeros_like(pu)
+    for r in range(n):
+        g = int(group[r])
+        if g < 0:
+            continue
+        v = float(values[r])
+        for w in range(W):
+            word = int(pu[r, w])
+            res = 0
+            for b in range(64):
+                if (word >> b) & 1 and _compare(v, op, scale * float(wv[g, 64 * w + b]) + offset):
+                    res |= 1 << b
+            out[r, w] = np.uint64(res)
+    return out
+
+
+def brute_force_nested_flat(pu_key_rows: np.ndarray, inner_group: np.ndarray, G_in: int, inner_vals: np.ndarray,
+                            outer_group: np.ndarray, G_out: int, sel_vals: np.ndarray, sum_vals: np.ndarray,
+                            query_key: int, m: int = 64, scale: float = 1.0) -> Dict[str, list]:
+    """A correlated nested query executed once per sampled database (Sec. 4.1 procedure):
+
+        SELECT outer_group, COUNT(*), SUM(sum_vals) FROM T t
+        WHERE sel_vals < scale * (SELECT AVG(inner_vals) FROM T u WHERE u.inner_group = t.inner_group)
+        GROUP BY outer_group
+
+    In instance j both the outer and the inner scan see only the rows whose PU
+    is in S_j; a part whose inner aggregate is NULL in instance j keeps none of
+    its rows.  Plain Python on small inputs.
+    """
+    keys = sorted({int(k) for k in pu_key_rows})
+    hashes = {k: pac_hash(k, query_key, m) for k in keys}
+    out_count = [[0] * m for _ in range(G_out)]
+    out_sum = [[0] * m for _ in range(G_out)]
+    n = pu_key_rows.shape[0]
+    for j in range(m):
+        rows_j = [r for r in range(n) if world_bit(hashes[int(pu_key_rows[r])], j)]
+        tot: Dict[int, int] = {}
+        num: Dict[int, int] = {}
+        for r in rows_j:                                   # inner GROUP BY: AVG per inner group
+            p = int(inner_group[r])
+            tot[p] = tot.get(p, 0) + int(inner_vals[r])
+            num[p] = num.get(p, 0) + 1
+        for r in rows_j:                                   # outer selection and GROUP BY
+            p, g = int(inner_group[r]), int(outer_group[r])
+            avg = float(tot[p]) / float(num[p])            # p has a row in instance j: r itself
+            if float(sel_vals[r]) < scale * avg:
+                out_count[g][j] += 1
+                out_sum[g][j] += int(sum_vals[r])
+    return {"count": out_count, "isum": out_sum}
+
+
+# ---------------------------------------------------------------------------
 # counter-based randomness  (reading: the paper does not name its RNG)
 # ---------------------------------------------------------------------------
 PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57

@@ -345,3 +345,55 @@ def test_minmax_cell_vector_zero_for_empty_worlds_and_unscaled():
     assert np.array_equal(R.cell_vector(counters, 0, R.KIND_MAX_I, 0, R.FLAG_SCALE2), [9.0, 0.0, -7.0, 0.0])
     assert np.array_equal(R.cell_vector(counters, 0, R.KIND_MIN_F, 0, 0), [0.5, 0.0, -2.0, 0.0])
     assert np.array_equal(R.cell_vector(counters, 0, R.KIND_MAX_F, 0, R.FLAG_SCALE2), [1.5, 0.0, -2.0, 0.0])
+
+
+# ----------------------------------------------------------------------------- pac_select (nested queries)
+def _nested_case(seed, n=400, n_keys=25, G_in=7, G_out=3):
+    g = np.random.default_rng(seed)
+    keys = g.integers(-(1 << 62), 1 << 62, size=n_keys, dtype=np.int64)
+    pu_key = keys[g.integers(0, n_keys, size=n)]
+    part = g.integers(0, G_in, size=n)
+    grp = g.integers(0, G_out, size=n)
+    q = g.integers(1, 51, size=n, dtype=np.int64)
+    price = g.integers(100, 100_000, size=n, dtype=np.int64)
+    return pu_key, part, grp, q, price
+
+
+@pytest.mark.parametrize("m", [64, 128])
+def test_pac_select_composition_equals_nested_brute_force(m):
+    """Inner per-world AVG -> world values -> pac_select(q < 0.2 avg_j) -> outer per-world
+    COUNT/SUM equals running the nested query on each of the m sampled databases."""
+    pu_key, part, grp, q, price = _nested_case(31)
+    K, scale = 0xF00D, 0.2 * 3  # 0.6 x the part average keeps a good share of the rows
+    pu = R.pu_of_rows_flat(pu_key, K, m)
+    inner = R.pac_agg_counters(pu, part, 7, [q])
+    wv = R.world_values(inner, R.KIND_AVG_I, 0)
+    pu2 = R.pac_select_cmp(pu, part, q, wv, R.SEL_LT, scale)
+    outer = R.pac_agg_counters(pu2, grp, 3, [price])
+    bf = R.brute_force_nested_flat(pu_key, part, 7, q, grp, 3, q, price, K, m, scale)
+    assert np.array_equal(outer["count"], np.array(bf["count"]))
+    assert np.array_equal(outer["isum"][:, 0, :], np.array(bf["isum"], dtype=np.int64))
+    # the selection only clears bits, and a row keeps a bit only if its world saw its part
+    assert np.all((pu2 & ~pu) == 0)
+
+
+def test_world_values_and_select_special_cases():
+    c = {"count": np.array([[2, 0, 4]]), "isum": np.array([[[10, 0, 8]]]), "fsum": np.zeros((1, 0, 3)),
+         "nrows": np.array([4])}
+    wv = R.world_values(c, R.KIND_AVG_I, 0)
+    assert wv[0, 0] == 5.0 and math.isnan(wv[0, 1]) and wv[0, 2] == 2.0
+    assert np.array_equal(R.world_values(c, R.KIND_COUNT), np.array([[2.0, 0.0, 4.0]]))
+    # NULL world: every comparison is false, including "not equal"
+    for op in range(6):
+        assert not R._compare(1.0, op, float("nan"))
+    # all-true / all-false predicates reduce pac_select to the identity / zero
+    pu = np.array([[np.uint64(0xF0F0F0F0F0F0F0F0)]], dtype=np.uint64)
+    wv64 = np.full((1, 64), 10.0)
+    assert R.pac_select_cmp(pu, np.array([0]), np.array([1.0]), wv64, R.SEL_LT)[0, 0] == pu[0, 0]
+    assert R.pac_select_cmp(pu, np.array([0]), np.array([11.0]), wv64, R.SEL_LT)[0, 0] == 0
+    assert R.pac_select_cmp(pu, np.array([-1]), np.array([1.0]), wv64, R.SEL_LT)[0, 0] == 0
+    # a threshold that differs per world selects exactly those worlds
+    wv_j = np.arange(64, dtype=np.float64)[None, :]
+    got = int(R.pac_select_cmp(np.array([[np.uint64((1 << 64) - 1)]], dtype=np.uint64), np.array([0]),
+                               np.array([31.5]), wv_j, R.SEL_GT)[0, 0])
+    assert got == (1 << 32) - 1
