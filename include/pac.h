@@ -219,6 +219,42 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
                  int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
                  uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y);
 
+/* ---- post-aggregation (Sec. 4.2 vector-lifted expressions and PAC
+ * Selection; Sec. 3.2 categorical rewrites, fused pac_select_<cmp>) -------- */
+
+/* World values of one aggregate for every group: out[g][j] = the aggregate
+ * that the j-th sampled database computes for group g -- COUNT, SUM,
+ * AVG = SUM / COUNT, MIN or MAX (kind and col as in pac_cell), never scaled.
+ * A world that received no row of g holds NaN (SQL NULL), except COUNT (0).
+ * state, out [n_groups][m]: device.  Bad kind / col / missing state array:
+ * PAC_ERR_INVALID. */
+int pac_world_values(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
+                     int n_float, int32_t kind, int32_t col, double *out);
+
+#define PAC_SEL_LT 0
+#define PAC_SEL_LE 1
+#define PAC_SEL_EQ 2
+#define PAC_SEL_NE 3
+#define PAC_SEL_GT 4
+#define PAC_SEL_GE 5
+
+/* pac_select in its fused comparison form.  rows describes the rows and
+ * their PU vectors exactly as for pac_group_aggregate (masks or the fused
+ * hash of pu_keys with query_key, FK links, filter); its dense grouping
+ * (gcols / gcards / group_mod / n_groups; no sparse keys) gives each row's
+ * group g in world_values [n_wv_groups][m] (n_wv_groups == rows->n_groups),
+ * and cols[0] (int or float, compared as a double) its value.
+ *   out_masks[r][w] bit b = PU bit (64 w + b) of row r  AND
+ *                           value(r) op (scale * world_values[g][64 w + b] + offset)
+ * A NaN world value is never satisfied (also for PAC_SEL_NE); a row that is
+ * filtered out or whose group is out of range gets 0 (the latter also sets
+ * PAC_STATUS_BAD_GROUP).  out_masks: device [n_rows][m/64]; a following
+ * pac_group_aggregate over the same rows takes masks = out_masks,
+ * n_masks = n_rows and no links. */
+int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m, uint64_t query_key,
+                   const double *world_values, int64_t n_wv_groups, int32_t op, double scale, double offset,
+                   uint64_t *out_masks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -377,6 +377,26 @@ def pac_select_cmp(pu: np.ndarray, group: np.ndarray, values: np.ndarray, wv: np
     return out
 
 
+def pac_select_cmp_np(pu: np.ndarray, group: np.ndarray, values: np.ndarray, wv: np.ndarray, op: int,
+                      scale: float = 1.0, offset: float = 0.0) -> np.ndarray:
+    """``pac_select_cmp`` with numpy, world by world (same definition; for larger inputs)."""
+    n, W = pu.shape
+    out = np.zeros_like(pu)
+    ok = group >= 0
+    gv = np.where(ok, group, 0)
+    v = values.astype(np.float64)
+    cmp = {SEL_LT: np.less, SEL_LE: np.less_equal, SEL_EQ: np.equal, SEL_NE: np.not_equal, SEL_GT: np.greater,
+           SEL_GE: np.greater_equal}[op]
+    for j in range(64 * W):
+        t = wv[gv, j]
+        thr = scale * t + offset
+        with np.errstate(invalid="ignore"):
+            p = ok & ~np.isnan(t) & cmp(v, thr)
+        bit = (pu[:, j // 64] >> np.uint64(j % 64)) & np.uint64(1)
+        out[:, j // 64] |= (bit & p.astype(np.uint64)) << np.uint64(j % 64)
+    return out
+
+
 def brute_force_nested_flat(pu_key_rows: np.ndarray, inner_group: np.ndarray, G_in: int, inner_vals: np.ndarray,
                             outer_group: np.ndarray, G_out: int, sel_vals: np.ndarray, sum_vals: np.ndarray,
                             query_key: int, m: int = 64, scale: float = 1.0) -> Dict[str, list]:

@@ -15,4 +15,6 @@ from .api import (  # noqa: F401
     pac_group_aggregate,
     pac_group_aggregate_batch,
     pac_hash_mask,
+    pac_select_cmp,
+    pac_world_values,
 )

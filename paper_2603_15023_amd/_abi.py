@@ -18,6 +18,7 @@ PAC_U8, PAC_U16, PAC_U32, PAC_I32, PAC_I64, PAC_F32, PAC_F64 = 1, 2, 3, 4, 5, 6,
 PAC_HASH_BALANCED = 1
 PAC_ALGO_AUTO, PAC_ALGO_PLAIN, PAC_ALGO_BALLOT, PAC_ALGO_MFMA_I8, PAC_ALGO_PARTITION = 0, 1, 2, 3, 4
 PAC_ALGO_REGISTER = 5
+PAC_SEL_LT, PAC_SEL_LE, PAC_SEL_EQ, PAC_SEL_NE, PAC_SEL_GT, PAC_SEL_GE = 0, 1, 2, 3, 4, 5
 ALGOS = {"auto": PAC_ALGO_AUTO, "plain": PAC_ALGO_PLAIN, "ballot": PAC_ALGO_BALLOT, "mfma": PAC_ALGO_MFMA_I8,
          "partition": PAC_ALGO_PARTITION, "register": PAC_ALGO_REGISTER}
 PAC_AGG_INIT = 1
@@ -75,6 +76,10 @@ EXPORTS = {
     "pac_finalize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
                                C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pac_world_values": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
+                                   C.c_int32, C.c_int32, C.c_void_p]),
+    "pac_select_cmp": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggInput), C.c_int, C.c_uint64, C.c_void_p,
+                                 C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_void_p]),
 }
 
 _lib = None

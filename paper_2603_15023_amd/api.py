@@ -251,3 +251,34 @@ def pac_finalize(ctx: Context, state: Dict[str, torch.Tensor], cells: torch.Tens
                                   int(state["isum"].shape[1]), int(state["fsum"].shape[1]), _ptr(cells), n_cells,
                                   C.byref(params), _ptr(vals), _ptr(nulls), _ptr(cflags), _ptr(post), _ptr(ys)))
     return vals, nulls, cflags, post, ys
+
+
+SELECT_OPS = {"<": A.PAC_SEL_LT, "<=": A.PAC_SEL_LE, "==": A.PAC_SEL_EQ, "!=": A.PAC_SEL_NE, ">": A.PAC_SEL_GT,
+              ">=": A.PAC_SEL_GE}
+
+
+def pac_world_values(ctx: Context, state: Dict[str, torch.Tensor], kind: str, col: int = 0, m: int = 64,
+                     out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """[G, m] per-world results of one aggregate of ``state`` (NaN for SQL NULL worlds)."""
+    G = int(state["count"].shape[0])
+    if out is None:
+        out = torch.empty((G, m), dtype=torch.float64, device=state["count"].device)
+    cst = _state_c(state)
+    A.check(A.load().pac_world_values(ctx.handle, _stream_handle(stream), C.byref(cst), m, G,
+                                      int(state["isum"].shape[1]), int(state["fsum"].shape[1]), CELL_KINDS[kind],
+                                      int(col), _ptr(out)))
+    return out
+
+
+def pac_select_cmp(ctx: Context, rows: AggSpec, world_values: torch.Tensor, op: str, scale: float = 1.0,
+                   offset: float = 0.0, m: int = 64, query_key: int = 0, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+    """[n_rows, m/64] int64 PU words: pu AND (cols[0] op scale * world_values[group] + offset) per world."""
+    n = int(rows.n_rows)
+    if out is None:
+        out = torch.empty((n, m // 64), dtype=torch.int64, device=world_values.device)
+    cin = rows.to_c()
+    A.check(A.load().pac_select_cmp(ctx.handle, _stream_handle(stream), C.byref(cin), m,
+                                    query_key & ((1 << 64) - 1), _ptr(world_values), int(world_values.shape[0]),
+                                    SELECT_OPS[op], float(scale), float(offset), _ptr(out)))
+    return out

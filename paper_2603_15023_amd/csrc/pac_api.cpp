@@ -76,7 +76,8 @@ int bit_length(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 // Validates one input and builds the kernel view.  Returns PAC_OK or an error.
 int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state *st, pac::DevInput *d,
                pac::DevState *ds) {
-  if (!in || !st) return fail(PAC_ERR_INVALID, "null input or state");
+  // st == nullptr: rows only (pac_select_cmp); no state checks, ds untouched
+  if (!in) return fail(PAC_ERR_INVALID, "null input");
   if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
   if (in->n_rows < 0) return fail(PAC_ERR_INVALID, "n_rows < 0");
   if (in->n_links < 0 || in->n_links > PAC_MAX_LINKS) return fail(PAC_ERR_INVALID, "n_links out of range");
@@ -92,7 +93,7 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
   if (in->group_keys) {
     if (in->n_gcols > 0 || in->group_mod > 0) return fail(PAC_ERR_INVALID, "sparse keys exclude group columns");
     if (in->n_groups & (in->n_groups - 1)) return fail(PAC_ERR_INVALID, "sparse capacity must be a power of two");
-    if (!st->slot_keys || !st->n_used) return fail(PAC_ERR_INVALID, "sparse mode needs slot_keys and n_used");
+    if (st && (!st->slot_keys || !st->n_used)) return fail(PAC_ERR_INVALID, "sparse mode needs slot_keys and n_used");
   } else {
     if (in->n_gcols == 0 && in->group_mod == 0 && in->n_groups != 1)
       return fail(PAC_ERR_INVALID, "ungrouped aggregate needs n_groups == 1");
@@ -105,7 +106,7 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
     }
     if (prod > 4.0e9) return fail(PAC_ERR_UNSUPPORTED, "composite group key space above 2^32");
   }
-  if (!st->count || !st->nrows) return fail(PAC_ERR_INVALID, "state.count and state.nrows are required");
+  if (st && (!st->count || !st->nrows)) return fail(PAC_ERR_INVALID, "state.count and state.nrows are required");
   const int64_t G = in->n_groups;
   if ((double)G * m * (1 + in->n_cols) > 4.0e12) return fail(PAC_ERR_INVALID, "state too large");
 
@@ -176,6 +177,7 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
   for (int k = 0; k < in->n_gcols; ++k)
     if (misaligned(in->gcols[k])) return fail(PAC_ERR_INVALID, "group column %d is not 16-byte aligned", k);
   if (misaligned(in->filter_col)) return fail(PAC_ERR_INVALID, "filter column is not 16-byte aligned");
+  if (!st) return PAC_OK;
   if (d->n_icols > 0 && !st->isum) return fail(PAC_ERR_INVALID, "state.isum required for int columns");
   if (d->n_fcols > 0 && !st->fsum) return fail(PAC_ERR_INVALID, "state.fsum required for float columns");
   ds->count = st->count;
@@ -393,6 +395,54 @@ int pac_group_aggregate_batch(pac_ctx *ctx, void *stream, const pac_agg_input *i
       return fail(rc, "query %d: %s", q, msg.c_str());
     }
   }
+  return PAC_OK;
+}
+
+int pac_world_values(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
+                     int n_float, int32_t kind, int32_t col, double *out) {
+  if (!ctx || !state || !out) return fail(PAC_ERR_INVALID, "null context, state or output");
+  if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
+  if (n_groups < 1 || n_int < 0 || n_float < 0) return fail(PAC_ERR_INVALID, "bad sizes");
+  if (!state->count) return fail(PAC_ERR_INVALID, "state.count missing");
+  const bool on_int = kind == PAC_CELL_SUM_I || kind == PAC_CELL_AVG_I || kind == PAC_CELL_MIN_I || kind == PAC_CELL_MAX_I;
+  const bool on_float = kind == PAC_CELL_SUM_F || kind == PAC_CELL_AVG_F || kind == PAC_CELL_MIN_F || kind == PAC_CELL_MAX_F;
+  if (kind != PAC_CELL_COUNT && !on_int && !on_float) return fail(PAC_ERR_INVALID, "bad kind %d", kind);
+  if ((on_int && (col < 0 || col >= n_int)) || (on_float && (col < 0 || col >= n_float)))
+    return fail(PAC_ERR_INVALID, "column %d out of range", col);
+  const void *need = kind == PAC_CELL_SUM_I || kind == PAC_CELL_AVG_I ? (const void *)state->isum
+                     : kind == PAC_CELL_SUM_F || kind == PAC_CELL_AVG_F ? (const void *)state->fsum
+                     : kind == PAC_CELL_MIN_I ? (const void *)state->imin
+                     : kind == PAC_CELL_MAX_I ? (const void *)state->imax
+                     : kind == PAC_CELL_MIN_F ? (const void *)state->fmin
+                     : kind == PAC_CELL_MAX_F ? (const void *)state->fmax : (const void *)state->count;
+  if (!need) return fail(PAC_ERR_INVALID, "the state has no array for kind %d", kind);
+  DeviceGuard guard(ctx->device);
+  pac::DevState ds{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used,
+                   state->imin,  state->imax, state->fmin, state->fmax,  0};
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e = pac::launch_world_values(env, ds, m, n_groups, n_int, n_float, kind, col, out);
+  if (e != hipSuccess) return hip_fail(e, "world values launch");
+  return PAC_OK;
+}
+
+int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m, uint64_t query_key,
+                   const double *world_values, int64_t n_wv_groups, int32_t op, double scale, double offset,
+                   uint64_t *out_masks) {
+  if (!ctx || !rows) return fail(PAC_ERR_INVALID, "null context or rows");
+  if (op < PAC_SEL_LT || op > PAC_SEL_GE) return fail(PAC_ERR_INVALID, "bad comparison %d", op);
+  if (rows->group_keys) return fail(PAC_ERR_INVALID, "pac_select_cmp takes dense groups only");
+  if (rows->n_cols < 1) return fail(PAC_ERR_INVALID, "cols[0] (the compared value) is required");
+  if (n_wv_groups != rows->n_groups) return fail(PAC_ERR_INVALID, "world value table has %lld groups, rows %lld",
+                                                 (long long)n_wv_groups, (long long)rows->n_groups);
+  if (rows->n_rows > 0 && (!world_values || !out_masks)) return fail(PAC_ERR_INVALID, "null world values or output");
+  pac::DevInput d;
+  int rc = plan_input(rows, m, query_key, nullptr, &d, nullptr);
+  if (rc != PAC_OK) return rc;
+  if (d.n_rows == 0) return PAC_OK;
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e = pac::launch_select_cmp(env, d, world_values, op, scale, offset, out_masks);
+  if (e != hipSuccess) return hip_fail(e, "select launch");
   return PAC_OK;
 }
 

@@ -264,6 +264,10 @@ bool part_supported(const DevInput &in);
 size_t part_scratch_bytes(const DevInput &in);
 bool plain_fits_lds(const DevInput &in);
 bool reg_supported(const DevInput &in, bool minmax);
+hipError_t launch_world_values(const LaunchEnv &env, const DevState &st, int m, int64_t G, int n_int, int n_float,
+                               int kind, int col, double *out);
+hipError_t launch_select_cmp(const LaunchEnv &env, const DevInput &in, const double *wv, int op, double scale,
+                             double offset, uint64_t *out);
 size_t reg_scratch_bytes(const DevInput &in, bool minmax);
 hipError_t launch_agg_reg(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
                           size_t scratch_bytes);

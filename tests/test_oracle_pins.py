@@ -397,3 +397,17 @@ def test_world_values_and_select_special_cases():
     got = int(R.pac_select_cmp(np.array([[np.uint64((1 << 64) - 1)]], dtype=np.uint64), np.array([0]),
                                np.array([31.5]), wv_j, R.SEL_GT)[0, 0])
     assert got == (1 << 32) - 1
+
+
+def test_pac_select_numpy_form_equals_loop_form():
+    g = np.random.default_rng(41)
+    n, G = 300, 5
+    pu = np.stack([R.pac_hash_np(g.integers(1, 40, size=n), 3, 128)[:, w] for w in range(2)], axis=1)
+    group = g.integers(-1, G, size=n)
+    vals = g.integers(0, 20, size=n)
+    wv = g.integers(0, 20, size=(G, 128)).astype(np.float64)
+    wv[g.random(size=wv.shape) < 0.1] = np.nan
+    for op in range(6):
+        a = R.pac_select_cmp(pu, group, vals, wv, op, 0.5, 3.0)
+        b = R.pac_select_cmp_np(pu, group, vals, wv, op, 0.5, 3.0)
+        assert np.array_equal(a, b), op
