@@ -4,6 +4,7 @@
     python -m paper_2603_15023_amd.bench_workloads float  [--reps 3] [--algo auto]
     python -m paper_2603_15023_amd.bench_workloads serve  [--queries 64] [--slots 4] [--load 0.7]
     python -m paper_2603_15023_amd.bench_workloads minmax [--reps 3] [--oracle-rows 20000000]
+    python -m paper_2603_15023_amd.bench_workloads nested [--reps 3]
 
 zipf:  100M rows, 2M PU keys per row, group keys Zipf(1.1) over 1M ranks
        (HBM hash table), SUM int64 + COUNT, m = 64.
@@ -11,6 +12,10 @@ float: 200M rows, 4M PU keys per row, 64 uniform groups, lognormal(0, 2)
        FP64 values and their FP32 copy; m = 64 and 128.
 serve: the served workload (100M-row resident star schema, queries of mixed
        selectivity, group count and aggregates) through the slot server.
+nested: a correlated nested query on the 60M-row star schema (TPC-H Q17
+       shape): inner AVG(qty) per part (200K parts), the per-world averages,
+       pac_select(qty < 0.2 avg_j), outer SUM(v1) over the selected vectors and
+       its release; each step timed.
 minmax: the float table's rows with 8 groups (its group column mod 8): COUNT,
        SUM, MIN and MAX of the FP64 column per world, m = 64, against the same
        query without MIN/MAX, and the C oracle timed on a row prefix.
@@ -119,6 +124,62 @@ def minmax(args):
                           "rows_per_s": n / el, "threads": ON.default_threads()}), flush=True)
 
 
+def nested(args):
+    from workloads import gen
+    from . import cells_tensor, pac_finalize, pac_hash_mask, pac_select_cmp, pac_world_values
+    t = gen.config2_star()
+    x = gen.nested_columns(t.n_rows)
+    dev = torch.device("cuda")
+    ctx = Context(0)
+    K = gen.query_key(2)
+    pu_key = torch.from_numpy(t.pu_key).to(dev)
+    links = [torch.from_numpy(t.f_order).to(dev), torch.from_numpy(t.o_pu).to(dev)]
+    part = torch.from_numpy(x["part"].view(np.int32)).to(dev)
+    qty = torch.from_numpy(x["qty"]).to(dev)
+    price = torch.from_numpy(t.cols["v1"]).to(dev)
+    masks = torch.empty((t.pu_key.shape[0], 1), dtype=torch.int64, device=dev)
+    n_parts = 200_000
+    inner = AggSpec(n_rows=t.n_rows, masks=masks, links=links, gcols=[part], gcards=[n_parts], n_groups=n_parts,
+                    cols=[qty])
+    st_in = new_state(inner, 64)
+    cells = cells_tensor([(0, 1, 0)])  # SUM of the int column
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+
+    def run(ev=None):
+        rec = (lambda i: ev[i].record()) if ev else (lambda i: None)
+        rec(0)
+        pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+        pac_group_aggregate(ctx, inner, st_in, m=64, query_key=K)
+        rec(1)
+        wv = pac_world_values(ctx, st_in, "avg_i", 0)
+        rec(2)
+        sel = pac_select_cmp(ctx, inner, wv, "<", 0.2)
+        rec(3)
+        outer = AggSpec(n_rows=t.n_rows, masks=sel, cols=[price], stats=[(100, 10_000_000)])
+        st_out = new_state(outer, 64)
+        pac_group_aggregate(ctx, outer, st_out, m=64)
+        rec(4)
+        out = pac_finalize(ctx, st_out, cells, 1, noise_seed=gen.noise_seed(2))
+        rec(5)
+        return out
+
+    run()
+    torch.cuda.synchronize()
+    steps = {"inner (hash + AVG by part)": [], "world values": [], "pac_select": [], "outer SUM": [],
+             "release": []}
+    for _ in range(args.reps):
+        run(evs)
+        torch.cuda.synchronize()
+        for i, k in enumerate(steps):
+            steps[k].append(evs[i].elapsed_time(evs[i + 1]))
+    ctx.check()
+    ms = {k: float(np.mean(v)) for k, v in steps.items()}
+    total = sum(ms.values())
+    print(json.dumps({"workload": "nested query, 60M fact rows, 200K parts (TPC-H Q17 shape), m=64",
+                      "ms": total, "rows_per_s": t.n_rows / (total * 1e-3), "steps_ms": ms}), flush=True)
+    ctx.close()
+
+
 def serve(args):
     from workloads import gen
     from .serve import ResidentStar, Server, latency_summary
@@ -137,7 +198,7 @@ def serve(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax"])
+    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested"])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--queries", type=int, default=64)
@@ -145,7 +206,7 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--oracle-rows", type=int, default=20_000_000)
     args = ap.parse_args(argv)
-    {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax}[args.what](args)
+    {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested}[args.what](args)
 
 
 if __name__ == "__main__":

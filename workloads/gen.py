@@ -111,6 +111,15 @@ def config2_star(scale: float = 1.0, seed: int = CONFIG_SEEDS[1], shuffled: bool
     return t
 
 
+def nested_columns(n: int, n_parts: int = 200_000, seed: int = CONFIG_SEEDS[1] + 0x200) -> Dict[str, np.ndarray]:
+    """Extra fact columns of the nested-query workload (a TPC-H Q17 shape: rows below a
+    fraction of their part's average quantity): ``part`` uniform over n_parts
+    (uint32), ``qty`` uniform in 1..50 (int64)."""
+    g = _rng(seed)
+    return {"part": g.integers(0, n_parts, size=n, dtype=np.uint32),
+            "qty": g.integers(1, 51, size=n, dtype=np.int64)}
+
+
 # ---------------------------------------------------------------------------
 # workload 3: high-cardinality GROUP BY with Zipf-distributed group keys
 # ---------------------------------------------------------------------------
