@@ -485,6 +485,32 @@ def null_uniform(seed: int, cell: int) -> float:
     return unit_uniform(a)
 
 
+PURPOSE_FILTER = 3
+
+
+def pac_filter(wv: np.ndarray, op: int, threshold: float, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Probabilistic filtering (Sec. 3.2): for group g, the fraction p_g of the m worlds whose value
+    satisfies ``wv[g][j] op threshold`` (a NULL world does not), then keep g with probability p_g.
+
+    reading: the coin of group g is the first uniform of the Philox stream of
+    ``seed`` at counter (g, 3), independent of the secret world.
+    Returns (keep[G] as 0/1, p[G]).
+    """
+    G, m = wv.shape
+    keep = np.zeros(G, dtype=np.uint8)
+    frac = np.zeros(G)
+    for g in range(G):
+        n_true = 0
+        for j in range(m):
+            y = float(wv[g, j])
+            if not math.isnan(y) and _compare(y, op, threshold):
+                n_true += 1
+        frac[g] = n_true / m
+        a, _ = draw64(seed, g, PURPOSE_FILTER)
+        keep[g] = 1 if unit_uniform(a) < frac[g] else 0
+    return keep, frac
+
+
 # ---------------------------------------------------------------------------
 # release: cell vectors, NULL coin, pac_noised, posterior  (Sec. 4.1, Sec. 3.2, Sec. 5)
 # ---------------------------------------------------------------------------

@@ -411,3 +411,20 @@ def test_pac_select_numpy_form_equals_loop_form():
         a = R.pac_select_cmp(pu, group, vals, wv, op, 0.5, 3.0)
         b = R.pac_select_cmp_np(pu, group, vals, wv, op, 0.5, 3.0)
         assert np.array_equal(a, b), op
+
+
+def test_pac_filter_fraction_and_coin():
+    """Sec. 3.2 probabilistic filtering: p_g = share of worlds where the predicate holds; keep with probability p_g."""
+    m, G = 64, 4
+    wv = np.zeros((G, m))
+    wv[0] = 10.0                                   # predicate true in every world -> always kept
+    wv[1] = -1.0                                   # never true -> never kept
+    wv[2, :16] = 10.0                              # a quarter of the worlds
+    wv[3] = np.nan                                 # NULL everywhere -> never kept (also for !=)
+    keep, frac = R.pac_filter(wv, R.SEL_GT, 5.0, seed=7)
+    assert list(frac) == [1.0, 0.0, 0.25, 0.0]
+    assert keep[0] == 1 and keep[1] == 0 and keep[3] == 0
+    assert R.pac_filter(wv, R.SEL_NE, 5.0, seed=7)[1][3] == 0.0
+    # the coin is Bernoulli(p): frequency over many seeds within a binomial bound
+    hits = sum(int(R.pac_filter(wv[2:3], R.SEL_GT, 5.0, seed=s)[0][0]) for s in range(4000))
+    assert abs(hits / 4000 - 0.25) < 4 * math.sqrt(0.25 * 0.75 / 4000)
