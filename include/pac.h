@@ -255,6 +255,15 @@ int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m,
                    const double *world_values, int64_t n_wv_groups, int32_t op, double scale, double offset,
                    uint64_t *out_masks);
 
+/* Probabilistic filtering (Sec. 3.2 pac_filter): for every group g, p_g =
+ * the share of the m worlds with world_values[g][j] op threshold (a NaN
+ * world is never true), and keep[g] = 1 with probability p_g, the coin being
+ * the first uniform of the Philox4x32-10 stream of noise_seed at counter
+ * (g, 3) -- independent of the secret world.  world_values [n_groups][m],
+ * keep [n_groups], frac [n_groups] (or NULL): device. */
+int pac_filter(pac_ctx *ctx, void *stream, const double *world_values, int64_t n_groups, int m, int32_t op,
+               double threshold, uint64_t noise_seed, uint8_t *keep, double *frac);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@ from .api import (  # noqa: F401
     Context,
     cells_tensor,
     new_state,
+    pac_filter,
     pac_finalize,
     pac_group_aggregate,
     pac_group_aggregate_batch,

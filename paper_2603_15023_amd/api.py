@@ -282,3 +282,14 @@ def pac_select_cmp(ctx: Context, rows: AggSpec, world_values: torch.Tensor, op: 
                                     query_key & ((1 << 64) - 1), _ptr(world_values), int(world_values.shape[0]),
                                     SELECT_OPS[op], float(scale), float(offset), _ptr(out)))
     return out
+
+
+def pac_filter(ctx: Context, world_values: torch.Tensor, op: str, threshold: float, noise_seed: int, m: int = 64,
+               stream=None):
+    """Probabilistic filter per group: (keep uint8 [G], p float64 [G])."""
+    G = int(world_values.shape[0])
+    keep = torch.empty(G, dtype=torch.uint8, device=world_values.device)
+    frac = torch.empty(G, dtype=torch.float64, device=world_values.device)
+    A.check(A.load().pac_filter(ctx.handle, _stream_handle(stream), _ptr(world_values), G, m, SELECT_OPS[op],
+                                float(threshold), noise_seed & ((1 << 64) - 1), _ptr(keep), _ptr(frac)))
+    return keep, frac

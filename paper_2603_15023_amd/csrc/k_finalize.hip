@@ -33,7 +33,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uin
   }
 }
 
-enum { kDrawJStar = 0, kDrawNoise = 1, kDrawNull = 2 };
+enum { kDrawJStar = 0, kDrawNoise = 1, kDrawNull = 2, kDrawFilter = 3 };
 
 __device__ __forceinline__ void draw2(uint64_t seed, int64_t index, uint32_t purpose, uint64_t *a, uint64_t *b) {
   uint32_t c[4] = {(uint32_t)index, (uint32_t)((uint64_t)index >> 32), purpose, 0u};
@@ -286,6 +286,53 @@ __global__ __launch_bounds__(64) void release_chain_kernel(FinParams fp, int64_t
   }
 #pragma unroll
   for (int w = 0; w < W; ++w) post[lane + 64 * w] = P[w];
+}
+
+// Probabilistic filter (Sec. 3.2): one wave per group; lane j tests world j
+// (NaN: not true), the popcount of the ballot over m gives p_g, and the
+// group's coin (Philox at counter (g, filter)) keeps it with probability p_g.
+template <int W>
+__global__ __launch_bounds__(256) void filter_kernel(const double *wv, int64_t G, int op, double threshold,
+                                                     uint64_t seed, uint8_t *keep, double *frac) {
+  constexpr int m = 64 * W;
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (g >= G) return;
+  int n_true = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const double y = wv[g * m + 64 * w + lane];
+    bool p;
+    switch (op) {
+      case PAC_SEL_LT: p = y < threshold; break;
+      case PAC_SEL_LE: p = y <= threshold; break;
+      case PAC_SEL_EQ: p = y == threshold; break;
+      case PAC_SEL_NE: p = y != threshold; break;
+      case PAC_SEL_GT: p = y > threshold; break;
+      default: p = y >= threshold; break;
+    }
+    n_true += __popcll(__ballot(p && y == y));
+  }
+  if (lane == 0) {
+    const double pg = (double)n_true / (double)m;
+    uint64_t a, b;
+    draw2(seed, g, kDrawFilter, &a, &b);
+    keep[g] = to_unit(a) < pg ? 1 : 0;
+    if (frac) frac[g] = pg;
+  }
+}
+
+hipError_t launch_filter(const LaunchEnv &env, const double *wv, int64_t G, int m, int op, double threshold,
+                         uint64_t seed, uint8_t *keep, double *frac) {
+  if (G <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((G + 3) / 4);
+  if (m == 64)
+    hipLaunchKernelGGL(filter_kernel<1>, dim3(blocks), dim3(256), 0, env.stream, wv, G, op, threshold, seed, keep,
+                       frac);
+  else
+    hipLaunchKernelGGL(filter_kernel<2>, dim3(blocks), dim3(256), 0, env.stream, wv, G, op, threshold, seed, keep,
+                       frac);
+  return hipGetLastError();
 }
 
 size_t finalize_scratch_bytes(int m, int64_t n_cells) {

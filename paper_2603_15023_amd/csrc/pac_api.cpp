@@ -446,6 +446,20 @@ int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m,
   return PAC_OK;
 }
 
+int pac_filter(pac_ctx *ctx, void *stream, const double *world_values, int64_t n_groups, int m, int32_t op,
+               double threshold, uint64_t noise_seed, uint8_t *keep, double *frac) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
+  if (n_groups < 0) return fail(PAC_ERR_INVALID, "n_groups < 0");
+  if (op < PAC_SEL_LT || op > PAC_SEL_GE) return fail(PAC_ERR_INVALID, "bad comparison %d", op);
+  if (n_groups > 0 && (!world_values || !keep)) return fail(PAC_ERR_INVALID, "null world values or output");
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e = pac::launch_filter(env, world_values, n_groups, m, op, threshold, noise_seed, keep, frac);
+  if (e != hipSuccess) return hip_fail(e, "filter launch");
+  return PAC_OK;
+}
+
 int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
                  int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
                  uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y) {

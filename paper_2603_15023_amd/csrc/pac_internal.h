@@ -264,6 +264,8 @@ bool part_supported(const DevInput &in);
 size_t part_scratch_bytes(const DevInput &in);
 bool plain_fits_lds(const DevInput &in);
 bool reg_supported(const DevInput &in, bool minmax);
+hipError_t launch_filter(const LaunchEnv &env, const double *wv, int64_t G, int m, int op, double threshold,
+                         uint64_t seed, uint8_t *keep, double *frac);
 hipError_t launch_world_values(const LaunchEnv &env, const DevState &st, int m, int64_t G, int n_int, int n_float,
                                int kind, int col, double *out);
 hipError_t launch_select_cmp(const LaunchEnv &env, const DevInput &in, const double *wv, int op, double scale,

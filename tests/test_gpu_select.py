@@ -103,3 +103,29 @@ def test_select_ops_offsets_and_star_chain(ctx, torch_mod):
                 want = R.pac_select_cmp_np(pu_rows, group, vals, w_want, cop, 0.5, 1.0)
                 assert np.array_equal(sel.cpu().numpy().view(np.uint64), want), (kind, op, col)
     assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("m", [64, 128])
+def test_pac_filter_matches_oracle(ctx, torch_mod, m):
+    """Per-group probabilistic filter on per-world SUM values: shares and coins identical to the oracle."""
+    import paper_2603_15023_amd as P
+    n, G, K, seed = 50_003, 300, 0x7A7A, 0xFEED
+    pu_key, part, grp, q, price = _flat(83, n, 300, G, 3)
+    dev = torch_mod.device("cuda")
+    spec = P.AggSpec(n_rows=n, pu_keys=torch_mod.from_numpy(pu_key).to(dev),
+                     gcols=[torch_mod.from_numpy(part.view(np.int32)).to(dev)], gcards=[G], n_groups=G,
+                     cols=[torch_mod.from_numpy(q).to(dev)])
+    st = P.new_state(spec, m)
+    P.pac_group_aggregate(ctx, spec, st, m=m, query_key=K)
+    c = ON.onepass(n, m, pu_keys=pu_key, query_key=K, gcols=[part], gcards=[G], n_groups=G, int_cols=[q])
+    for kind, ckind, op, cop in (("sum_i", R.KIND_SUM_I, ">", R.SEL_GT), ("avg_i", R.KIND_AVG_I, "<=", R.SEL_LE),
+                                 ("count", R.KIND_COUNT, "!=", R.SEL_NE)):
+        w_want = R.world_values(c, ckind, 0)
+        thr = float(np.nanmedian(w_want))  # a threshold inside the values' range
+        wv = P.pac_world_values(ctx, st, kind, 0, m=m)
+        keep, frac = P.pac_filter(ctx, wv, op, thr, seed, m=m)
+        k_want, f_want = R.pac_filter(w_want, cop, thr, seed)
+        assert np.array_equal(frac.cpu().numpy(), f_want), kind
+        assert np.array_equal(keep.cpu().numpy(), k_want), kind
+        assert 0 < int(k_want.sum()) < G  # the case mixes kept and dropped groups
+    assert ctx.status() == 0
