@@ -321,6 +321,22 @@ def brute_force_flat(pu_key_rows: np.ndarray, group: np.ndarray, G: int, int_col
 
 
 # ---------------------------------------------------------------------------
+# PU-key join index  (Sec. 3.2: the rewriter joins each sensitive table to the
+# PU table along its foreign keys; Sec. 2 relational privacy unit)
+# ---------------------------------------------------------------------------
+def key_index(keys: np.ndarray, fk: np.ndarray) -> np.ndarray:
+    """Row of the referenced table for every referencing key: i with keys[i] == fk[r], or -1.
+
+    keys must be distinct.  A dict from key to row, then one lookup per row.
+    """
+    where = {}
+    for i, k in enumerate(keys.tolist()):
+        assert k not in where, "referenced keys must be distinct"
+        where[k] = i
+    return np.array([where.get(k, -1) for k in fk.tolist()], dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
 # post-aggregation: world values and pac_select  (Sec. 4.2 vector-lifted
 # expressions and PAC Selection; Sec. 3.2 categorical rewrites)
 # ---------------------------------------------------------------------------

@@ -428,3 +428,14 @@ def test_pac_filter_fraction_and_coin():
     # the coin is Bernoulli(p): frequency over many seeds within a binomial bound
     hits = sum(int(R.pac_filter(wv[2:3], R.SEL_GT, 5.0, seed=s)[0][0]) for s in range(4000))
     assert abs(hits / 4000 - 0.25) < 4 * math.sqrt(0.25 * 0.75 / 4000)
+
+
+def test_key_index_inverts_a_gather():
+    """The join index of key-valued foreign keys is the row-index foreign key they were gathered from."""
+    g = np.random.default_rng(51)
+    keys = gen.distinct_keys(g, 5000)
+    idx = g.integers(0, 5000, size=20000).astype(np.int32)
+    fk = keys[idx]
+    assert np.array_equal(R.key_index(keys, fk), idx)
+    missing = np.array([k for k in g.integers(-(1 << 62), 1 << 62, size=50) if k not in set(keys.tolist())])
+    assert np.all(R.key_index(keys, missing) == -1)
