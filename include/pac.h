@@ -46,6 +46,7 @@ extern "C" {
 #define PAC_STATUS_BAD_LINK 2u     /* foreign-key index out of range: row skipped */
 #define PAC_STATUS_TABLE_FULL 4u   /* sparse group hash table out of slots: rows skipped */
 #define PAC_STATUS_DIVERSITY 8u    /* strict diversity check failed in pac_finalize */
+#define PAC_STATUS_DUPLICATE_KEY 16u /* pac_key_index: a key occurs twice in the referenced table */
 
 typedef struct pac_ctx pac_ctx;
 
@@ -263,6 +264,22 @@ int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m,
  * keep [n_groups], frac [n_groups] (or NULL): device. */
 int pac_filter(pac_ctx *ctx, void *stream, const double *world_values, int64_t n_groups, int m, int32_t op,
                double threshold, uint64_t noise_seed, uint8_t *keep, double *frac);
+
+/* ---- PU-key join index (Sec. 3.2: the rewriter joins each sensitive table
+ * to the PU table along its foreign keys; Sec. 2 relational privacy unit) --- */
+
+/* The aggregation follows foreign keys given as row indices (links).  A table
+ * whose foreign key holds key values is mapped to row indices first:
+ *   out_index[r] = i with keys[i] == fk[r], or -1 when no row has that key
+ *   (an aggregation that follows such a link skips the row and reports
+ *   PAC_STATUS_BAD_LINK: a PU chain follows foreign keys).
+ * keys [n_keys] must be distinct (a repeat sets PAC_STATUS_DUPLICATE_KEY and
+ * one of the equal rows is used) and n_keys < 2^31; a key equal to
+ * PAC_EMPTY_KEY is not indexed.  The hash table (12 bytes x the next power of
+ * two >= 2 n_keys) lives in the context's scratch.  keys, fk [n],
+ * out_index [n]: device. */
+int pac_key_index(pac_ctx *ctx, void *stream, const int64_t *keys, int64_t n_keys, const int64_t *fk, int64_t n,
+                  int32_t *out_index);
 
 #ifdef __cplusplus
 }

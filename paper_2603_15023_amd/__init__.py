@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     pac_group_aggregate,
     pac_group_aggregate_batch,
     pac_hash_mask,
+    pac_key_index,
     pac_select_cmp,
     pac_world_values,
 )

@@ -78,6 +78,7 @@ EXPORTS = {
                                C.c_void_p, C.c_void_p, C.c_void_p]),
     "pac_world_values": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
                                    C.c_int32, C.c_int32, C.c_void_p]),
+    "pac_key_index": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "pac_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_int32, C.c_double,
                              C.c_uint64, C.c_void_p, C.c_void_p]),
     "pac_select_cmp": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggInput), C.c_int, C.c_uint64, C.c_void_p,

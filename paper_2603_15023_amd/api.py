@@ -293,3 +293,15 @@ def pac_filter(ctx: Context, world_values: torch.Tensor, op: str, threshold: flo
     A.check(A.load().pac_filter(ctx.handle, _stream_handle(stream), _ptr(world_values), G, m, SELECT_OPS[op],
                                 float(threshold), noise_seed & ((1 << 64) - 1), _ptr(keep), _ptr(frac)))
     return keep, frac
+
+
+def pac_key_index(ctx: Context, keys: torch.Tensor, fk: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """int32 [n] row index into ``keys`` of every key in ``fk`` (-1: no such key): a link for AggSpec.links."""
+    if keys.dtype != torch.int64 or fk.dtype != torch.int64:
+        raise TypeError("keys and fk must be int64")
+    if out is None:
+        out = torch.empty(fk.numel(), dtype=torch.int32, device=fk.device)
+    A.check(A.load().pac_key_index(ctx.handle, _stream_handle(stream), _ptr(keys), keys.numel(), _ptr(fk), fk.numel(),
+                                   _ptr(out)))
+    return out

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "pac_internal.h"
+#include "pac_join.h"
 
 struct pac_ctx {
   int device;
@@ -457,6 +458,21 @@ int pac_filter(pac_ctx *ctx, void *stream, const double *world_values, int64_t n
   pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
   const hipError_t e = pac::launch_filter(env, world_values, n_groups, m, op, threshold, noise_seed, keep, frac);
   if (e != hipSuccess) return hip_fail(e, "filter launch");
+  return PAC_OK;
+}
+
+int pac_key_index(pac_ctx *ctx, void *stream, const int64_t *keys, int64_t n_keys, const int64_t *fk, int64_t n,
+                  int32_t *out_index) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  if (n_keys < 0 || n < 0) return fail(PAC_ERR_INVALID, "negative size");
+  if (n_keys >= ((int64_t)1 << 31)) return fail(PAC_ERR_UNSUPPORTED, "more than 2^31 - 1 referenced rows");
+  if ((n_keys > 0 && !keys) || (n > 0 && (!fk || !out_index))) return fail(PAC_ERR_INVALID, "null array");
+  DeviceGuard guard(ctx->device);
+  const int rc = ensure_scratch(ctx, pac::join_scratch_bytes(n_keys));
+  if (rc != PAC_OK) return rc;
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e = pac::launch_key_index(env, keys, n_keys, fk, n, out_index, ctx->scratch);
+  if (e != hipSuccess) return hip_fail(e, "key index launch");
   return PAC_OK;
 }
 
