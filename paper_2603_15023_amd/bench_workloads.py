@@ -5,6 +5,7 @@
     python -m paper_2603_15023_amd.bench_workloads serve  [--queries 64] [--slots 4] [--load 0.7]
     python -m paper_2603_15023_amd.bench_workloads minmax [--reps 3] [--oracle-rows 20000000]
     python -m paper_2603_15023_amd.bench_workloads nested [--reps 3]
+    python -m paper_2603_15023_amd.bench_workloads join   [--reps 3]
 
 zipf:  100M rows, 2M PU keys per row, group keys Zipf(1.1) over 1M ranks
        (HBM hash table), SUM int64 + COUNT, m = 64.
@@ -16,6 +17,10 @@ nested: a correlated nested query on the 60M-row star schema (TPC-H Q17
        shape): inner AVG(qty) per part (200K parts), the per-world averages,
        pac_select(qty < 0.2 avg_j), outer SUM(v1) over the selected vectors and
        its release; each step timed.
+join:  the 60M-row star schema with the fact rows naming their order by key
+       (15M distinct int64 order keys): the join index (build over the
+       orders, probe of the fact rows), then the benchmark aggregation along
+       the resulting link.
 minmax: the float table's rows with 8 groups (its group column mod 8): COUNT,
        SUM, MIN and MAX of the FP64 column per world, m = 64, against the same
        query without MIN/MAX, and the C oracle timed on a row prefix.
@@ -180,6 +185,53 @@ def nested(args):
     ctx.close()
 
 
+def join(args):
+    from workloads import gen
+    from . import pac_hash_mask, pac_key_index
+    t = gen.config2_star()
+    o_key = gen.distinct_keys(np.random.default_rng(gen.CONFIG_SEEDS[1] + 0x300), t.o_pu.shape[0])
+    dev = torch.device("cuda")
+    ctx = Context(0)
+    K = gen.query_key(1)
+    t_okey = torch.from_numpy(o_key).to(dev)
+    t_fkey = torch.from_numpy(o_key[t.f_order]).to(dev)
+    link0 = torch.empty(t.n_rows, dtype=torch.int32, device=dev)
+    pu_key = torch.from_numpy(t.pu_key).to(dev)
+    masks = torch.empty((t.pu_key.shape[0], 1), dtype=torch.int64, device=dev)
+    spec = AggSpec(n_rows=t.n_rows, masks=masks, links=[link0, torch.from_numpy(t.o_pu).to(dev)],
+                   gcols=[torch.from_numpy(g).to(dev) for g in t.gcols], gcards=t.gcards, n_groups=6,
+                   cols=[torch.from_numpy(t.cols[c]).to(dev) for c in ("v1", "v2", "v3")],
+                   stats=[(100, 10_000_000)] * 3)
+    st = new_state(spec, 64)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def run(timed=False):
+        if timed:
+            ev[0].record()
+        pac_key_index(ctx, t_okey, t_fkey, out=link0)
+        if timed:
+            ev[1].record()
+        pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+        pac_group_aggregate(ctx, spec, st, m=64, query_key=K)
+        if timed:
+            ev[2].record()
+
+    run()
+    torch.cuda.synchronize()
+    assert torch.equal(link0.cpu(), torch.from_numpy(t.f_order)), "join index differs from the row-index keys"
+    jm, am = [], []
+    for _ in range(args.reps):
+        run(True)
+        torch.cuda.synchronize()
+        jm.append(ev[0].elapsed_time(ev[1]))
+        am.append(ev[1].elapsed_time(ev[2]))
+    ctx.check()
+    print(json.dumps({"workload": "join index: 15M order keys, 60M fact rows, then the star aggregation",
+                      "join_ms": float(np.mean(jm)), "aggregate_ms": float(np.mean(am)),
+                      "probe_rows_per_s": t.n_rows / (np.mean(jm) * 1e-3)}), flush=True)
+    ctx.close()
+
+
 def serve(args):
     from workloads import gen
     from .serve import ResidentStar, Server, latency_summary
@@ -198,7 +250,7 @@ def serve(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested"])
+    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested", "join"])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--queries", type=int, default=64)
@@ -206,7 +258,7 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--oracle-rows", type=int, default=20_000_000)
     args = ap.parse_args(argv)
-    {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested}[args.what](args)
+    {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested, "join": join}[args.what](args)
 
 
 if __name__ == "__main__":
