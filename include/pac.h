@@ -157,8 +157,8 @@ typedef struct {
 #define PAC_ALGO_BALLOT 2u  /* ballot transpose of world bits, popcounts of bit-sliced values (ints) */
 #define PAC_ALGO_MFMA_I8 3u /* int8 matrix cores on byte digits, exact int32 -> int64 recombination */
 #define PAC_ALGO_PARTITION 4u /* many groups: rows radix-partitioned by group slot, each partition in LDS */
-#define PAC_ALGO_REGISTER 5u  /* few groups (<= 8 at m = 64, <= 4 at m = 128): the plain form with every counter
-                                 in registers; up to 3 columns (2 with MIN/MAX) */
+#define PAC_ALGO_REGISTER 5u  /* up to 64 dense groups at m = 64 (32 for some column mixes), 8 or 4 at m = 128: the
+                                 plain form with every counter in registers; up to 3 columns (2 with MIN/MAX) */
 #define PAC_AGG_INIT 1u     /* clear the state (and the sparse table) before aggregating */
 
 /* m in {64, 128}; query_key is used by the fused hash.  Returns

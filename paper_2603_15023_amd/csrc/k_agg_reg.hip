@@ -16,13 +16,15 @@
 
 namespace pac {
 
-constexpr int kRegWaves = 2048;  // row ranges (one wavefront each)
+constexpr int kRegWaves = 2048;  // row ranges of the one-wave form
+constexpr int kRegShare = 8;     // wavefronts of the shared form (a workgroup per row range)
 
 struct RegPlan {
-  int S;                 // slots (groups) per wavefront
+  int S;                 // groups per wavefront (register slots)
+  int P;                 // wavefronts sharing a row range: 1, or kRegShare (groups split over them)
   int64_t n_ranges;
   int64_t slot_words;    // A*m + 1 (+ 2 (ni + nf) m with MIN/MAX)
-  size_t bytes;          // partials [n_ranges][S][slot_words]
+  size_t bytes;          // partials [n_ranges][S * P][slot_words]
 };
 
 // Column mixes with a compiled loop: up to two int and two float columns,
@@ -31,91 +33,108 @@ static bool reg_mix(int ni, int nf, bool mm) {
   return ni <= 2 && nf <= 2 && ni + nf >= 1 && ni + nf <= (mm ? 2 : 3);
 }
 
-static bool reg_plan(const DevInput &in, bool mm, RegPlan *p) {
-  if (in.group_keys || !reg_mix(in.n_icols, in.n_fcols, mm)) return false;
-  const int S = in.W == 1 ? 8 : 4;
-  if (in.n_groups > S || in.n_rows <= 0) return false;
+// Register slots per wavefront: 8, or 4 when 8 would need more than 112
+// registers (S x W x (1 + 2 (ni + nf)) (x3 for the columns with MIN/MAX)).
+static int reg_slots(int W, int ni, int nf, bool mm) {
+  const int per = W * (1 + 2 * (ni + nf) * (mm ? 3 : 1));
+  return 8 * per <= 112 ? 8 : 4;
+}
+
+static bool reg_plan(const DevInput &in, bool mm, int n_cu, RegPlan *p) {
+  if (in.group_keys || !reg_mix(in.n_icols, in.n_fcols, mm) || in.n_rows <= 0) return false;
+  const int S = reg_slots(in.W, in.n_icols, in.n_fcols, mm);
+  // Shared ranges only at m = 64: at m = 128 every record costs two words and
+  // the partitioned form was measured faster (200M rows, 64 groups: 17 vs 19 ms).
+  if (in.n_groups > (in.W == 1 ? (int64_t)S * kRegShare : (int64_t)S)) return false;
   p->S = S;
-  p->n_ranges = std::max<int64_t>(1, std::min<int64_t>(kRegWaves, (in.n_rows + 63) / 64));
+  p->P = in.n_groups <= S ? 1 : kRegShare;
+  const int64_t n_chunks = (in.n_rows + 63) / 64;
+  p->n_ranges = p->P == 1 ? std::max<int64_t>(1, std::min<int64_t>(kRegWaves, n_chunks))
+                          : std::max<int64_t>(1, std::min<int64_t>((int64_t)2 * n_cu, (n_chunks + p->P - 1) / p->P));
   const int A = 1 + in.n_icols + in.n_fcols;
   p->slot_words = (int64_t)A * in.m + 1 + (mm ? (int64_t)2 * (in.n_icols + in.n_fcols) * in.m : 0);
-  p->bytes = (size_t)p->n_ranges * S * p->slot_words * 8;
+  p->bytes = (size_t)p->n_ranges * S * p->P * p->slot_words * 8;
   return true;
 }
 
 bool reg_supported(const DevInput &in, bool minmax) {
   RegPlan p;
-  return reg_plan(in, minmax, &p);
+  return reg_plan(in, minmax, 256, &p);
 }
 
-size_t reg_scratch_bytes(const DevInput &in, bool minmax) {
+size_t reg_scratch_bytes(const DevInput &in, bool minmax, int n_cu) {
   RegPlan p;
-  return reg_plan(in, minmax, &p) ? p.bytes : 0;
+  return reg_plan(in, minmax, n_cu, &p) ? p.bytes : 0;
 }
 
+// One row of a 64-row batch: group (-1: past the end or skipped), PU words, values.
+template <int W, int NI, int NF>
+__device__ __forceinline__ int64_t reg_row(const DevInput &in, const DevState &st, int64_t r, uint32_t *status,
+                                           uint64_t (&mk)[W], uint64_t (&iv)[NI > 0 ? NI : 1],
+                                           uint64_t (&fv)[NF > 0 ? NF : 1]) {
+  int64_t g = -1;
+#pragma unroll
+  for (int w = 0; w < W; ++w) mk[w] = 0;
+  if (r < in.n_rows) {
+    g = row_group(in, st, r, status);
+    int64_t idx = 0;
+    if (g >= 0 && !chain_index(in, r, &idx, status)) g = -1;
+    if (g >= 0) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) mk[w] = pu_of_index(in, idx, w);
+#pragma unroll
+      for (int k = 0; k < NI; ++k) iv[k] = (uint64_t)load_icol(in.icols[k], in.icol_type[k], r);
+#pragma unroll
+      for (int k = 0; k < NF; ++k) fv[k] = (uint64_t)__double_as_longlong(load_fcol(in.fcols[k], in.fcol_type[k], r));
+    }
+  }
+  return g;
+}
+
+// Counters of S groups (g0 .. g0 + S - 1) of one wavefront, lane = world.
 // Partial layout of one slot: count[m], isum[NI][m], fsum[NF][m], nrows,
 // then with MIN/MAX imin[NI][m], imax[NI][m], fmin[NF][m], fmax[NF][m].
 template <int W, int NI, int NF, int S, bool MM>
-__global__ __launch_bounds__(256) void agg_reg(DevInput in, DevState st, uint32_t *status, int64_t n_ranges,
-                                               int64_t slot_words, uint64_t *partial) {
-  constexpr int m = 64 * W, A = 1 + NI + NF, NIa = NI > 0 ? NI : 1, NFa = NF > 0 ? NF : 1;
-  const int lane = threadIdx.x & 63;
-  const int64_t range = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (range >= n_ranges) return;  // whole wavefronts; no workgroup barrier below
-  const int64_t G = in.n_groups;
-  const int64_t n_chunks = (in.n_rows + 63) >> 6, cpr = (n_chunks + n_ranges - 1) / n_ranges;
-  const int64_t c0 = range * cpr, c1 = min(n_chunks, c0 + cpr);
+struct RegAcc {
+  static constexpr int NIa = NI > 0 ? NI : 1, NFa = NF > 0 ? NF : 1;
   uint32_t cn[S][W], nr[S];
   uint64_t is[S][W][NIa];
   double fs[S][W][NFa];
   int64_t imn[S][W][NIa], imx[S][W][NIa];
   double fmn[S][W][NFa], fmx[S][W][NFa];
+
+  __device__ __forceinline__ void init() {
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    nr[s] = 0;
+    for (int s = 0; s < S; ++s) {
+      nr[s] = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      cn[s][w] = 0;
+      for (int w = 0; w < W; ++w) {
+        cn[s][w] = 0;
 #pragma unroll
-      for (int k = 0; k < NIa; ++k) {
-        is[s][w][k] = 0;
-        imn[s][w][k] = INT64_MAX;
-        imx[s][w][k] = INT64_MIN;
-      }
+        for (int k = 0; k < NIa; ++k) {
+          is[s][w][k] = 0;
+          imn[s][w][k] = INT64_MAX;
+          imx[s][w][k] = INT64_MIN;
+        }
 #pragma unroll
-      for (int k = 0; k < NFa; ++k) {
-        fs[s][w][k] = 0.0;
-        fmn[s][w][k] = INFINITY;
-        fmx[s][w][k] = -INFINITY;
+        for (int k = 0; k < NFa; ++k) {
+          fs[s][w][k] = 0.0;
+          fmn[s][w][k] = INFINITY;
+          fmx[s][w][k] = -INFINITY;
+        }
       }
     }
   }
-  for (int64_t c = c0; c < c1; ++c) {
-    // the row: group (-1: past the end or skipped), PU words, values
-    const int64_t r = c * 64 + lane;
-    int64_t g = -1;
-    uint64_t mk[W], iv[NIa], fv[NFa];
-#pragma unroll
-    for (int w = 0; w < W; ++w) mk[w] = 0;
-    if (r < in.n_rows) {
-      g = row_group(in, st, r, status);
-      int64_t idx = 0;
-      if (g >= 0 && !chain_index(in, r, &idx, status)) g = -1;
-      if (g >= 0) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) mk[w] = pu_of_index(in, idx, w);
-#pragma unroll
-        for (int k = 0; k < NI; ++k) iv[k] = (uint64_t)load_icol(in.icols[k], in.icol_type[k], r);
-#pragma unroll
-        for (int k = 0; k < NF; ++k) fv[k] = (uint64_t)__double_as_longlong(load_fcol(in.fcols[k], in.fcol_type[k], r));
-      }
-    }
+
+  // The batch's records of each of the S groups, in lane (row) order.
+  __device__ __forceinline__ void batch(int64_t g, int64_t g0, int64_t G, const uint64_t (&mk)[W],
+                                        const uint64_t (&iv)[NIa], const uint64_t (&fv)[NFa], int lane) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      if (s >= G) break;
-      uint64_t todo = __ballot(g == s);
+      if (g0 + s >= G) break;
+      uint64_t todo = __ballot(g == g0 + s);
       nr[s] += (uint32_t)__popcll(todo);
-      while (todo) {  // the slot's records in row order
+      while (todo) {
         const int rr = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
         uint64_t u[NIa];
@@ -149,35 +168,108 @@ __global__ __launch_bounds__(256) void agg_reg(DevInput in, DevState st, uint32_
       }
     }
   }
-  uint64_t *out = partial + range * (slot_words * S);
+
+  // Slots g0 .. g0 + S - 1 (those below G) of the range's partial.
+  __device__ __forceinline__ void store(uint64_t *out, int64_t slot_words, int64_t g0, int64_t G, int lane) const {
+    constexpr int m = 64 * W, A = 1 + NI + NF;
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    if (s >= G) break;
-    uint64_t *b = out + (int64_t)s * slot_words;
-    const int64_t mo = (int64_t)A * m + 1;
+    for (int s = 0; s < S; ++s) {
+      if (g0 + s >= G) break;
+      uint64_t *b = out + (g0 + s) * slot_words;
+      const int64_t mo = (int64_t)A * m + 1;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int j = w * 64 + lane;
-      b[j] = cn[s][w];
+      for (int w = 0; w < W; ++w) {
+        const int j = w * 64 + lane;
+        b[j] = cn[s][w];
 #pragma unroll
-      for (int k = 0; k < NI; ++k) b[(int64_t)(1 + k) * m + j] = is[s][w][k];
+        for (int k = 0; k < NI; ++k) b[(int64_t)(1 + k) * m + j] = is[s][w][k];
 #pragma unroll
-      for (int k = 0; k < NF; ++k) b[(int64_t)(1 + NI + k) * m + j] = (uint64_t)__double_as_longlong(fs[s][w][k]);
-      if (MM) {
+        for (int k = 0; k < NF; ++k) b[(int64_t)(1 + NI + k) * m + j] = (uint64_t)__double_as_longlong(fs[s][w][k]);
+        if (MM) {
 #pragma unroll
-        for (int k = 0; k < NI; ++k) {
-          b[mo + (int64_t)k * m + j] = (uint64_t)imn[s][w][k];
-          b[mo + (int64_t)(NI + k) * m + j] = (uint64_t)imx[s][w][k];
-        }
+          for (int k = 0; k < NI; ++k) {
+            b[mo + (int64_t)k * m + j] = (uint64_t)imn[s][w][k];
+            b[mo + (int64_t)(NI + k) * m + j] = (uint64_t)imx[s][w][k];
+          }
 #pragma unroll
-        for (int k = 0; k < NF; ++k) {
-          b[mo + (int64_t)(2 * NI + k) * m + j] = (uint64_t)__double_as_longlong(fmn[s][w][k]);
-          b[mo + (int64_t)(2 * NI + NF + k) * m + j] = (uint64_t)__double_as_longlong(fmx[s][w][k]);
+          for (int k = 0; k < NF; ++k) {
+            b[mo + (int64_t)(2 * NI + k) * m + j] = (uint64_t)__double_as_longlong(fmn[s][w][k]);
+            b[mo + (int64_t)(2 * NI + NF + k) * m + j] = (uint64_t)__double_as_longlong(fmx[s][w][k]);
+          }
         }
       }
+      if (lane == 0) b[(int64_t)A * m] = nr[s];
     }
-    if (lane == 0) b[(int64_t)A * m] = nr[s];
   }
+};
+
+// One wavefront per row range; the wave holds every group (G <= S).
+template <int W, int NI, int NF, int S, bool MM>
+__global__ __launch_bounds__(256) void agg_reg(DevInput in, DevState st, uint32_t *status, int64_t n_ranges,
+                                               int64_t slot_words, uint64_t *partial) {
+  using Acc = RegAcc<W, NI, NF, S, MM>;
+  const int lane = threadIdx.x & 63;
+  const int64_t range = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (range >= n_ranges) return;  // whole wavefronts; no workgroup barrier below
+  const int64_t G = in.n_groups;
+  const int64_t n_chunks = (in.n_rows + 63) >> 6, cpr = (n_chunks + n_ranges - 1) / n_ranges;
+  const int64_t c0 = range * cpr, c1 = min(n_chunks, c0 + cpr);
+  Acc acc;
+  acc.init();
+  for (int64_t c = c0; c < c1; ++c) {
+    uint64_t mk[W], iv[Acc::NIa], fv[Acc::NFa];
+    const int64_t g = reg_row<W, NI, NF>(in, st, c * 64 + lane, status, mk, iv, fv);
+    acc.batch(g, 0, G, mk, iv, fv, lane);
+  }
+  acc.store(partial + range * (slot_words * S), slot_words, 0, G, lane);
+}
+
+// kRegShare wavefronts per row range, wave w holding groups [w S, w S + S):
+// each step the waves load kRegShare consecutive 64-row batches into LDS,
+// then every wave walks all of them in row order for its own groups.
+template <int W, int NI, int NF, int S, bool MM>
+__global__ __launch_bounds__(64 * kRegShare) void agg_reg_shared(DevInput in, DevState st, uint32_t *status,
+                                                                 int64_t n_ranges, int64_t slot_words,
+                                                                 uint64_t *partial) {
+  using Acc = RegAcc<W, NI, NF, S, MM>;
+  constexpr int P = kRegShare;
+  __shared__ int32_t s_g[P][64];
+  __shared__ uint64_t s_mk[P][W][64], s_iv[P][Acc::NIa][64], s_fv[P][Acc::NFa][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t range = blockIdx.x;  // n_ranges == gridDim.x
+  const int64_t G = in.n_groups, g0 = (int64_t)wave * S;
+  const int64_t n_chunks = (in.n_rows + 63) >> 6, cpr = (n_chunks + n_ranges - 1) / n_ranges;
+  const int64_t c0 = range * cpr, c1 = min(n_chunks, c0 + cpr);
+  Acc acc;
+  acc.init();
+  for (int64_t step = c0; step < c1; step += P) {
+    {
+      const int64_t c = step + wave;  // this wave's batch of the step (rows past the range read as absent)
+      uint64_t mk[W], iv[Acc::NIa], fv[Acc::NFa];
+      const int64_t g = c < c1 ? reg_row<W, NI, NF>(in, st, c * 64 + lane, status, mk, iv, fv) : -1;
+      s_g[wave][lane] = (int32_t)g;
+#pragma unroll
+      for (int w = 0; w < W; ++w) s_mk[wave][w][lane] = mk[w];
+#pragma unroll
+      for (int k = 0; k < NI; ++k) s_iv[wave][k][lane] = iv[k];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) s_fv[wave][k][lane] = fv[k];
+    }
+    __syncthreads();
+    for (int sub = 0; sub < P; ++sub) {  // the step's batches in row order
+      uint64_t mk[W], iv[Acc::NIa], fv[Acc::NFa];
+      const int64_t g = s_g[sub][lane];
+#pragma unroll
+      for (int w = 0; w < W; ++w) mk[w] = s_mk[sub][w][lane];
+#pragma unroll
+      for (int k = 0; k < NI; ++k) iv[k] = s_iv[sub][k][lane];
+#pragma unroll
+      for (int k = 0; k < NF; ++k) fv[k] = s_fv[sub][k][lane];
+      if (g0 < G) acc.batch(g, g0, G, mk, iv, fv, lane);
+    }
+    __syncthreads();
+  }
+  if (g0 < G) acc.store(partial + range * (slot_words * S * P), slot_words, g0, G, lane);
 }
 
 // Fixed-order merge of the range partials into the state: workgroup b takes
@@ -255,19 +347,31 @@ __global__ __launch_bounds__(256) void reg_reduce(DevState st, int ni, int nf, i
 
 using RegFn = void (*)(DevInput, DevState, uint32_t *, int64_t, int64_t, uint64_t *);
 
-template <int W, bool MM>
-static RegFn reg_fn(int ni, int nf) {
-  constexpr int S = W == 1 ? 8 : 4;
-  if (ni == 1 && nf == 0) return agg_reg<W, 1, 0, S, MM>;
-  if (ni == 2 && nf == 0) return agg_reg<W, 2, 0, S, MM>;
-  if (ni == 0 && nf == 1) return agg_reg<W, 0, 1, S, MM>;
-  if (ni == 1 && nf == 1) return agg_reg<W, 1, 1, S, MM>;
-  if (ni == 0 && nf == 2) return agg_reg<W, 0, 2, S, MM>;
+template <int W, bool MM, bool SHARED, int S>
+static RegFn reg_fn_s(int ni, int nf) {
+#define PAC_REG_K(NI_, NF_) (SHARED ? agg_reg_shared<W, NI_, NF_, S, MM> : agg_reg<W, NI_, NF_, S, MM>)
+  if (ni == 1 && nf == 0) return PAC_REG_K(1, 0);
+  if (ni == 2 && nf == 0) return PAC_REG_K(2, 0);
+  if (ni == 0 && nf == 1) return PAC_REG_K(0, 1);
+  if (ni == 1 && nf == 1) return PAC_REG_K(1, 1);
+  if (ni == 0 && nf == 2) return PAC_REG_K(0, 2);
   if constexpr (!MM) {  // three columns: without MIN/MAX only (registers)
-    if (ni == 2 && nf == 1) return agg_reg<W, 2, 1, S, MM>;
-    if (ni == 1 && nf == 2) return agg_reg<W, 1, 2, S, MM>;
+    if (ni == 2 && nf == 1) return PAC_REG_K(2, 1);
+    if (ni == 1 && nf == 2) return PAC_REG_K(1, 2);
   }
+#undef PAC_REG_K
   return nullptr;
+}
+
+template <int W, bool MM, bool SHARED>
+static RegFn reg_fn(int ni, int nf, int S) {
+  return S == 8 ? reg_fn_s<W, MM, SHARED, 8>(ni, nf) : reg_fn_s<W, MM, SHARED, 4>(ni, nf);
+}
+
+template <int W>
+static RegFn reg_fn_w(int ni, int nf, int S, bool mm, bool shared) {
+  if (mm) return shared ? reg_fn<W, true, true>(ni, nf, S) : reg_fn<W, true, false>(ni, nf, S);
+  return shared ? reg_fn<W, false, true>(ni, nf, S) : reg_fn<W, false, false>(ni, nf, S);
 }
 
 hipError_t launch_agg_reg(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
@@ -275,16 +379,21 @@ hipError_t launch_agg_reg(const LaunchEnv &env, const DevInput &in, const DevSta
   if (in.n_rows <= 0) return hipSuccess;
   const bool mm = st.minmax != 0;
   RegPlan p;
-  if (!reg_plan(in, mm, &p) || scratch_bytes < p.bytes) return hipErrorInvalidValue;
-  const RegFn fn = in.W == 1 ? (mm ? reg_fn<1, true>(in.n_icols, in.n_fcols) : reg_fn<1, false>(in.n_icols, in.n_fcols))
-                             : (mm ? reg_fn<2, true>(in.n_icols, in.n_fcols) : reg_fn<2, false>(in.n_icols, in.n_fcols));
+  if (!reg_plan(in, mm, env.n_cu, &p) || scratch_bytes < p.bytes) return hipErrorInvalidValue;
+  const bool shared = p.P > 1;
+  const RegFn fn = in.W == 1 ? reg_fn_w<1>(in.n_icols, in.n_fcols, p.S, mm, shared)
+                             : reg_fn_w<2>(in.n_icols, in.n_fcols, p.S, mm, shared);
   if (!fn) return hipErrorInvalidValue;
   uint64_t *partial = (uint64_t *)scratch;
-  hipLaunchKernelGGL(fn, dim3((unsigned)((p.n_ranges + 3) / 4)), dim3(256), 0, env.stream, in, st, env.status,
-                     p.n_ranges, p.slot_words, partial);
+  if (shared)
+    hipLaunchKernelGGL(fn, dim3((unsigned)p.n_ranges), dim3(64 * kRegShare), 0, env.stream, in, st, env.status,
+                       p.n_ranges, p.slot_words, partial);
+  else
+    hipLaunchKernelGGL(fn, dim3((unsigned)((p.n_ranges + 3) / 4)), dim3(256), 0, env.stream, in, st, env.status,
+                       p.n_ranges, p.slot_words, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t words = p.slot_words * p.S;
+  const int64_t words = p.slot_words * p.S * p.P;
   hipLaunchKernelGGL(reg_reduce, dim3((unsigned)((words + 63) / 64)), dim3(256), 0, env.stream, st, in.n_icols,
                      in.n_fcols, in.m, in.n_groups, p.slot_words, words, p.n_ranges, mm ? 1 : 0, partial);
   return hipGetLastError();

@@ -275,9 +275,9 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
     }
     case PAC_ALGO_REGISTER: {
       if (!pac::reg_supported(d, ds.minmax != 0))
-        return fail(PAC_ERR_UNSUPPORTED, "register form needs dense groups (<= 8 at m = 64, <= 4 at m = 128) and "
+        return fail(PAC_ERR_UNSUPPORTED, "register form needs at most 64 (or 32) dense groups and "
                                          "1-3 value columns (1-2 with MIN/MAX)");
-      rc = ensure_scratch(ctx, pac::reg_scratch_bytes(d, ds.minmax != 0));
+      rc = ensure_scratch(ctx, pac::reg_scratch_bytes(d, ds.minmax != 0, ctx->n_cu));
       if (rc != PAC_OK) return rc;
       e = pac::launch_agg_reg(env, d, ds, ctx->scratch, ctx->scratch_bytes);
       break;

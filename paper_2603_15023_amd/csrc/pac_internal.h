@@ -270,7 +270,7 @@ hipError_t launch_world_values(const LaunchEnv &env, const DevState &st, int m, 
                                int kind, int col, double *out);
 hipError_t launch_select_cmp(const LaunchEnv &env, const DevInput &in, const double *wv, int op, double scale,
                              double offset, uint64_t *out);
-size_t reg_scratch_bytes(const DevInput &in, bool minmax);
+size_t reg_scratch_bytes(const DevInput &in, bool minmax, int n_cu);
 hipError_t launch_agg_reg(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
                           size_t scratch_bytes);
 bool plain_fits_lds4(const DevInput &in);

@@ -166,14 +166,15 @@ def test_minmax_release_matches_oracle(ctx, torch_mod, m):
     np.testing.assert_allclose(post.cpu().numpy(), wp, rtol=1e-9, atol=1e-300)
 
 
-# Register form (few groups): every compiled column mix, with and without
-# MIN/MAX, against the oracle; float sums within 1e-12 of the sum of
+# Register form (one wavefront per row range for up to 8 (4) groups, eight
+# wavefronts sharing each row range beyond): every compiled column mix, with
+# and without MIN/MAX, against the oracle; float sums within 1e-12 of the sum of
 # magnitudes (their order differs from the oracle's), bit-identical on a rerun.
 _REG_MIXES = [(1, 0, True), (2, 0, True), (0, 1, False), (0, 1, True), (1, 1, True), (0, 2, True),
               (2, 1, False), (1, 2, False)]
 
 
-@pytest.mark.parametrize("m,G", [(64, 1), (64, 8), (128, 4)])
+@pytest.mark.parametrize("m,G", [(64, 1), (64, 8), (128, 4), (64, 61), (64, 30)])
 @pytest.mark.parametrize("mix", _REG_MIXES)
 def test_register_form_mixes(ctx, torch_mod, m, G, mix):
     import paper_2603_15023_amd as P
