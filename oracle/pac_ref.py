@@ -11,7 +11,10 @@ known-answer vectors, m-execution brute force == per-world definition
 (Theorem 2), all-ones / zero / single-bit masks against a plain GROUP BY,
 complement and popcount invariants, ``math.fsum`` for float sums, closed forms
 of the weighted variance and of the posterior after several releases,
-Monte-Carlo moments of the released noise and of the NULL coin.
+Monte-Carlo moments of the released noise and of the NULL coin, nested
+queries and lifted expressions executed once per sampled database, hand-worked
+lifted programs, pac_noised over release-scaled world vectors equal to the
+release of the same cells.
 """
 from __future__ import annotations
 
@@ -577,7 +580,7 @@ def diversity_flag(nrows: int, or_pop: int, m: int) -> bool:
 
 def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows: Sequence[int], m: int,
                         budget: float, seed: int, j_star: Optional[int] = None, flags: int = FLAG_SCALE2,
-                        prior: Optional[np.ndarray] = None):
+                        prior: Optional[np.ndarray] = None, first_cell: int = 0):
     """Release the cells in order, each with pac_noised under the running posterior.
 
     For cell c with world values y (Sec. 4.1, noise function):
@@ -588,6 +591,8 @@ def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows:
       3. y~ = y_{j*} + N(0, Delta).
       4. P <- P * W / sum(P * W),  W_j = exp(-(y~ - y_j)^2 / (2 Delta)).
     Reading: Delta = 0 releases y_{j*} exactly and skips step 4.
+    The draws of cell c are those of cell index first_cell + c, so one query's
+    cells may be released over several calls without reusing a draw.
     Returns (values, is_null, cell_flags, final P).
     """
     if j_star is None:
@@ -601,7 +606,7 @@ def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows:
             if flags & FLAG_STRICT_DIVERSITY:
                 raise ValueError(f"diversity check failed on cell {c}")
         p_null = (m - int(or_pops[c])) / m
-        if null_uniform(seed, c) < p_null:
+        if null_uniform(seed, first_cell + c) < p_null:
             vals.append(0.0)
             nulls.append(1)
             cflags.append(f | CELL_NULL)
@@ -615,7 +620,7 @@ def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows:
             nulls.append(0)
             cflags.append(f | CELL_ZERO_VARIANCE)
             continue
-        y_rel = float(y[j_star]) + math.sqrt(delta) * standard_normal(seed, c)
+        y_rel = float(y[j_star]) + math.sqrt(delta) * standard_normal(seed, first_cell + c)
         vals.append(y_rel)
         nulls.append(0)
         cflags.append(f)
@@ -643,3 +648,122 @@ def release(counters: Dict[str, np.ndarray], cells: Sequence[Tuple[int, int, int
         ns.append(int(counters["nrows"][g]))
     vals, nulls, cflags, P = pac_noised_sequence(ys, pops, ns, m, budget, seed, j_star, flags, prior)
     return vals, nulls, cflags, P, np.array(ys)
+
+
+# ---------------------------------------------------------------------------
+# vector-lifted expressions and pac_noised over given world vectors
+# (Sec. 4.2 Vector-lifted Expression, Eq. vectorexpressionlambda; Sec. 3.2
+# categorical rewrites: pac_noised on top of list_transform)
+# ---------------------------------------------------------------------------
+LIFT_INPUT, LIFT_CONST, LIFT_ADD, LIFT_SUB, LIFT_MUL, LIFT_DIV, LIFT_NEG = 0, 1, 2, 3, 4, 5, 6
+
+
+def release_world_values(counters: Dict[str, np.ndarray], kind: int, col: int = 0,
+                         flags: int = FLAG_SCALE2) -> np.ndarray:
+    """[G][m] world vectors of one aggregate as the release sees them: y_j of
+    ``cell_vector`` for every group (COUNT and SUM doubled under FLAG_SCALE2),
+    with every world that received no row of the group as NaN (SQL NULL).
+
+    Reading: an expression over several aggregates is evaluated on these
+    release-scaled values (so a ratio of two doubled sums is the ratio of the
+    sums), and pac_noised then releases the result with no further scaling.
+    """
+    G = counters["count"].shape[0]
+    y = np.stack([cell_vector(counters, g, kind, col, flags) for g in range(G)])
+    return np.where(counters["count"] > 0, y, np.nan)
+
+
+def _lift_apply(op: int, a: float, b: float) -> float:
+    if op == LIFT_ADD:
+        return a + b
+    if op == LIFT_SUB:
+        return a - b
+    if op == LIFT_MUL:
+        return a * b
+    # reading: division by zero gives SQL NULL; NULL operands give NULL
+    return a / b if b != 0.0 else math.nan
+
+
+def lift_scalar(program: Sequence[Tuple[int, int, float]], args: Sequence[float]) -> float:
+    """e(x[1], ..., x[a]) for one world: the expression as a postfix program of
+    (op, input index, constant) triples evaluated on plain floats."""
+    stack: List[float] = []
+    for op, arg, value in program:
+        if op == LIFT_INPUT:
+            stack.append(float(args[arg]))
+        elif op == LIFT_CONST:
+            stack.append(float(value))
+        elif op == LIFT_NEG:
+            stack.append(-stack.pop())
+        else:
+            b = stack.pop()
+            a = stack.pop()
+            stack.append(_lift_apply(op, a, b))
+    if len(stack) != 1:
+        raise ValueError("program leaves %d values" % len(stack))
+    return stack[0]
+
+
+def lift(inputs: Sequence[np.ndarray], program: Sequence[Tuple[int, int, float]], G: int, m: int) -> np.ndarray:
+    """Vector-lifted expression: out[g][j] = e(col_1[g][j], ..., col_a[g][j]).
+
+    A [G][m] input is a per-world vector; a [G] input is a scalar of its group,
+    broadcast to every world.  Loops over (g, j): for small cases.
+    """
+    out = np.empty((G, m))
+    for g in range(G):
+        for j in range(m):
+            args = [float(x[g]) if x.ndim == 1 else float(x[g, j]) for x in inputs]
+            out[g, j] = lift_scalar(program, args)
+    return out
+
+
+def lift_np(inputs: Sequence[np.ndarray], program: Sequence[Tuple[int, int, float]], G: int, m: int) -> np.ndarray:
+    """``lift`` with every step applied to whole [G][m] arrays (the same
+    element-wise IEEE operations, for sizes the loop form cannot reach)."""
+    stack: List[np.ndarray] = []
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for op, arg, value in program:
+            if op == LIFT_INPUT:
+                x = np.asarray(inputs[arg], dtype=np.float64)
+                stack.append(np.broadcast_to(x[:, None], (G, m)) if x.ndim == 1 else x)
+            elif op == LIFT_CONST:
+                stack.append(np.full((G, m), float(value)))
+            elif op == LIFT_NEG:
+                stack.append(-stack.pop())
+            else:
+                b = stack.pop()
+                a = stack.pop()
+                if op == LIFT_ADD:
+                    r = a + b
+                elif op == LIFT_SUB:
+                    r = a - b
+                elif op == LIFT_MUL:
+                    r = a * b
+                else:
+                    r = np.where(b != 0.0, a / np.where(b != 0.0, b, 1.0), np.nan)
+                stack.append(r)
+    if len(stack) != 1:
+        raise ValueError("program leaves %d values" % len(stack))
+    return np.array(stack[0], dtype=np.float64)
+
+
+def pac_noised(world_vectors: np.ndarray, m: int, budget: float, seed: int, j_star: Optional[int] = None,
+               flags: int = 0, prior: Optional[np.ndarray] = None, cell_rows: Optional[Sequence[int]] = None,
+               first_cell: int = 0):
+    """pac_noised over given world vectors, one released cell per row of
+    ``world_vectors`` ([n_cells][m]), in order, under the running posterior.
+
+    K (the worlds that saw a contribution) is the set of non-NULL worlds; a
+    NULL world counts as 0 in the noise calibration (Sec. 3.2 NULLs).  The
+    values are released as given (no x2).  cell_rows: rows behind each cell
+    for the diversity check, or None (no check).
+    """
+    ys, pops = [], []
+    for v in np.asarray(world_vectors, dtype=np.float64):
+        null = np.isnan(v)
+        ys.append(np.where(null, 0.0, v))
+        pops.append(int(m - np.count_nonzero(null)))
+    n = len(ys)
+    rows = [0] * n if cell_rows is None else [int(r) for r in cell_rows]
+    return pac_noised_sequence(ys, pops, rows, m, budget, seed, j_star, flags, prior, first_cell)

@@ -439,3 +439,136 @@ def test_key_index_inverts_a_gather():
     assert np.array_equal(R.key_index(keys, fk), idx)
     missing = np.array([k for k in g.integers(-(1 << 62), 1 << 62, size=50) if k not in set(keys.tolist())])
     assert np.all(R.key_index(keys, missing) == -1)
+
+
+# ----------------------------------------------------------------------------- vector-lifted expressions
+def _prog(*ops):
+    """Postfix program from ("in", k) / ("const", c) / ("add",) ... steps."""
+    code = {"in": R.LIFT_INPUT, "const": R.LIFT_CONST, "add": R.LIFT_ADD, "sub": R.LIFT_SUB, "mul": R.LIFT_MUL,
+            "div": R.LIFT_DIV, "neg": R.LIFT_NEG}
+    out = []
+    for o in ops:
+        arg = o[1] if o[0] == "in" else 0
+        val = o[1] if o[0] == "const" else 0.0
+        out.append((code[o[0]], arg, val))
+    return out
+
+
+def test_lift_hand_worked_programs():
+    """Sec. 4.2 lifting, worked by hand on values whose results are exact binary fractions."""
+    nan = float("nan")
+    a = np.array([[6.0, 4.0, nan, 1.0], [0.0, -3.0, 5.0, 2.0]])
+    b = np.array([[3.0, 0.0, 2.0, 4.0], [2.0, 2.0, 2.0, 0.0]])
+    s = np.array([2.0, 8.0])  # a scalar of each group, the same in every world
+    # (a - b) / (s * 2): operand order matters for both SUB and DIV
+    p = _prog(("in", 0), ("in", 1), ("sub",), ("in", 2), ("const", 2.0), ("mul",), ("div",))
+    got = R.lift([a, b, s], p, 2, 4)
+    want = np.array([[0.75, 1.0, nan, -0.75], [-0.125, -0.3125, 0.1875, 0.125]])
+    assert np.array_equal(np.isnan(got), np.isnan(want)) and np.array_equal(np.nan_to_num(got), np.nan_to_num(want))
+    # a / b: division by zero and NULL operands give NULL
+    got = R.lift([a, b], _prog(("in", 0), ("in", 1), ("div",)), 2, 4)
+    want = np.array([[2.0, nan, nan, 0.25], [0.0, -1.5, 2.5, nan]])
+    assert np.array_equal(np.isnan(got), np.isnan(want)) and np.array_equal(np.nan_to_num(got), np.nan_to_num(want))
+    # -(a) + b and b - a agree; the single-input program is the identity
+    p1 = R.lift([a, b], _prog(("in", 0), ("neg",), ("in", 1), ("add",)), 2, 4)
+    p2 = R.lift([a, b], _prog(("in", 1), ("in", 0), ("sub",)), 2, 4)
+    assert np.array_equal(np.isnan(p1), np.isnan(p2)) and np.array_equal(np.nan_to_num(p1), np.nan_to_num(p2))
+    ident = R.lift([a], _prog(("in", 0)), 2, 4)
+    assert np.array_equal(np.nan_to_num(ident), np.nan_to_num(a)) and np.array_equal(np.isnan(ident), np.isnan(a))
+    # malformed programs
+    with pytest.raises(ValueError):
+        R.lift_scalar(_prog(("in", 0), ("in", 1)), [1.0, 2.0])
+    with pytest.raises(IndexError):
+        R.lift_scalar(_prog(("in", 0), ("add",)), [1.0])
+
+
+def test_lift_numpy_form_equals_loop_form():
+    g = np.random.default_rng(43)
+    G, m = 6, 64
+    x = g.integers(-5, 6, size=(G, m)).astype(np.float64)
+    y = g.integers(-3, 4, size=(G, m)).astype(np.float64)
+    x[g.random(size=x.shape) < 0.1] = np.nan
+    sc = g.normal(size=G)
+    progs = [_prog(("const", 100.0), ("in", 0), ("mul",), ("in", 1), ("div",)),
+             _prog(("in", 0), ("in", 2), ("sub",), ("in", 1), ("in", 1), ("mul",), ("add",), ("neg",)),
+             _prog(("in", 2), ("in", 0), ("div",), ("const", 0.5), ("sub",))]
+    for p in progs:
+        a = R.lift([x, y, sc], p, G, m)
+        b = R.lift_np([x, y, sc], p, G, m)
+        assert np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(np.nan_to_num(a), np.nan_to_num(b))
+
+
+@pytest.mark.parametrize("m", [64, 128])
+def test_lifted_ratio_equals_per_world_brute_force(m):
+    """100 * SUM(a) / SUM(b) lifted over the release-scaled world vectors equals the ratio computed from the
+    query executed on each sampled database (Sec. 3.2 ratio rewrite, Sec. 4.2 lifting)."""
+    g = np.random.default_rng(44)
+    n, G, K = 300, 4, 0xACE
+    keys = g.integers(1, 1 << 40, size=12, dtype=np.int64)
+    pu_key = keys[g.integers(0, 12, size=n)]
+    group = g.integers(0, G - 1, size=n)
+    group[pu_key == keys[0]] = G - 1  # one group of a single PU: NULL in the worlds without it
+    a = g.integers(-20, 100, size=n, dtype=np.int64)
+    b = g.integers(1, 50, size=n, dtype=np.int64)
+    c = R.pac_agg_counters(R.pu_of_rows_flat(pu_key, K, m), group, G, [a, b])
+    wa = R.release_world_values(c, R.KIND_SUM_I, 0)
+    wb = R.release_world_values(c, R.KIND_SUM_I, 1)
+    got = R.lift([wa, wb], _prog(("const", 100.0), ("in", 0), ("mul",), ("in", 1), ("div",)), G, m)
+    bf = R.brute_force_flat(pu_key, group, G, [a, b], [], K, m)
+    n_null = 0
+    for gg in range(G):
+        for j in range(m):
+            if bf["count"][gg][j] == 0:  # the world saw no row of the group: NULL
+                assert math.isnan(got[gg, j])
+                n_null += 1
+            else:
+                sa, sb = 2.0 * bf["isum"][gg][0][j], 2.0 * bf["isum"][gg][1][j]
+                assert got[gg, j] == (100.0 * sa) / sb
+    assert n_null > 0  # the case has worlds without rows
+
+
+def _release_case(m):
+    g = np.random.default_rng(45)
+    n, G, K = 400, 5, 0xBEEF
+    keys = g.integers(1, 1 << 40, size=10, dtype=np.int64)
+    pu_key = keys[g.integers(0, 10, size=n)]
+    group = g.integers(0, G - 1, size=n)
+    group[pu_key == keys[0]] = G - 1  # one group of a single PU: worlds without rows
+    iv = g.integers(-50, 500, size=n, dtype=np.int64)
+    fv = g.normal(10.0, 3.0, size=n)
+    return R.pac_agg_counters(R.pu_of_rows_flat(pu_key, K, m), group, G, [iv], [fv], minmax=True), G
+
+
+@pytest.mark.parametrize("m", [64, 128])
+def test_pac_noised_of_release_world_values_equals_release(m):
+    """pac_noised over the release-scaled world vectors of one aggregate releases exactly what the release of
+    the same cells does: values, NULLs, flags, posterior (the lifted identity expression)."""
+    c, G = _release_case(m)
+    assert np.any(c["count"] == 0)
+    B, seed = 1.0 / 64, 0x5151
+    for kind, col in ((R.KIND_COUNT, 0), (R.KIND_SUM_I, 0), (R.KIND_AVG_I, 0), (R.KIND_SUM_F, 0),
+                      (R.KIND_AVG_F, 0), (R.KIND_MIN_I, 0), (R.KIND_MAX_F, 0)):
+        for flags in (R.FLAG_SCALE2, R.FLAG_SCALE2 | R.FLAG_AVG_TOTALCOUNT, 0):
+            cells = [(gg, kind, col) for gg in range(G)]
+            v1, n1, f1, P1, _ = R.release(c, cells, m, B, seed, flags=flags)
+            wv = R.release_world_values(c, kind, col, flags)
+            v2, n2, f2, P2 = R.pac_noised(wv, m, B, seed, cell_rows=c["nrows"])
+            assert np.array_equal(v1, v2) and np.array_equal(n1, n2) and np.array_equal(f1, f2), (kind, flags)
+            assert np.array_equal(P1, P2), (kind, flags)
+
+
+def test_pac_noised_split_over_two_calls_equals_one_call():
+    """Draw indices continue across calls (first_cell) and the posterior is carried: two calls = one call."""
+    c, G = _release_case(64)
+    wv = np.concatenate([R.release_world_values(c, R.KIND_SUM_I, 0), R.release_world_values(c, R.KIND_AVG_F, 0)])
+    rows = np.concatenate([c["nrows"], c["nrows"]])
+    B, seed = 1.0 / 32, 0x7777
+    v, n, f, P = R.pac_noised(wv, 64, B, seed, cell_rows=rows)
+    k = 4
+    va, na, fa, Pa = R.pac_noised(wv[:k], 64, B, seed, cell_rows=rows[:k])
+    vb, nb, fb, Pb = R.pac_noised(wv[k:], 64, B, seed, prior=Pa, cell_rows=rows[k:], first_cell=k)
+    assert np.array_equal(v, np.concatenate([va, vb])) and np.array_equal(n, np.concatenate([na, nb]))
+    assert np.array_equal(f, np.concatenate([fa, fb])) and np.array_equal(P, Pb)
+    # without the offset the second call would reuse the first call's draws
+    vc, _, _, _ = R.pac_noised(wv[k:], 64, B, seed, prior=Pa, cell_rows=rows[k:])
+    assert not np.array_equal(vb, vc)
