@@ -227,8 +227,17 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
  * that the j-th sampled database computes for group g -- COUNT, SUM,
  * AVG = SUM / COUNT, MIN or MAX (kind and col as in pac_cell), never scaled.
  * A world that received no row of g holds NaN (SQL NULL), except COUNT (0).
- * state, out [n_groups][m]: device.  Bad kind / col / missing state array:
- * PAC_ERR_INVALID. */
+ * With PAC_WV_RELEASE OR-ed into kind, out[g][j] is instead the world vector
+ * that pac_finalize releases for cell (g, kind, col) -- COUNT and SUM doubled
+ * with PAC_WV_SCALE2, AVG = 2 SUM / rows(g) with PAC_WV_AVG_TOTALCOUNT (the
+ * PAC_FIN_* flags of the same names) -- and every world without rows of g is
+ * NaN, COUNT included: the input of vector-lifted expressions (pac_lift) that
+ * pac_noised releases (Sec. 3.2 categorical rewrites).
+ * state, out [n_groups][m]: device.  Bad kind / col / flags / missing state
+ * array: PAC_ERR_INVALID. */
+#define PAC_WV_RELEASE 0x100
+#define PAC_WV_SCALE2 0x200
+#define PAC_WV_AVG_TOTALCOUNT 0x400
 int pac_world_values(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
                      int n_float, int32_t kind, int32_t col, double *out);
 
@@ -264,6 +273,60 @@ int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m,
  * keep [n_groups], frac [n_groups] (or NULL): device. */
 int pac_filter(pac_ctx *ctx, void *stream, const double *world_values, int64_t n_groups, int m, int32_t op,
                double threshold, uint64_t noise_seed, uint8_t *keep, double *frac);
+
+/* ---- vector-lifted expressions and pac_noised (Sec. 4.2 Vector-lifted
+ * Expression; Sec. 3.2 categorical rewrites: an expression over several
+ * aggregates is evaluated per world, then noised once) ---------------------- */
+
+/* A postfix program over per-world inputs, evaluated independently for every
+ * group g and world j:
+ *   PAC_LIFT_INPUT  push inputs[arg][g][j] (or inputs[arg][g] for a scalar input)
+ *   PAC_LIFT_CONST  push value
+ *   PAC_LIFT_ADD / SUB / MUL / DIV  pop b, pop a, push a op b (each one IEEE
+ *                   fp64 operation, rounded to nearest; no fused multiply-add)
+ *   PAC_LIFT_NEG    pop a, push -a
+ * NaN is SQL NULL and propagates; a / b with b == 0 gives NULL. */
+#define PAC_LIFT_INPUT 0
+#define PAC_LIFT_CONST 1
+#define PAC_LIFT_ADD 2
+#define PAC_LIFT_SUB 3
+#define PAC_LIFT_MUL 4
+#define PAC_LIFT_DIV 5
+#define PAC_LIFT_NEG 6
+#define PAC_LIFT_MAX_INPUTS 8
+#define PAC_LIFT_MAX_OPS 64
+#define PAC_LIFT_MAX_DEPTH 8
+typedef struct {
+  int32_t op;    /* PAC_LIFT_* */
+  int32_t arg;   /* input index for PAC_LIFT_INPUT, else 0 */
+  double value;  /* constant for PAC_LIFT_CONST, else 0 */
+} pac_lift_op;
+
+/* out[g][j] = e(inputs[0][g][j], ...) for the program e (Sec. 4.2: the
+ * pointwise extension of a scalar expression to m-vectors; scalar inputs are
+ * broadcast to every world).  inputs: host array of n_inputs device pointers,
+ * each [n_groups][m] fp64, or [n_groups] when bit k of scalar_inputs is set.
+ * program: host array of n_ops ops.  out [n_groups][m]: device, may alias no
+ * input.  A program that reads a missing input, pops an empty stack, holds
+ * more than PAC_LIFT_MAX_DEPTH values or does not end with exactly one value
+ * is rejected (PAC_ERR_INVALID) before any launch. */
+int pac_lift(pac_ctx *ctx, void *stream, const double *const *inputs, uint32_t scalar_inputs, int n_inputs,
+             int64_t n_groups, int m, const pac_lift_op *program, int n_ops, double *out);
+
+/* pac_noised over given world vectors (Sec. 4.1 noise function, Sec. 3.2
+ * NULLs, Sec. 2 adaptive composition): releases cell c = 0..n_cells-1 from
+ * world_values[c][0..m-1] exactly as pac_finalize releases a cell from its
+ * world vector, with K = the worlds whose value is not NaN (a NaN world counts
+ * as 0 in the variance and the update) and no scaling of the values.
+ * The draws of cell c are those of cell index first_cell + c (so the cells
+ * of one query may be released over several calls; j* does not depend on
+ * it).  cell_rows [n_cells]: rows behind each cell for the diversity check,
+ * or NULL (no check).  params: as for pac_finalize; PAC_FIN_SCALE2 and
+ * PAC_FIN_AVG_TOTALCOUNT are refused (they belong to pac_world_values here).
+ * world_values, cell_rows, out_*, posterior: device; params: host. */
+int pac_noised(pac_ctx *ctx, void *stream, const double *world_values, const int64_t *cell_rows, int64_t n_cells,
+               int m, int64_t first_cell, const pac_finalize_params *params, double *out_val, uint8_t *out_is_null,
+               uint32_t *out_flags, double *posterior);
 
 /* ---- PU-key join index (Sec. 3.2: the rewriter joins each sensitive table
  * to the PU table along its foreign keys; Sec. 2 relational privacy unit) --- */

@@ -17,6 +17,8 @@ from .api import (  # noqa: F401
     pac_group_aggregate_batch,
     pac_hash_mask,
     pac_key_index,
+    pac_lift,
+    pac_noised,
     pac_select_cmp,
     pac_world_values,
 )

@@ -28,6 +28,9 @@ PAC_CELL_COUNT, PAC_CELL_SUM_I, PAC_CELL_SUM_F, PAC_CELL_AVG_I, PAC_CELL_AVG_F =
 PAC_CELL_MIN_I, PAC_CELL_MAX_I, PAC_CELL_MIN_F, PAC_CELL_MAX_F = 5, 6, 7, 8
 PAC_FIN_SCALE2, PAC_FIN_AVG_TOTALCOUNT, PAC_FIN_STRICT_DIVERSITY, PAC_FIN_FIXED_PRIOR, PAC_FIN_PRIOR_IN = 1, 2, 4, 8, 16
 PAC_CELL_NULL, PAC_CELL_DIVERSITY, PAC_CELL_ZERO_VARIANCE = 1, 2, 4
+PAC_WV_RELEASE, PAC_WV_SCALE2, PAC_WV_AVG_TOTALCOUNT = 0x100, 0x200, 0x400
+PAC_LIFT_INPUT, PAC_LIFT_CONST, PAC_LIFT_ADD, PAC_LIFT_SUB, PAC_LIFT_MUL, PAC_LIFT_DIV, PAC_LIFT_NEG = range(7)
+PAC_LIFT_MAX_INPUTS, PAC_LIFT_MAX_OPS, PAC_LIFT_MAX_DEPTH = 8, 64, 8
 
 
 class AggInput(C.Structure):
@@ -53,6 +56,10 @@ class AggState(C.Structure):
 
 class Cell(C.Structure):
     _fields_ = [("group", C.c_int64), ("kind", C.c_int32), ("col", C.c_int32)]
+
+
+class LiftOp(C.Structure):
+    _fields_ = [("op", C.c_int32), ("arg", C.c_int32), ("value", C.c_double)]
 
 
 class FinalizeParams(C.Structure):
@@ -83,6 +90,10 @@ EXPORTS = {
                              C.c_uint64, C.c_void_p, C.c_void_p]),
     "pac_select_cmp": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggInput), C.c_int, C.c_uint64, C.c_void_p,
                                  C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_void_p]),
+    "pac_lift": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, C.c_int, C.c_int64, C.c_int,
+                           C.POINTER(LiftOp), C.c_int, C.c_void_p]),
+    "pac_noised": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_int64,
+                             C.POINTER(FinalizeParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

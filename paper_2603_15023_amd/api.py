@@ -258,16 +258,75 @@ SELECT_OPS = {"<": A.PAC_SEL_LT, "<=": A.PAC_SEL_LE, "==": A.PAC_SEL_EQ, "!=": A
 
 
 def pac_world_values(ctx: Context, state: Dict[str, torch.Tensor], kind: str, col: int = 0, m: int = 64,
-                     out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """[G, m] per-world results of one aggregate of ``state`` (NaN for SQL NULL worlds)."""
+                     out: Optional[torch.Tensor] = None, release: bool = False, scale2: bool = True,
+                     avg_totalcount: bool = False, stream=None) -> torch.Tensor:
+    """[G, m] per-world results of one aggregate of ``state`` (NaN for SQL NULL worlds).
+
+    release=True: the world vectors the release uses (COUNT/SUM doubled with scale2, AVG over all rows with
+    avg_totalcount), every world without rows NULL -- the inputs of ``pac_lift`` / ``pac_noised``."""
     G = int(state["count"].shape[0])
     if out is None:
         out = torch.empty((G, m), dtype=torch.float64, device=state["count"].device)
+    k = CELL_KINDS[kind]
+    if release:
+        k |= A.PAC_WV_RELEASE | (A.PAC_WV_SCALE2 if scale2 else 0) | (A.PAC_WV_AVG_TOTALCOUNT if avg_totalcount else 0)
     cst = _state_c(state)
     A.check(A.load().pac_world_values(ctx.handle, _stream_handle(stream), C.byref(cst), m, G,
-                                      int(state["isum"].shape[1]), int(state["fsum"].shape[1]), CELL_KINDS[kind],
-                                      int(col), _ptr(out)))
+                                      int(state["isum"].shape[1]), int(state["fsum"].shape[1]), k, int(col),
+                                      _ptr(out)))
     return out
+
+
+LIFT_OPS = {"in": A.PAC_LIFT_INPUT, "const": A.PAC_LIFT_CONST, "add": A.PAC_LIFT_ADD, "sub": A.PAC_LIFT_SUB,
+            "mul": A.PAC_LIFT_MUL, "div": A.PAC_LIFT_DIV, "neg": A.PAC_LIFT_NEG}
+
+
+def pac_lift(ctx: Context, inputs: Sequence[torch.Tensor], program: Sequence[tuple], m: int = 64,
+             out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Vector-lifted expression: [G, m] = program applied per (group, world).
+
+    inputs: float64 tensors [G, m] (per-world) or [G] (a scalar of each group, broadcast over the worlds).
+    program: postfix steps ("in", k), ("const", c), ("add",), ("sub",), ("mul",), ("div",), ("neg",)."""
+    if not inputs and out is None:
+        raise ValueError("without inputs, pass out (its first dimension is the number of groups)")
+    G = int(inputs[0].shape[0]) if inputs else int(out.shape[0])
+    scalar = 0
+    for k, t in enumerate(inputs):
+        if t.dtype != torch.float64 or int(t.shape[0]) != G or t.dim() not in (1, 2) or (t.dim() == 2 and
+                                                                                       int(t.shape[1]) != m):
+            raise ValueError(f"input {k}: float64 [{G}] or [{G}, {m}] expected, got {t.dtype} {tuple(t.shape)}")
+        if t.dim() == 1:
+            scalar |= 1 << k
+    ops = (A.LiftOp * max(1, len(program)))()
+    for i, step in enumerate(program):
+        ops[i].op = LIFT_OPS[step[0]]
+        ops[i].arg = int(step[1]) if step[0] == "in" else 0
+        ops[i].value = float(step[1]) if step[0] == "const" else 0.0
+    ptrs = (C.c_void_p * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    if out is None:
+        out = torch.empty((G, m), dtype=torch.float64, device=inputs[0].device)
+    A.check(A.load().pac_lift(ctx.handle, _stream_handle(stream), ptrs, scalar, len(inputs), G, m, ops, len(program),
+                              _ptr(out)))
+    return out
+
+
+def pac_noised(ctx: Context, world_values: torch.Tensor, m: int = 64, mi_budget: float = 1.0 / 128,
+               noise_seed: int = 0, j_star: int = -1, flags: int = 0, prior: Optional[torch.Tensor] = None,
+               cell_rows: Optional[torch.Tensor] = None, first_cell: int = 0, stream=None):
+    """Release each row of ``world_values`` [n_cells, m] as one cell; returns (values, is_null, flags, posterior)."""
+    n = int(world_values.shape[0])
+    dev = world_values.device
+    vals = torch.empty(n, dtype=torch.float64, device=dev)
+    nulls = torch.empty(n, dtype=torch.uint8, device=dev)
+    cflags = torch.empty(n, dtype=torch.int32, device=dev)
+    post = torch.empty(m, dtype=torch.float64, device=dev)
+    if prior is not None:
+        post.copy_(prior)
+        flags |= A.PAC_FIN_PRIOR_IN
+    params = A.FinalizeParams(float(mi_budget), noise_seed & ((1 << 64) - 1), int(j_star), int(flags))
+    A.check(A.load().pac_noised(ctx.handle, _stream_handle(stream), _ptr(world_values), _ptr(cell_rows), n, m,
+                                int(first_cell), C.byref(params), _ptr(vals), _ptr(nulls), _ptr(cflags), _ptr(post)))
+    return vals, nulls, cflags, post
 
 
 def pac_select_cmp(ctx: Context, rows: AggSpec, world_values: torch.Tensor, op: str, scale: float = 1.0,

@@ -14,7 +14,7 @@
 // Randomness is counter based (Philox4x32-10 keyed by the query's noise
 // seed, counter = (cell, purpose)), so every draw depends only on the seed
 // and the cell index, never on execution order.
-#include "pac_internal.h"
+#include "pac_post.h"
 
 namespace pac {
 
@@ -124,6 +124,45 @@ __global__ __launch_bounds__(256) void cell_vectors_kernel(DevState st, const pa
     const double p_null = (double)(m - pop) / (double)m;
     if (to_unit(a) < p_null) flags |= PAC_CELL_NULL;
     draw2(fp.seed, c, kDrawNoise, &a, &b);
+    const double u1 = to_unit(a), u2 = to_unit(b);
+    const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
+    meta[ci] = CellMeta{z, flags, 0u};
+  }
+}
+
+// Phase 1 of pac_noised over given world vectors: as cell_vectors_kernel,
+// with y read from the caller's [n_cells][m] vectors (a NaN world is NULL:
+// not in K, 0 in y) and the draws of cell index first + c.
+template <int W>
+__global__ __launch_bounds__(256) void noised_vectors_kernel(const double *__restrict__ wv,
+                                                             const int64_t *__restrict__ cell_rows, FinParams fp,
+                                                             int64_t first, int64_t c0, int64_t nc, double *ybuf,
+                                                             CellMeta *meta, uint32_t *status) {
+  constexpr int m = 64 * W;
+  const int lane = threadIdx.x & 63;
+  const int64_t ci = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (ci >= nc) return;
+  const int64_t c = c0 + ci;
+  int pop = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int j = lane + 64 * w;
+    const double v = wv[c * m + j];
+    const bool null = v != v;
+    pop += __popcll(__ballot(!null));
+    ybuf[ci * m + j] = null ? 0.0 : v;
+  }
+  if (lane == 0) {
+    uint32_t flags = 0;
+    if (cell_rows && cell_rows[c] >= 16 && pop <= (m == 64 ? 40 : 80)) {
+      flags |= PAC_CELL_DIVERSITY;
+      if (fp.flags & PAC_FIN_STRICT_DIVERSITY) atomicOr(status, PAC_STATUS_DIVERSITY);
+    }
+    uint64_t a, b;
+    draw2(fp.seed, first + c, kDrawNull, &a, &b);
+    const double p_null = (double)(m - pop) / (double)m;
+    if (to_unit(a) < p_null) flags |= PAC_CELL_NULL;
+    draw2(fp.seed, first + c, kDrawNoise, &a, &b);
     const double u1 = to_unit(a), u2 = to_unit(b);
     const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
     meta[ci] = CellMeta{z, flags, 0u};
@@ -370,6 +409,33 @@ hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_c
     else
       hipLaunchKernelGGL(release_chain_kernel<2>, dim3(1), dim3(64), 0, env.stream, fp, c0, nc, ybuf, meta, out_val,
                          out_is_null, out_flags, posterior, c0 == 0 ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_noised(const LaunchEnv &env, const double *wv, const int64_t *cell_rows, int64_t first_cell,
+                         const FinParams &fp, double *out_val, uint8_t *out_is_null, uint32_t *out_flags,
+                         double *posterior, void *scratch) {
+  const int m = fp.m;
+  const int64_t chunk = fp.n_cells < kCellChunk ? fp.n_cells : kCellChunk;
+  double *ybuf = (double *)scratch;
+  CellMeta *meta = (CellMeta *)(((uintptr_t)(ybuf + chunk * m) + 255) & ~(uintptr_t)255);
+  if (fp.n_cells == 0) {  // posterior out = prior (or uniform)
+    hipLaunchKernelGGL(m == 64 ? release_chain_kernel<1> : release_chain_kernel<2>, dim3(1), dim3(64), 0, env.stream,
+                       fp, (int64_t)0, (int64_t)0, ybuf, meta, out_val, out_is_null, out_flags, posterior, 1);
+    return hipGetLastError();
+  }
+  for (int64_t c0 = 0; c0 < fp.n_cells; c0 += chunk) {
+    const int64_t nc = fp.n_cells - c0 < chunk ? fp.n_cells - c0 : chunk;
+    const int blocks = (int)((nc + 3) / 4);
+    hipLaunchKernelGGL(m == 64 ? noised_vectors_kernel<1> : noised_vectors_kernel<2>, dim3(blocks), dim3(256), 0,
+                       env.stream, wv, cell_rows, fp, first_cell, c0, nc, ybuf, meta, env.status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(m == 64 ? release_chain_kernel<1> : release_chain_kernel<2>, dim3(1), dim3(64), 0, env.stream,
+                       fp, c0, nc, ybuf, meta, out_val, out_is_null, out_flags, posterior, c0 == 0 ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -6,34 +6,53 @@
 //     `value op scale * world_value[g][j] + offset`, g the row's group in the
 //     inner aggregate.  A following aggregation over these per-row vectors is
 //     the outer query of a correlated nested query (e.g. rows below a
-//     fraction of their part's average).
+//     fraction of their part's average);
+//   * vector-lifted expressions: a postfix program over per-world inputs,
+//     evaluated for every (group, world) -- e.g. a ratio of two sums -- whose
+//     result pac_noised releases once.
 #include <algorithm>
 
-#include "pac_internal.h"
+#include "pac_post.h"
 
 namespace pac {
 
-// out[g][j], one thread per (group, world).
+// out[g][j], one thread per (group, world).  kind carries the PAC_WV_* flags
+// above its low byte: with PAC_WV_RELEASE the value is the release's world
+// vector (the same operations as the release's phase 1) and every world
+// without rows is NULL, COUNT included.
 __global__ __launch_bounds__(256) void world_values_kernel(DevState st, int m, int64_t G, int n_int, int n_float,
                                                            int kind, int col, double *out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= G * m) return;
   const int64_t g = t / m;
   const int j = (int)(t % m);
+  const int k = kind & 0xFF;
+  const bool rel = (kind & PAC_WV_RELEASE) != 0;
   const int64_t cnt = st.count[t];
   double v;
-  switch (kind) {
-    case PAC_CELL_COUNT: out[t] = (double)cnt; return;
-    case PAC_CELL_SUM_I: v = (double)st.isum[(g * n_int + col) * m + j]; break;
-    case PAC_CELL_AVG_I: v = (double)st.isum[(g * n_int + col) * m + j] / (double)(cnt > 0 ? cnt : 1); break;
-    case PAC_CELL_SUM_F: v = st.fsum[(g * n_float + col) * m + j]; break;
-    case PAC_CELL_AVG_F: v = st.fsum[(g * n_float + col) * m + j] / (double)(cnt > 0 ? cnt : 1); break;
+  switch (k) {
+    case PAC_CELL_COUNT: v = (double)cnt; break;
+    case PAC_CELL_SUM_I:
+    case PAC_CELL_AVG_I: v = (double)st.isum[(g * n_int + col) * m + j]; break;
+    case PAC_CELL_SUM_F:
+    case PAC_CELL_AVG_F: v = st.fsum[(g * n_float + col) * m + j]; break;
     case PAC_CELL_MIN_I: v = (double)st.imin[(g * n_int + col) * m + j]; break;
     case PAC_CELL_MAX_I: v = (double)st.imax[(g * n_int + col) * m + j]; break;
     case PAC_CELL_MIN_F: v = st.fmin[(g * n_float + col) * m + j]; break;
     default: v = st.fmax[(g * n_float + col) * m + j]; break;
   }
-  out[t] = cnt > 0 ? v : __longlong_as_double(0x7FF8000000000000ll);  // NULL world: NaN
+  if (k == PAC_CELL_AVG_I || k == PAC_CELL_AVG_F) {
+    if (rel && (kind & PAC_WV_AVG_TOTALCOUNT)) {
+      const double nr = (double)st.nrows[g];
+      v = nr > 0.0 ? (2.0 * v) / nr : 0.0;
+    } else {
+      v = v / (double)(cnt > 0 ? cnt : 1);
+    }
+  } else if ((kind & PAC_WV_SCALE2) && (k == PAC_CELL_COUNT || k == PAC_CELL_SUM_I || k == PAC_CELL_SUM_F)) {
+    v = 2.0 * v;
+  }
+  const bool null = cnt <= 0 && (rel || k != PAC_CELL_COUNT);
+  out[t] = null ? __longlong_as_double(0x7FF8000000000000ll) : v;  // NULL world: NaN
 }
 
 __device__ __forceinline__ bool sel_cmp(double v, int op, double t) {
@@ -88,6 +107,70 @@ __global__ __launch_bounds__(256) void select_cmp_kernel(DevInput in, DevState s
       for (int w = 0; w < W; ++w) out[r * W + w] = res[w];
     }
   }
+}
+
+// ---------------------------------------------------------------- vector-lifted expressions
+// The value stack lives in registers: the stack pointer is the same in every
+// lane (one program for all), and each access selects among the fixed slots.
+__device__ __forceinline__ double stk_get(const double (&s)[PAC_LIFT_MAX_DEPTH], int i) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < PAC_LIFT_MAX_DEPTH; ++k) r = k == i ? s[k] : r;
+  return r;
+}
+
+__device__ __forceinline__ void stk_put(double (&s)[PAC_LIFT_MAX_DEPTH], int i, double v) {
+#pragma unroll
+  for (int k = 0; k < PAC_LIFT_MAX_DEPTH; ++k) s[k] = k == i ? v : s[k];
+}
+
+// One thread per (group, world), grid-stride.  The host has checked the
+// program: every input index exists, the stack never underflows, never holds
+// more than PAC_LIFT_MAX_DEPTH values and ends with one.
+__global__ __launch_bounds__(256) void lift_kernel(LiftProg p, int64_t G, int m_shift, double *out) {
+  const int64_t n = G << m_shift;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int64_t g = t >> m_shift;
+    double s[PAC_LIFT_MAX_DEPTH];
+#pragma unroll
+    for (int k = 0; k < PAC_LIFT_MAX_DEPTH; ++k) s[k] = 0.0;
+    int sp = 0;
+    for (int i = 0; i < p.n_ops; ++i) {
+      const int op = p.op[i];
+      if (op == PAC_LIFT_INPUT) {
+        const int a = p.arg[i];
+        const double *x = p.in[a];
+        stk_put(s, sp, ((p.scalar >> a) & 1u) ? x[g] : x[t]);
+        ++sp;
+      } else if (op == PAC_LIFT_CONST) {
+        stk_put(s, sp, p.val[i]);
+        ++sp;
+      } else if (op == PAC_LIFT_NEG) {
+        stk_put(s, sp - 1, -stk_get(s, sp - 1));
+      } else {
+        const double b = stk_get(s, sp - 1), a = stk_get(s, sp - 2);
+        double r;
+        switch (op) {
+          case PAC_LIFT_ADD: r = __dadd_rn(a, b); break;
+          case PAC_LIFT_SUB: r = __dsub_rn(a, b); break;
+          case PAC_LIFT_MUL: r = __dmul_rn(a, b); break;
+          default: r = b == 0.0 ? __longlong_as_double(0x7FF8000000000000ll) : __ddiv_rn(a, b); break;
+        }
+        --sp;
+        stk_put(s, sp - 1, r);
+      }
+    }
+    out[t] = s[0];
+  }
+}
+
+hipError_t launch_lift(const LaunchEnv &env, const LiftProg &prog, int64_t G, int m, double *out) {
+  const int64_t n = G * m;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, (int64_t)env.n_cu * 16);
+  hipLaunchKernelGGL(lift_kernel, dim3(blocks), dim3(256), 0, env.stream, prog, G, m == 64 ? 6 : 7, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_world_values(const LaunchEnv &env, const DevState &st, int m, int64_t G, int n_int, int n_float,

@@ -10,6 +10,7 @@
 
 #include "pac_internal.h"
 #include "pac_join.h"
+#include "pac_post.h"
 
 struct pac_ctx {
   int device;
@@ -405,6 +406,14 @@ int pac_world_values(pac_ctx *ctx, void *stream, const pac_agg_state *state, int
   if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
   if (n_groups < 1 || n_int < 0 || n_float < 0) return fail(PAC_ERR_INVALID, "bad sizes");
   if (!state->count) return fail(PAC_ERR_INVALID, "state.count missing");
+  const int32_t wv_flags = kind & ~0xFF;
+  if (wv_flags & ~(PAC_WV_RELEASE | PAC_WV_SCALE2 | PAC_WV_AVG_TOTALCOUNT))
+    return fail(PAC_ERR_INVALID, "unknown world-value flags 0x%x", (unsigned)wv_flags);
+  if (wv_flags && !(wv_flags & PAC_WV_RELEASE))
+    return fail(PAC_ERR_INVALID, "PAC_WV_SCALE2 / PAC_WV_AVG_TOTALCOUNT need PAC_WV_RELEASE");
+  if ((wv_flags & PAC_WV_AVG_TOTALCOUNT) && !state->nrows) return fail(PAC_ERR_INVALID, "state.nrows missing");
+  const int32_t full_kind = kind;
+  kind &= 0xFF;
   const bool on_int = kind == PAC_CELL_SUM_I || kind == PAC_CELL_AVG_I || kind == PAC_CELL_MIN_I || kind == PAC_CELL_MAX_I;
   const bool on_float = kind == PAC_CELL_SUM_F || kind == PAC_CELL_AVG_F || kind == PAC_CELL_MIN_F || kind == PAC_CELL_MAX_F;
   if (kind != PAC_CELL_COUNT && !on_int && !on_float) return fail(PAC_ERR_INVALID, "bad kind %d", kind);
@@ -421,7 +430,7 @@ int pac_world_values(pac_ctx *ctx, void *stream, const pac_agg_state *state, int
   pac::DevState ds{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used,
                    state->imin,  state->imax, state->fmin, state->fmax,  0};
   pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
-  const hipError_t e = pac::launch_world_values(env, ds, m, n_groups, n_int, n_float, kind, col, out);
+  const hipError_t e = pac::launch_world_values(env, ds, m, n_groups, n_int, n_float, full_kind, col, out);
   if (e != hipSuccess) return hip_fail(e, "world values launch");
   return PAC_OK;
 }
@@ -500,6 +509,86 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
   hipError_t e =
       pac::launch_finalize(env, ds, cells, fp, out_val, out_is_null, out_flags, posterior, out_y, ctx->scratch);
   if (e != hipSuccess) return hip_fail(e, "finalize launch");
+  return PAC_OK;
+}
+
+int pac_lift(pac_ctx *ctx, void *stream, const double *const *inputs, uint32_t scalar_inputs, int n_inputs,
+             int64_t n_groups, int m, const pac_lift_op *program, int n_ops, double *out) {
+  if (!ctx || !program) return fail(PAC_ERR_INVALID, "null context or program");
+  if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
+  if (n_groups < 0) return fail(PAC_ERR_INVALID, "bad sizes");
+  if (n_inputs < 0 || n_inputs > PAC_LIFT_MAX_INPUTS)
+    return fail(PAC_ERR_INVALID, "n_inputs must be 0..%d (got %d)", PAC_LIFT_MAX_INPUTS, n_inputs);
+  if (n_inputs > 0 && !inputs) return fail(PAC_ERR_INVALID, "null inputs");
+  if (n_ops < 1 || n_ops > PAC_LIFT_MAX_OPS)
+    return fail(PAC_ERR_INVALID, "n_ops must be 1..%d (got %d)", PAC_LIFT_MAX_OPS, n_ops);
+  if (scalar_inputs >> n_inputs) return fail(PAC_ERR_INVALID, "scalar_inputs names a missing input");
+  pac::LiftProg prog{};
+  prog.scalar = scalar_inputs;
+  prog.n_ops = n_ops;
+  int depth = 0;
+  for (int i = 0; i < n_ops; ++i) {
+    const pac_lift_op &o = program[i];
+    switch (o.op) {
+      case PAC_LIFT_INPUT:
+        if (o.arg < 0 || o.arg >= n_inputs) return fail(PAC_ERR_INVALID, "op %d reads missing input %d", i, o.arg);
+        ++depth;
+        break;
+      case PAC_LIFT_CONST: ++depth; break;
+      case PAC_LIFT_NEG:
+        if (depth < 1) return fail(PAC_ERR_INVALID, "op %d pops an empty stack", i);
+        break;
+      case PAC_LIFT_ADD:
+      case PAC_LIFT_SUB:
+      case PAC_LIFT_MUL:
+      case PAC_LIFT_DIV:
+        if (depth < 2) return fail(PAC_ERR_INVALID, "op %d needs two values", i);
+        --depth;
+        break;
+      default: return fail(PAC_ERR_INVALID, "op %d: unknown opcode %d", i, o.op);
+    }
+    if (depth > PAC_LIFT_MAX_DEPTH) return fail(PAC_ERR_INVALID, "op %d: stack deeper than %d", i, PAC_LIFT_MAX_DEPTH);
+    prog.op[i] = (int8_t)o.op;
+    prog.arg[i] = (int8_t)(o.op == PAC_LIFT_INPUT ? o.arg : 0);
+    prog.val[i] = o.value;
+  }
+  if (depth != 1) return fail(PAC_ERR_INVALID, "the program leaves %d values (needs 1)", depth);
+  if (n_groups == 0) return PAC_OK;
+  if (!out) return fail(PAC_ERR_INVALID, "null output");
+  for (int k = 0; k < n_inputs; ++k) {
+    if (!inputs[k]) return fail(PAC_ERR_INVALID, "input %d is null", k);
+    if (inputs[k] == out) return fail(PAC_ERR_INVALID, "input %d aliases the output", k);
+    prog.in[k] = inputs[k];
+  }
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e = pac::launch_lift(env, prog, n_groups, m, out);
+  if (e != hipSuccess) return hip_fail(e, "lift launch");
+  return PAC_OK;
+}
+
+int pac_noised(pac_ctx *ctx, void *stream, const double *world_values, const int64_t *cell_rows, int64_t n_cells,
+               int m, int64_t first_cell, const pac_finalize_params *params, double *out_val, uint8_t *out_is_null,
+               uint32_t *out_flags, double *posterior) {
+  if (!ctx || !params) return fail(PAC_ERR_INVALID, "null context or params");
+  if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
+  if (n_cells < 0 || first_cell < 0) return fail(PAC_ERR_INVALID, "bad sizes");
+  if (!posterior) return fail(PAC_ERR_INVALID, "posterior buffer is required");
+  if (!(params->mi_budget > 0.0)) return fail(PAC_ERR_INVALID, "mi_budget must be > 0");
+  if (params->j_star >= m) return fail(PAC_ERR_INVALID, "j_star out of range");
+  if (params->flags & ~31u) return fail(PAC_ERR_INVALID, "unknown finalize flags 0x%x", params->flags);
+  if (params->flags & (PAC_FIN_SCALE2 | PAC_FIN_AVG_TOTALCOUNT))
+    return fail(PAC_ERR_INVALID, "PAC_FIN_SCALE2 / PAC_FIN_AVG_TOTALCOUNT apply to pac_world_values, not pac_noised");
+  if (n_cells > 0 && (!world_values || !out_val || !out_is_null || !out_flags))
+    return fail(PAC_ERR_INVALID, "null world value or output arrays");
+  DeviceGuard guard(ctx->device);
+  pac::FinParams fp{params->mi_budget, params->noise_seed, params->j_star, params->flags, m, 0, 0, n_cells, 1};
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const int rc = ensure_scratch(ctx, pac::finalize_scratch_bytes(m, n_cells));
+  if (rc != PAC_OK) return rc;
+  const hipError_t e = pac::launch_noised(env, world_values, cell_rows, first_cell, fp, out_val, out_is_null, out_flags,
+                                          posterior, ctx->scratch);
+  if (e != hipSuccess) return hip_fail(e, "noised launch");
   return PAC_OK;
 }
 

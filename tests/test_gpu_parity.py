@@ -463,8 +463,9 @@ def test_finalize_matches_oracle(ctx, torch_mod, m):
     t.cols["f0"] = np.random.default_rng(2).lognormal(0, 2, size=t.n_rows)
     K = 1234
     ints, flts = ["v0", "v1"], ["f0"]
-    got = gpu_star(ctx, t, K, m, int_cols=ints, float_cols=flts, algo="plain")
-    counters = {k: got[k] for k in ("count", "isum", "fsum", "nrows")}
+    # the release reads the oracle's counters (uploaded as the state): its inputs never come from the GPU
+    want_c = star_oracle(t, K, m, int_cols=ints, float_cols=flts)
+    counters = {k: want_c[k] for k in ("count", "isum", "fsum", "nrows")}
     cells = []
     for g in range(6):
         cells += [(g, R.KIND_COUNT, 0), (g, R.KIND_SUM_I, 0), (g, R.KIND_AVG_I, 1), (g, R.KIND_SUM_F, 0),
@@ -488,8 +489,8 @@ def _release_case(ctx, torch_mod, m, cells, B, seed, flags, j_star=-1, prior=Non
     import paper_2603_15023_amd as P
     t = gen.tiny_star(33, n_pu=60, n_orders=600, n_rows=9000, gcards=(3, 2), n_cols=1, value_range=(1, 10**5))
     t.cols["f0"] = np.random.default_rng(3).lognormal(0, 1, size=t.n_rows)
-    got = gpu_star(ctx, t, 77, m, int_cols=["v0"], float_cols=["f0"], algo="plain")
-    counters = {k: got[k] for k in ("count", "isum", "fsum", "nrows")}
+    want_c = star_oracle(t, 77, m, int_cols=["v0"], float_cols=["f0"])
+    counters = {k: want_c[k] for k in ("count", "isum", "fsum", "nrows")}
     dev = torch_mod.device("cuda")
     state = {k: torch_mod.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in counters.items()}
     pr = None if prior is None else torch_mod.from_numpy(prior).to(dev)
