@@ -6,6 +6,7 @@
     python -m paper_2603_15023_amd.bench_workloads minmax [--reps 3] [--oracle-rows 20000000]
     python -m paper_2603_15023_amd.bench_workloads nested [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads join   [--reps 3]
+    python -m paper_2603_15023_amd.bench_workloads ratio  [--reps 3] [--seeds 200]
 
 zipf:  100M rows, 2M PU keys per row, group keys Zipf(1.1) over 1M ranks
        (HBM hash table), SUM int64 + COUNT, m = 64.
@@ -21,6 +22,13 @@ join:  the 60M-row star schema with the fact rows naming their order by key
        (15M distinct int64 order keys): the join index (build over the
        orders, probe of the fact rows), then the benchmark aggregation along
        the resulting link.
+ratio: the ratio rewrite on the 60M-row star schema: per group, the three
+       expressions 100 S1 / S3, 100 S2 / S3 and 100 (S1 + S2) / S3 of the
+       sums S_i = SUM(v_i), each evaluated per world on the release-scaled
+       world vectors and noised once (pac_lift + pac_noised), each step
+       timed; then, over --seeds noise seeds, the error of that release
+       against noising each SUM on its own and combining the released values
+       (the paper's naive form).
 minmax: the float table's rows with 8 groups (its group column mod 8): COUNT,
        SUM, MIN and MAX of the FP64 column per world, m = 64, against the same
        query without MIN/MAX, and the C oracle timed on a row prefix.
@@ -232,6 +240,78 @@ def join(args):
     ctx.close()
 
 
+def ratio(args):
+    from workloads import gen
+    from . import cells_tensor, pac_finalize, pac_hash_mask, pac_lift, pac_noised, pac_world_values
+    t = gen.config2_star()
+    dev = torch.device("cuda")
+    ctx = Context(0)
+    K, B = gen.query_key(3), 1.0 / 128
+    vals = [t.cols[c] for c in ("v1", "v2", "v3")]
+    pu_key = torch.from_numpy(t.pu_key).to(dev)
+    links = [torch.from_numpy(t.f_order).to(dev), torch.from_numpy(t.o_pu).to(dev)]
+    masks = torch.empty((t.pu_key.shape[0], 1), dtype=torch.int64, device=dev)
+    spec = AggSpec(n_rows=t.n_rows, masks=masks, links=links, gcols=[torch.from_numpy(g).to(dev) for g in t.gcols],
+                   gcards=t.gcards, n_groups=6, cols=[torch.from_numpy(v).to(dev) for v in vals],
+                   stats=[(100, 10_000_000)] * 3)
+    st = new_state(spec, 64)
+    # 100 S1 / S3, 100 S2 / S3, 100 (S1 + S2) / S3 over the world vectors (S1, S2, S3)
+    progs = [[("const", 100.0), ("in", 0), ("mul",), ("in", 2), ("div",)],
+             [("const", 100.0), ("in", 1), ("mul",), ("in", 2), ("div",)],
+             [("const", 100.0), ("in", 0), ("in", 1), ("add",), ("mul",), ("in", 2), ("div",)]]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+
+    def run(seed, ev=None):
+        rec = (lambda i: ev[i].record()) if ev else (lambda i: None)
+        rec(0)
+        pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+        pac_group_aggregate(ctx, spec, st, m=64, query_key=K)
+        rec(1)
+        wv = [pac_world_values(ctx, st, "sum_i", c, release=True) for c in range(3)]
+        rec(2)
+        lifted = torch.cat([pac_lift(ctx, wv, p) for p in progs])  # cell 6 e + g
+        rec(3)
+        out = pac_noised(ctx, lifted, mi_budget=B, noise_seed=seed)
+        rec(4)
+        return out
+
+    run(1)
+    torch.cuda.synchronize()
+    steps = {"hash + aggregate (3 SUMs)": [], "world values (3)": [], "lift (3 expressions)": [],
+             "pac_noised (18 cells)": []}
+    for _ in range(args.reps):
+        run(1, evs)
+        torch.cuda.synchronize()
+        for i, k in enumerate(steps):
+            steps[k].append(evs[i].elapsed_time(evs[i + 1]))
+    ms = {k: float(np.mean(v)) for k, v in steps.items()}
+
+    def exprs(s):  # the three expressions from per-group sums s[c][g]
+        return np.concatenate([100.0 * s[0] / s[2], 100.0 * s[1] / s[2], 100.0 * (s[0] + s[1]) / s[2]])
+
+    # utility: the lifted release against noising each SUM and combining the released values (the same budget
+    # per released cell)
+    g_row = 2 * t.gcols[0].astype(np.int64) + t.gcols[1].astype(np.int64)
+    truth = exprs(np.array([np.bincount(g_row, weights=v.astype(np.float64), minlength=6) for v in vals]))
+    naive_cells = cells_tensor([(g, 1, c) for c in range(3) for g in range(6)])  # SUM cells, column-major
+    err_l, err_n = [], []
+    for s in range(args.seeds):
+        seed = gen.noise_seed(100 + s)
+        rel = run(seed)[0].cpu().numpy()
+        nv = pac_finalize(ctx, st, naive_cells, 18, mi_budget=B, noise_seed=seed)[0].cpu().numpy().reshape(3, 6)
+        err_l.append(np.abs(rel - truth) / np.abs(truth))
+        err_n.append(np.abs(exprs(nv) - truth) / np.abs(truth))
+    ctx.check()
+    err_l, err_n = np.concatenate(err_l), np.concatenate(err_n)
+    print(json.dumps({"workload": "ratio rewrite, 60M fact rows, 6 groups x 3 expressions (100 S1/S3, 100 S2/S3, "
+                      "100 (S1+S2)/S3), m=64, B=1/128 per cell", "ms": sum(ms.values()), "steps_ms": ms,
+                      "seeds": args.seeds,
+                      "rel_err_lifted": {"median": float(np.median(err_l)), "p90": float(np.quantile(err_l, 0.9))},
+                      "rel_err_naive": {"median": float(np.median(err_n)), "p90": float(np.quantile(err_n, 0.9))}}),
+          flush=True)
+    ctx.close()
+
+
 def serve(args):
     from workloads import gen
     from .serve import ResidentStar, Server, latency_summary
@@ -250,7 +330,8 @@ def serve(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested", "join"])
+    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested", "join", "ratio"])
+    ap.add_argument("--seeds", type=int, default=200)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--queries", type=int, default=64)
@@ -258,7 +339,8 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--oracle-rows", type=int, default=20_000_000)
     args = ap.parse_args(argv)
-    {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested, "join": join}[args.what](args)
+    {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested, "join": join,
+     "ratio": ratio}[args.what](args)
 
 
 if __name__ == "__main__":
