@@ -252,6 +252,9 @@ def main():
         log(f"calibration copy: {ne * 8} bytes read and written per launch")
         del src, dst
 
+    stream = stream_read_gbs(dev)
+    log(f"stream read: {stream['gbs']:.0f} GB/s ({stream['kernel']})")
+
     alg_bytes = 30 * n + 4 * n_orders + 8 * n_pu  # fact columns + o_pu + the PU word table, each once
     alg_kv = 30 * n + 8 * n_orders  # fact columns + the orders' PU keys
     achieved = (alg_kv if args.algo == "mfma_kv" else alg_bytes) / (agg_ms * 1e-3) / 1e9
@@ -295,6 +298,7 @@ def main():
                                          / 1e9 / HBM_PEAK_GBS, 4))
                   for k, v in forms.items()},
         "roofline": roofline,
+        "stream_read": dict(stream, frac_of_stream=round(achieved / stream["gbs"], 4)),
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -302,6 +306,28 @@ def main():
     ctx_prep.close()
     ctx_rel.close()
     ctx.close()
+
+
+def stream_read_gbs(dev, gib=2.0, reps=10):
+    """The read rate of plain streaming reductions over `gib` GiB in this job (the best of a float32 and an int64
+    sum): what a read-only kernel reaches on this GPU, beside the datasheet peak."""
+    import torch
+    best = None
+    for dt in (torch.float32, torch.int64):
+        x = torch.ones(int(gib * (1 << 30)) // torch.tensor([], dtype=dt).element_size(), dtype=dt, device=dev)
+        x.sum()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            x.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = x.numel() * x.element_size() * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        if best is None or gbs > best["gbs"]:
+            best = {"gbs": round(gbs, 1), "kernel": f"torch sum over {gib:g} GiB of {str(dt).split('.')[-1]}"}
+        del x
+    return best
 
 
 def serve_measurement(args):

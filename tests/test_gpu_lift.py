@@ -183,3 +183,32 @@ def test_lifted_ratio_release_chain(ctx, torch_mod, m):
     np.testing.assert_allclose(both[0].cpu().numpy(), split[0], rtol=1e-12, atol=0)
     np.testing.assert_allclose(both[3].cpu().numpy(), second[3].cpu().numpy(), rtol=1e-9, atol=1e-300)
     assert ctx.status() == 0
+
+
+def test_noised_and_lift_degenerate_cases(ctx, torch_mod):
+    """No cells (the prior comes back), an infinite budget (y_{j*} exactly), an all-NULL cell (always NULL),
+    a program of constants only, one group."""
+    import math
+    import paper_2603_15023_amd as P
+    dev = torch_mod.device("cuda")
+    prior = torch_mod.from_numpy(np.random.default_rng(5).dirichlet(np.ones(64))).to(dev)
+    v, n, f, post = P.pac_noised(ctx, torch_mod.empty((0, 64), dtype=torch_mod.float64, device=dev), m=64,
+                                 prior=prior)
+    assert v.numel() == 0 and torch_mod.equal(post.cpu(), prior.cpu())
+    y = torch_mod.arange(64, dtype=torch_mod.float64, device=dev)[None, :].contiguous()
+    v, n, f, post = P.pac_noised(ctx, y, m=64, mi_budget=math.inf, noise_seed=7, j_star=5)
+    assert v.item() == 5.0 and n.item() == 0 and (int(f.item()) & R.CELL_ZERO_VARIANCE)
+    allnull = torch_mod.full((2, 128), float("nan"), dtype=torch_mod.float64, device=dev)
+    v, n, f, post = P.pac_noised(ctx, allnull, m=128, noise_seed=7)
+    assert n.cpu().tolist() == [1, 1] and torch_mod.allclose(post.cpu(), torch_mod.full((128,), 1.0 / 128,
+                                                                                        dtype=torch_mod.float64))
+    out = torch_mod.empty((3, 128), dtype=torch_mod.float64, device=dev)
+    P.pac_lift(ctx, [], [("const", 2.0), ("const", 0.0), ("div",)], m=128, out=out)
+    assert torch_mod.isnan(out).all()
+    P.pac_lift(ctx, [], [("const", 1.5), ("neg",)], m=128, out=out)
+    assert (out == -1.5).all()
+    one = torch_mod.tensor([[4.0] * 64], dtype=torch_mod.float64, device=dev)
+    got = P.pac_lift(ctx, [one, torch_mod.tensor([2.0], dtype=torch_mod.float64, device=dev)],
+                     [("in", 0), ("in", 1), ("div",)], m=64)
+    assert (got == 2.0).all()
+    assert ctx.status() == 0
