@@ -153,7 +153,7 @@ def nested(args):
     masks = torch.empty((t.pu_key.shape[0], 1), dtype=torch.int64, device=dev)
     n_parts = 200_000
     inner = AggSpec(n_rows=t.n_rows, masks=masks, links=links, gcols=[part], gcards=[n_parts], n_groups=n_parts,
-                    cols=[qty])
+                    cols=[qty], stats=[(1, 50)])  # quantity 1..50: pac_select takes its table form
     st_in = new_state(inner, 64)
     cells = cells_tensor([(0, 1, 0)])  # SUM of the int column
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)]

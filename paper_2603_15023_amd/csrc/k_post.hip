@@ -67,13 +67,53 @@ __device__ __forceinline__ bool sel_cmp(double v, int op, double t) {
   }
 }
 
+// Table form for an integer compared value with a small known range
+// [lo, lo + R): for every group g and value v, the m-bit word of worlds j with
+// v op scale * y_j(g) + offset, one wave per group (lane = world; lane k of
+// each 64-value batch keeps the ballot of value k and writes it, so the table
+// rows are written contiguously).  The comparison is the one the row-wise
+// form makes, on the same doubles, so a table word equals that form's result.
+template <int W>
+__global__ __launch_bounds__(256) void sel_table_kernel(const double *wv, int64_t G, int op, double scale,
+                                                        double offset, int64_t lo, int32_t R, uint64_t *table) {
+  constexpr int m = 64 * W;
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (g >= G) return;
+  double t[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) t[w] = __dadd_rn(__dmul_rn(scale, wv[g * m + 64 * w + lane]), offset);
+  for (int v0 = 0; v0 < R; v0 += 64) {
+    uint64_t mine[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) mine[w] = 0;
+    const int nb = R - v0 < 64 ? R - v0 : 64;
+    for (int k = 0; k < nb; ++k) {
+      const double v = (double)(lo + v0 + k);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t bits = __ballot(sel_cmp(v, op, t[w]));
+        mine[w] = lane == k ? bits : mine[w];
+      }
+    }
+    if (lane < nb) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) table[((g * R) + v0 + lane) * W + w] = mine[w];
+    }
+  }
+}
+
 // Lane = world.  Each wave takes 64-row batches; for every live row of the
 // batch (broadcast by readlane) lane j reads world value [g][64 w + j] (one
 // coalesced 512-byte read per row and word), compares, and the ballot ANDed
 // with the row's PU word is that row's output word, kept by the row's lane.
-template <int W>
+// With a table (TAB), a row whose integer value lies in [lo, lo + R) takes its
+// word from the table instead (one 8-byte read per word); only the other rows
+// go through the per-world loop.
+template <int W, bool TAB>
 __global__ __launch_bounds__(256) void select_cmp_kernel(DevInput in, DevState st, uint32_t *status, const double *wv,
-                                                         int op, double scale, double offset, uint64_t *out) {
+                                                         int op, double scale, double offset, const uint64_t *table,
+                                                         int64_t lo, int32_t R, uint64_t *out) {
   constexpr int m = 64 * W;
   const int lane = threadIdx.x & 63;
   const int64_t n_chunks = (in.n_rows + 63) >> 6;
@@ -88,7 +128,16 @@ __global__ __launch_bounds__(256) void select_cmp_kernel(DevInput in, DevState s
     uint64_t res[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) res[w] = 0;
-    uint64_t todo = __ballot(g >= 0);
+    bool done = false;
+    if (TAB && g >= 0) {
+      const uint64_t d = (uint64_t)((int64_t)iv[0] - lo);  // wraps to a large value below lo
+      if (d < (uint64_t)R) {
+        done = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) res[w] = table[((g * R) + (int64_t)d) * W + w] & mk[w];
+      }
+    }
+    uint64_t todo = __ballot(g >= 0 && !done);
     while (todo) {
       const int rr = __ffsll((unsigned long long)todo) - 1;
       todo &= todo - 1;
@@ -184,16 +233,36 @@ hipError_t launch_world_values(const LaunchEnv &env, const DevState &st, int m, 
 
 hipError_t launch_select_cmp(const LaunchEnv &env, const DevInput &in, const double *wv, int op, double scale,
                              double offset, uint64_t *out) {
+  return launch_select_table(env, in, wv, op, scale, offset, 0, 0, nullptr, out);
+}
+
+hipError_t launch_select_table(const LaunchEnv &env, const DevInput &in, const double *wv, int op, double scale,
+                               double offset, int64_t lo, int32_t R, uint64_t *table, uint64_t *out) {
   if (in.n_rows <= 0) return hipSuccess;
+  const bool tab = table != nullptr && R > 0;
+  if (tab) {
+    const unsigned gblocks = (unsigned)((in.n_groups + 3) / 4);
+    if (in.W == 1)
+      hipLaunchKernelGGL(sel_table_kernel<1>, dim3(gblocks), dim3(256), 0, env.stream, wv, in.n_groups, op, scale,
+                         offset, lo, R, table);
+    else
+      hipLaunchKernelGGL(sel_table_kernel<2>, dim3(gblocks), dim3(256), 0, env.stream, wv, in.n_groups, op, scale,
+                         offset, lo, R, table);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int64_t n_chunks = (in.n_rows + 63) / 64;
   const int blocks = (int)std::min<int64_t>((n_chunks + 3) / 4, (int64_t)env.n_cu * 8);
   DevState none{};
-  if (in.W == 1)
-    hipLaunchKernelGGL(select_cmp_kernel<1>, dim3(blocks), dim3(256), 0, env.stream, in, none, env.status, wv, op,
-                       scale, offset, out);
-  else
-    hipLaunchKernelGGL(select_cmp_kernel<2>, dim3(blocks), dim3(256), 0, env.stream, in, none, env.status, wv, op,
-                       scale, offset, out);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, env.stream, in, none, env.status, wv, op, scale, offset,
+                       (const uint64_t *)table, lo, R, out);
+  };
+  if (in.W == 1) {
+    if (tab) go(select_cmp_kernel<1, true>); else go(select_cmp_kernel<1, false>);
+  } else {
+    if (tab) go(select_cmp_kernel<2, true>); else go(select_cmp_kernel<2, false>);
+  }
   return hipGetLastError();
 }
 

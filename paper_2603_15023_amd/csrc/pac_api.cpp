@@ -73,6 +73,11 @@ bool is_int(int t) { return t == PAC_I32 || t == PAC_I64; }
 bool is_float(int t) { return t == PAC_F32 || t == PAC_F64; }
 bool is_gtype(int t) { return t == PAC_U8 || t == PAC_U16 || t == PAC_U32; }
 
+// pac_select_cmp's table form: at most this many distinct compared values,
+// and at most this much scratch for the [groups][values] word table.
+constexpr int64_t kSelTableMaxRange = 4096;
+constexpr int64_t kSelTableMaxBytes = (int64_t)1 << 30;
+
 int bit_length(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
 // Validates one input and builds the kernel view.  Returns PAC_OK or an error.
@@ -451,7 +456,24 @@ int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m,
   if (d.n_rows == 0) return PAC_OK;
   DeviceGuard guard(ctx->device);
   pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
-  const hipError_t e = pac::launch_select_cmp(env, d, world_values, op, scale, offset, out_masks);
+  // Table form: an int compared value with statistics of a small range, and a
+  // table (groups x values) smaller than what the row-wise form reads.
+  int64_t lo = 0;
+  int32_t R = 0;
+  uint64_t *table = nullptr;
+  if (rows->has_stats && is_int(rows->col_type[0])) {
+    const __int128 range = (__int128)rows->col_max[0] - (__int128)rows->col_min[0] + 1;
+    const __int128 entries = range * (__int128)d.n_groups;
+    if (range >= 1 && range <= kSelTableMaxRange && entries <= (__int128)d.n_rows * 32 &&
+        entries * 8 * d.W <= (__int128)kSelTableMaxBytes) {
+      lo = rows->col_min[0];
+      R = (int32_t)range;
+      const int rc2 = ensure_scratch(ctx, (size_t)entries * 8 * (size_t)d.W);
+      if (rc2 != PAC_OK) return rc2;
+      table = (uint64_t *)ctx->scratch;
+    }
+  }
+  const hipError_t e = pac::launch_select_table(env, d, world_values, op, scale, offset, lo, R, table, out_masks);
   if (e != hipSuccess) return hip_fail(e, "select launch");
   return PAC_OK;
 }

@@ -15,6 +15,11 @@ struct LiftProg {
   double val[PAC_LIFT_MAX_OPS];
 };
 
+// pac_select_cmp through a table of the comparison's words for every group and
+// integer value in [lo, lo + R) (table: [n_groups][R][W] words of scratch);
+// rows with other values take the row-wise form.
+hipError_t launch_select_table(const LaunchEnv &env, const DevInput &in, const double *wv, int op, double scale,
+                               double offset, int64_t lo, int32_t R, uint64_t *table, uint64_t *out);
 hipError_t launch_lift(const LaunchEnv &env, const LiftProg &prog, int64_t G, int m, double *out);
 hipError_t launch_noised(const LaunchEnv &env, const double *wv, const int64_t *cell_rows, int64_t first_cell,
                          const FinParams &fp, double *out_val, uint8_t *out_is_null, uint32_t *out_flags,

@@ -129,3 +129,42 @@ def test_pac_filter_matches_oracle(ctx, torch_mod, m):
         assert np.array_equal(keep.cpu().numpy(), k_want), kind
         assert 0 < int(k_want.sum()) < G  # the case mixes kept and dropped groups
     assert ctx.status() == 0
+
+
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("stats", [(1, 50), (10, 30), (-5, 200)])
+def test_select_table_form_matches_oracle(ctx, torch_mod, m, stats):
+    """An int compared value with column statistics goes through the per-group table of comparison words; rows
+    whose value lies outside the stated range (10..30 on data 1..50) take the row-wise form.  Either way the
+    selected vectors equal the oracle's bit for bit, for every comparison, with a filter and the FK chain."""
+    import paper_2603_15023_amd as P
+    t = gen.tiny_star(84, n_pu=500, n_orders=5000, n_rows=60_001, gcards=(7, 3), n_cols=1, with_sel=True,
+                      value_range=(1, 50))
+    K, lt = 0xAB12 + m, 3 << 30
+    dev = torch_mod.device("cuda")
+    masks = P.pac_hash_mask(ctx, torch_mod.from_numpy(t.pu_key).to(dev), K, m)
+    links = [torch_mod.from_numpy(t.f_order).to(dev), torch_mod.from_numpy(t.o_pu).to(dev)]
+    gc = [torch_mod.from_numpy(g).to(dev) for g in t.gcols]
+    filt = torch_mod.from_numpy(t.sel.view(np.int32)).to(dev)
+    v0 = torch_mod.from_numpy(t.cols["v0"]).to(dev)
+    G = 21
+    inner = P.AggSpec(n_rows=t.n_rows, masks=masks, links=links, gcols=gc, gcards=[7, 3], n_groups=G,
+                      filter_col=filt, filter_lt=lt, cols=[v0])
+    st = P.new_state(inner, m)
+    P.pac_group_aggregate(ctx, inner, st, m=m)
+    c_in = ON.onepass(t.n_rows, m, masks=R.pac_hash_np(t.pu_key, K, m), links=[t.f_order, t.o_pu], gcols=t.gcols,
+                      gcards=[7, 3], n_groups=G, filter_col=t.sel, filter_lt=lt, int_cols=[t.cols["v0"]])
+    w_want = R.world_values(c_in, R.KIND_AVG_I, 0)
+    wv = torch_mod.from_numpy(w_want).to(dev)  # the oracle's world values (NaN worlds included)
+    pu_rows = R.pu_of_rows_star(t.pu_key, t.o_pu, t.f_order, K, m)
+    group = np.where(t.sel < lt, R.dense_group(t.gcols, [7, 3]).astype(np.int64), -1)
+    rows = P.AggSpec(n_rows=t.n_rows, masks=masks, links=links, gcols=gc, gcards=[7, 3], n_groups=G,
+                     filter_col=filt, filter_lt=lt, cols=[v0], stats=[stats])
+    for op, cop in (("<", R.SEL_LT), ("<=", R.SEL_LE), ("==", R.SEL_EQ), ("!=", R.SEL_NE), (">", R.SEL_GT),
+                    (">=", R.SEL_GE)):
+        for scale, offset in ((1.0, 0.0), (0.6, 0.5)):
+            _say("select table", m, stats, op, scale)
+            sel = P.pac_select_cmp(ctx, rows, wv, op, scale, offset, m=m)
+            want = R.pac_select_cmp_np(pu_rows, group, t.cols["v0"], w_want, cop, scale, offset)
+            assert np.array_equal(sel.cpu().numpy().view(np.uint64), want), (op, scale)
+    assert ctx.status() == 0
