@@ -260,7 +260,13 @@ int pac_world_values(pac_ctx *ctx, void *stream, const pac_agg_state *state, int
  * filtered out or whose group is out of range gets 0 (the latter also sets
  * PAC_STATUS_BAD_GROUP).  out_masks: device [n_rows][m/64]; a following
  * pac_group_aggregate over the same rows takes masks = out_masks,
- * n_masks = n_rows and no links. */
+ * n_masks = n_rows and no links.
+ * When cols[0] is an int column with statistics (has_stats) spanning at most
+ * 4096 values, and n_groups x values <= 32 n_rows, the comparison words of
+ * every (group, value) are first written to the context's scratch
+ * (n_groups x values x m/8 bytes, at most 1 GiB) and each row reads its word
+ * there; the result is the same, and rows whose value lies outside the stated
+ * range are compared directly. */
 int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m, uint64_t query_key,
                    const double *world_values, int64_t n_wv_groups, int32_t op, double scale, double offset,
                    uint64_t *out_masks);
