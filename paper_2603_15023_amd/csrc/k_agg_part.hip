@@ -11,7 +11,12 @@
 //                 chunks, so a heavy group -- Zipf head -- is split over many
 //                 workgroups);
 //   3. scatter:   each live row's PU words and values go to its partition as
-//                 a compact record (structure of arrays);
+//                 a compact record (structure of arrays).  With many
+//                 partitions (integer columns) this takes two passes: rows to
+//                 about sqrt(partitions) coarse buckets, then each bucket's
+//                 records to its fine partitions -- a workgroup then writes
+//                 into few partitions at a time, so its partly written lines
+//                 stay in L2 instead of going out one record at a time;
 //   4. aggregate: a workgroup takes work items from a queue, accumulates the
 //                 records into LDS counters [2^SB slots][A][m] (lane = world,
 //                 records broadcast, LDS atomics), then adds the non-zero
@@ -54,7 +59,18 @@ struct PartPlan {
   size_t off_pfirst;    // deterministic: first work item and item count of each partition
   size_t off_row_slot, off_count, off_off, off_cur, off_items, off_meta, off_rec_slot, off_rec_mk, off_rec_iv,
       off_rec_fv, total;
+  // two-pass scatter (S2 > 0): 2^S2 fine partitions per coarse bucket
+  int S2;
+  int64_t n_coarse, chunk2, max_items2;
+  size_t off_ccount, off_coff, off_ccur, off_items2, off_meta2, off_tmp_slot, off_tmp_mk, off_tmp_iv;
 };
+
+// Above this many partitions the integer form scatters in two passes.
+constexpr int64_t kTwoPassParts = 1024;
+#ifndef PART_SCATTER_WG_PER_CU
+#define PART_SCATTER_WG_PER_CU 1
+#endif
+constexpr int kScatterWgPerCu = PART_SCATTER_WG_PER_CU;  // 1024-thread workgroups per CU in both passes
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr int kPartLdsTarget = 80 * 1024;  // two workgroups per CU
@@ -120,6 +136,22 @@ static bool part_plan(const DevInput &in, PartPlan *pl) {
   p.off_rec_mk = o;   o = align256(o + 8 * (size_t)in.W * p.cap);
   p.off_rec_iv = o;   o = align256(o + 8 * (size_t)in.n_icols * p.cap);
   p.off_rec_fv = o;   o = align256(o + 8 * (size_t)in.n_fcols * p.cap);
+  if (!p.det && p.n_parts > kTwoPassParts && p.n_parts <= (int64_t)256 * 256) {
+    int bits = 0;
+    while (((int64_t)1 << bits) < p.n_parts) ++bits;
+    p.S2 = std::min(8, (bits + 1) / 2);  // both passes write into about sqrt(n_parts) <= 256 partitions
+    p.n_coarse = (p.n_parts + ((int64_t)1 << p.S2) - 1) >> p.S2;
+    p.chunk2 = 65536;
+    p.max_items2 = p.n_coarse + p.cap / p.chunk2 + 1;
+    p.off_ccount = o;   o = align256(o + 4 * (size_t)p.n_coarse);
+    p.off_coff = o;     o = align256(o + 8 * (size_t)(p.n_coarse + 1));
+    p.off_ccur = o;     o = align256(o + 4 * (size_t)p.n_coarse);
+    p.off_items2 = o;   o = align256(o + sizeof(PartItem) * (size_t)p.max_items2);
+    p.off_meta2 = o;    o = align256(o + 2 * sizeof(int64_t));
+    p.off_tmp_slot = o; o = align256(o + 4 * (size_t)p.cap);
+    p.off_tmp_mk = o;   o = align256(o + 8 * (size_t)in.W * p.cap);
+    p.off_tmp_iv = o;   o = align256(o + 8 * (size_t)in.n_icols * p.cap);
+  }
   p.total = o;
   *pl = p;
   return true;
@@ -289,6 +321,215 @@ __global__ __launch_bounds__(1024) void part_scatter_lds(DevInput in, uint32_t *
 #pragma unroll
     for (int k = 0; k < kMaxCols; ++k)
       if (k < in.n_fcols) rec_fv[k * cap + pos] = fv[k];
+  }
+}
+
+// Two-pass scatter, between the passes: rows of each coarse bucket (the sum of
+// its 2^S2 fine partitions' counts), one thread per bucket.
+__global__ __launch_bounds__(256) void part_coarse_count(const uint32_t *count, int64_t n_parts, int S2,
+                                                         int64_t n_coarse, uint32_t *ccount) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_coarse) return;
+  const int64_t p0 = c << S2, p1 = min(n_parts, (c + 1) << S2);
+  uint32_t n = 0;
+  for (int64_t p = p0; p < p1; ++p) n += count[p];
+  ccount[c] = n;
+}
+
+// Both passes of the two-pass scatter place their records tile by tile: the
+// 1024 records of a tile (one per thread) are ordered by bucket in LDS, so
+// that consecutive threads write consecutive positions of a bucket's range
+// instead of one record per cache line.  LDS: the buckets' cursors, the tile's
+// per-bucket counts and offsets (at most kTileBuckets buckets), then the
+// staged tile: slot, bucket and payload words (PU words, int and float
+// values) of every record in bucket order.
+constexpr int kTileBuckets = 256;
+constexpr int kTileRecs = 1024;
+
+__host__ __device__ constexpr size_t tile_lds_bytes(int words) {
+  return (size_t)(3 * kTileBuckets + 2 * kTileRecs) * 4 + (size_t)words * kTileRecs * 8;
+}
+
+struct TileLds {
+  uint32_t *base, *tcount, *toff, *s_slot, *s_q;
+  uint64_t *s_pay;
+  __device__ explicit TileLds(uint8_t *raw) {
+    base = (uint32_t *)raw;
+    tcount = base + kTileBuckets;
+    toff = tcount + kTileBuckets;
+    s_slot = toff + kTileBuckets;
+    s_q = s_slot + kTileRecs;
+    s_pay = (uint64_t *)(s_q + kTileRecs);
+  }
+};
+
+// Exclusive scan of tcount[0..nb) into toff (wave 0; nb <= 4 * 64).
+__device__ __forceinline__ void tile_scan(const TileLds &L, int nb) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    uint32_t a[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = 4 * t + k < nb ? L.tcount[4 * t + k] : 0u;
+      sum += a[k];
+    }
+    uint32_t incl = sum;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      if (t >= d) incl += v;
+    }
+    uint32_t ex = incl - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (4 * t + k < nb) L.toff[4 * t + k] = ex;
+      ex += a[k];
+    }
+  }
+}
+
+// Output pointers of the payload words: PU words, then int columns
+// (structure of arrays, `cap` records each).
+constexpr int kPayMax = 2 + kMaxCols;
+struct PayOut {
+  uint64_t *p[kPayMax];
+};
+
+// One tile: each live thread holds a record (bucket q, output slot, payload
+// of `words` words); records are ranked in their bucket, staged in bucket
+// order, then written from the staged order to base[q] + rank.  Every thread
+// of the workgroup calls it (barriers inside).
+__device__ __forceinline__ void tile_place(const TileLds &L, int nb, bool live, uint32_t q, uint32_t slot_out,
+                                           const uint64_t (&pay)[kPayMax], int words, uint32_t *out_slot,
+                                           const PayOut &out) {
+  const int t = threadIdx.x;
+  for (int b = t; b < nb; b += blockDim.x) L.tcount[b] = 0;
+  __syncthreads();
+  const uint32_t lr = live ? atomicAdd(&L.tcount[q], 1u) : 0u;
+  __syncthreads();
+  tile_scan(L, nb);
+  __syncthreads();
+  if (live) {
+    const uint32_t si = L.toff[q] + lr;
+    L.s_slot[si] = slot_out;
+    L.s_q[si] = q;
+#pragma unroll
+    for (int k = 0; k < kPayMax; ++k)
+      if (k < words) L.s_pay[k * kTileRecs + si] = pay[k];
+  }
+  const uint32_t n_live = (uint32_t)__syncthreads_count(live);
+  if ((uint32_t)t < n_live) {
+    const uint32_t qq = L.s_q[t];
+    const int64_t pos = (int64_t)L.base[qq] + (t - (int64_t)L.toff[qq]);
+    out_slot[pos] = L.s_slot[t];
+#pragma unroll
+    for (int k = 0; k < kPayMax; ++k)
+      if (k < words) out.p[k][pos] = L.s_pay[k * kTileRecs + t];
+  }
+  __syncthreads();
+  for (int b = t; b < nb; b += blockDim.x) L.base[b] += L.tcount[b];
+  __syncthreads();
+}
+
+template <int W>
+__device__ __forceinline__ PayOut pay_out(int ni, int64_t cap, uint64_t *mk, uint64_t *iv) {
+  PayOut o{};
+#pragma unroll
+  for (int w = 0; w < W; ++w) o.p[w] = mk + w * cap;
+#pragma unroll
+  for (int c = 0; c < kMaxCols; ++c) o.p[W + c] = c < ni ? iv + c * cap : nullptr;
+  return o;
+}
+
+// Two-pass scatter (integer columns only), pass 1: rows -> coarse buckets
+// (nb <= kTileBuckets buckets of 2^SBC slots).  The workgroup counts its rows
+// per bucket, reserves one range per bucket, then places its rows tile by
+// tile.  Each record keeps its slot within the bucket.  A row the route gave
+// a slot has a valid FK chain, so every counted row is placed.
+template <int W>
+__global__ __launch_bounds__(1024) void part_scatter_coarse(DevInput in, uint32_t *status, const uint32_t *row_slot,
+                                                            const int64_t *coff, uint32_t *ccur, int SBC, int nb,
+                                                            int64_t cap, uint32_t *tmp_slot, uint64_t *tmp_mk,
+                                                            uint64_t *tmp_iv) {
+  extern __shared__ uint8_t tile_raw[];
+  const TileLds L(tile_raw);
+  const int t = threadIdx.x;
+  const int words = W + in.n_icols;
+  const PayOut out = pay_out<W>(in.n_icols, cap, tmp_mk, tmp_iv);
+  for (int b = t; b < nb; b += blockDim.x) L.base[b] = 0;
+  __syncthreads();
+  const int64_t n = in.n_rows, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + t; r < n; r += stride) {
+    const uint32_t sl = row_slot[r];
+    if (sl != kNoSlot) atomicAdd(&L.base[sl >> SBC], 1u);
+  }
+  __syncthreads();
+  for (int b = t; b < nb; b += blockDim.x)
+    if (L.base[b]) L.base[b] = (uint32_t)(coff[b] + atomicAdd(&ccur[b], L.base[b]));
+  __syncthreads();
+  const uint32_t lmask = (1u << SBC) - 1u;
+  for (int64_t rt = (int64_t)blockIdx.x * blockDim.x; rt < n; rt += stride) {
+    const int64_t r = rt + t;
+    const uint32_t sl = r < n ? row_slot[r] : kNoSlot;
+    const bool live = sl != kNoSlot;
+    uint64_t pay[kPayMax];
+#pragma unroll
+    for (int k = 0; k < kPayMax; ++k) pay[k] = 0;
+    if (live) {
+      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+      if (load_payload<W>(in, r, status, mk, iv, fv)) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) pay[w] = mk[w];
+#pragma unroll
+        for (int c = 0; c < kMaxCols; ++c)
+          if (c < in.n_icols) pay[W + c] = iv[c];
+      }
+    }
+    tile_place(L, nb, live, live ? sl >> SBC : 0u, sl & lmask, pay, words, tmp_slot, out);
+  }
+}
+
+// Two-pass scatter, pass 2: each work item is a run of one coarse bucket's
+// records; the workgroup counts them per fine partition (2^S2 of them),
+// reserves one range per fine partition, then places them tile by tile.
+template <int W>
+__global__ __launch_bounds__(1024) void part_scatter2(const PartItem *items2, const int64_t *meta2, int S2, int SB,
+                                                      const int64_t *off, uint32_t *cur, int64_t cap, int ni,
+                                                      const uint32_t *tmp_slot, const uint64_t *tmp_mk,
+                                                      const uint64_t *tmp_iv, uint32_t *rec_slot, uint64_t *rec_mk,
+                                                      uint64_t *rec_iv) {
+  extern __shared__ uint8_t tile_raw[];
+  const TileLds L(tile_raw);
+  const int t = threadIdx.x;
+  const int nq = 1 << S2, words = W + ni;
+  const uint32_t lmask = (1u << SB) - 1u;
+  const PayOut out = pay_out<W>(ni, cap, rec_mk, rec_iv);
+  const int64_t n_items = meta2[0];
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const PartItem item = items2[it];
+    const int64_t pbase = item.part << S2;
+    for (int q = t; q < nq; q += blockDim.x) L.base[q] = 0;
+    __syncthreads();
+    for (int64_t r = item.begin + t; r < item.end; r += blockDim.x) atomicAdd(&L.base[tmp_slot[r] >> SB], 1u);
+    __syncthreads();
+    for (int q = t; q < nq; q += blockDim.x)
+      if (L.base[q]) L.base[q] = (uint32_t)(off[pbase + q] + atomicAdd(&cur[pbase + q], L.base[q]));
+    __syncthreads();
+    for (int64_t rt = item.begin; rt < item.end; rt += blockDim.x) {
+      const int64_t r = rt + t;
+      const bool live = r < item.end;
+      const uint32_t sc = live ? tmp_slot[r] : 0u;
+      uint64_t pay[kPayMax];
+#pragma unroll
+      for (int k = 0; k < kPayMax; ++k) pay[k] = 0;
+      if (live) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) pay[w] = tmp_mk[w * cap + r];
+#pragma unroll
+        for (int c = 0; c < kMaxCols; ++c)
+          if (c < ni) pay[W + c] = tmp_iv[c * cap + r];
+      }
+      tile_place(L, nq, live, sc >> SB, sc & lmask, pay, words, rec_slot, out);
+    }
   }
 }
 
@@ -820,23 +1061,61 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
     hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, count, p.n_parts, p.chunk, off, cur, items,
                        meta, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (few) {
+    if (p.S2 > 0) {
+      // two passes: rows -> coarse buckets (the LDS scatter over n_coarse
+      // partitions of SB + S2 bits, into the temporary records), then
+      // buckets -> fine partitions
+      uint32_t *ccount = (uint32_t *)(base + p.off_ccount);
+      int64_t *coff = (int64_t *)(base + p.off_coff);
+      uint32_t *ccur = (uint32_t *)(base + p.off_ccur);
+      PartItem *items2 = (PartItem *)(base + p.off_items2);
+      int64_t *meta2 = (int64_t *)(base + p.off_meta2);
+      uint32_t *tmp_slot = (uint32_t *)(base + p.off_tmp_slot);
+      uint64_t *tmp_mk = (uint64_t *)(base + p.off_tmp_mk);
+      uint64_t *tmp_iv = (uint64_t *)(base + p.off_tmp_iv);
+      hipLaunchKernelGGL(part_coarse_count, dim3((unsigned)((p.n_coarse + 255) / 256)), dim3(256), 0, env.stream,
+                         count, p.n_parts, p.S2, p.n_coarse, ccount);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, ccount, p.n_coarse, p.chunk2, coff, ccur,
+                         items2, meta2, nullptr);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const size_t tlds = tile_lds_bytes(in.W + in.n_icols);  // the two-pass form has no float columns
+      const void *cfn = in.W == 1 ? (const void *)part_scatter_coarse<1> : (const void *)part_scatter_coarse<2>;
+      const void *sfn2 = in.W == 1 ? (const void *)part_scatter2<1> : (const void *)part_scatter2<2>;
+      if ((e = hipFuncSetAttribute(cfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess ||
+          (e = hipFuncSetAttribute(sfn2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess)
+        return e;
+      const dim3 sgrid(env.n_cu * kScatterWgPerCu), sblock(kTileRecs);
+      if (in.W == 1)
+        hipLaunchKernelGGL(part_scatter_coarse<1>, sgrid, sblock, tlds, env.stream, in, env.status, row_slot, coff,
+                           ccur, p.SB + p.S2, (int)p.n_coarse, p.cap, tmp_slot, tmp_mk, tmp_iv);
+      else
+        hipLaunchKernelGGL(part_scatter_coarse<2>, sgrid, sblock, tlds, env.stream, in, env.status, row_slot, coff,
+                           ccur, p.SB + p.S2, (int)p.n_coarse, p.cap, tmp_slot, tmp_mk, tmp_iv);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (in.W == 1)
+        hipLaunchKernelGGL(part_scatter2<1>, sgrid, sblock, tlds, env.stream, items2, meta2, p.S2, p.SB, off, cur,
+                           p.cap, in.n_icols, tmp_slot, tmp_mk, tmp_iv, rec_slot, rec_mk, rec_iv);
+      else
+        hipLaunchKernelGGL(part_scatter2<2>, sgrid, sblock, tlds, env.stream, items2, meta2, p.S2, p.SB, off, cur,
+                           p.cap, in.n_icols, tmp_slot, tmp_mk, tmp_iv, rec_slot, rec_mk, rec_iv);
+    } else if (few) {
       const void *sfn = in.W == 1 ? (const void *)part_scatter_lds<1> : (const void *)part_scatter_lds<2>;
       if ((e = hipFuncSetAttribute(sfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
         return e;
-    }
-    if (few && in.W == 1)
-      hipLaunchKernelGGL(part_scatter_lds<1>, dim3(lgrid), dim3(lblock), lds, env.stream, in, env.status, row_slot,
-                         off, cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
-    else if (few)
-      hipLaunchKernelGGL(part_scatter_lds<2>, dim3(lgrid), dim3(lblock), lds, env.stream, in, env.status, row_slot,
-                         off, cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
-    else if (in.W == 1)
+      if (in.W == 1)
+        hipLaunchKernelGGL(part_scatter_lds<1>, dim3(lgrid), dim3(lblock), lds, env.stream, in, env.status, row_slot,
+                           off, cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+      else
+        hipLaunchKernelGGL(part_scatter_lds<2>, dim3(lgrid), dim3(lblock), lds, env.stream, in, env.status, row_slot,
+                           off, cur, p.SB, p.n_parts, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+    } else if (in.W == 1) {
       hipLaunchKernelGGL(part_scatter<1>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off, cur,
                          p.SB, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
-    else
+    } else {
       hipLaunchKernelGGL(part_scatter<2>, dim3(grid), dim3(256), 0, env.stream, in, env.status, row_slot, off, cur,
                          p.SB, p.cap, rec_slot, rec_mk, rec_iv, rec_fv);
+    }
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const AggFn afn = p.det ? nullptr : (in.W == 1 ? agg_fn<1>(in.n_icols) : agg_fn<2>(in.n_icols));

@@ -566,3 +566,32 @@ def test_finalize_no_cells_returns_prior(ctx, torch_mod, with_prior):
     _, (v, n, f, post) = _release_case(ctx, torch_mod, 64, [], 1.0 / 128, 5, R.FLAG_SCALE2, prior=prior)
     assert v.shape == (0,)
     np.testing.assert_array_equal(post, prior if with_prior else np.full(64, 1.0 / 64))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m", [64, 128])
+@pytest.mark.parametrize("ni", [0, 1, 3, 5])
+def test_two_pass_scatter(ctx, torch_mod, m, ni):
+    """More than 1024 partitions with integer columns: rows go to coarse buckets, then to their partitions.
+    150 001 groups (a ragged last bucket), filter, FK chain, 0-5 int columns; counters equal the oracle's."""
+    import paper_2603_15023_amd as P
+    t = gen.tiny_star(61 + ni, n_pu=3000, n_orders=30_000, n_rows=400_009, gcards=(3,), n_cols=max(ni, 1),
+                      value_range=(-10**12, 10**12), with_sel=True)
+    gsrc = np.random.default_rng(7 + ni).integers(0, 1_000_000, size=t.n_rows, dtype=np.uint32)
+    G, lt, K = 150_001, 3 << 30, 0x2B2B + ni
+    names = [f"v{i}" for i in range(ni)]
+    dev = torch_mod.device("cuda")
+    _say("two-pass scatter", m, ni)
+    spec = P.AggSpec(n_rows=t.n_rows, masks=P.pac_hash_mask(ctx, torch_mod.from_numpy(t.pu_key).to(dev), K, m),
+                     links=[torch_mod.from_numpy(t.f_order).to(dev), torch_mod.from_numpy(t.o_pu).to(dev)],
+                     gcols=[torch_mod.from_numpy(gsrc.view(np.int32)).to(dev)], gcards=[1_000_000], group_mod=G,
+                     n_groups=G, filter_col=torch_mod.from_numpy(t.sel.view(np.int32)).to(dev), filter_lt=lt,
+                     cols=[torch_mod.from_numpy(t.cols[c]).to(dev) for c in names])
+    st = P.new_state(spec, m)
+    P.pac_group_aggregate(ctx, spec, st, m=m, algo="partition")
+    assert ctx.status() == 0
+    want = ON.onepass(t.n_rows, m, masks=R.pac_hash_np(t.pu_key, K, m), links=[t.f_order, t.o_pu], gcols=[gsrc],
+                      gcards=[1_000_000], group_mod=G, n_groups=G, filter_col=t.sel, filter_lt=lt,
+                      int_cols=[t.cols[c] for c in names])
+    for k in ("count", "isum", "nrows"):
+        assert np.array_equal(st[k].cpu().numpy(), want[k]), k
