@@ -45,6 +45,32 @@ static hipError_t launch_fill(const LaunchEnv &env, T *p, int64_t n, T v) {
 }
 
 hipError_t launch_fill_i64(const LaunchEnv &env, int64_t *p, int64_t n, int64_t v) { return launch_fill(env, p, n, v); }
+
+// Occupied slots of a sparse-key table: per-wave ballot counts, summed per
+// workgroup in LDS, one atomic add per workgroup (n_used cleared first).
+__global__ __launch_bounds__(256) void count_used_kernel(const int64_t *slot_keys, int64_t cap, int64_t *n_used) {
+  __shared__ uint32_t part[4];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride)
+    c += slot_keys[i] != PAC_EMPTY_KEY ? 1u : 0u;
+  for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t sum = (uint64_t)part[0] + part[1] + part[2] + part[3];
+    if (sum) atomicAdd((unsigned long long *)n_used, (unsigned long long)sum);
+  }
+}
+
+hipError_t launch_count_used(const LaunchEnv &env, const int64_t *slot_keys, int64_t cap, int64_t *n_used) {
+  hipError_t e = launch_fill(env, n_used, (int64_t)1, (int64_t)0);
+  if (e != hipSuccess || cap <= 0) return e;
+  const int64_t need = (cap + 255) / 256;
+  const int blocks = (int)(need < (int64_t)env.n_cu * 4 ? need : (int64_t)env.n_cu * 4);
+  hipLaunchKernelGGL(count_used_kernel, dim3(blocks), dim3(256), 0, env.stream, slot_keys, cap, n_used);
+  return hipGetLastError();
+}
 hipError_t launch_fill_f64(const LaunchEnv &env, double *p, int64_t n, double v) { return launch_fill(env, p, n, v); }
 
 }  // namespace pac

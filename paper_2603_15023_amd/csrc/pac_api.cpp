@@ -291,6 +291,7 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
     default:
       return fail(PAC_ERR_INVALID, "unknown algorithm %u", algo);
   }
+  if (e == hipSuccess && d.group_keys) e = pac::launch_count_used(env, ds.slot_keys, G, ds.n_used);
   if (e != hipSuccess) return hip_fail(e, "aggregate launch");
   return PAC_OK;
 }

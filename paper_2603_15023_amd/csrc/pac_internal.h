@@ -145,8 +145,10 @@ __device__ __forceinline__ int64_t dense_group(const DevInput &in, int64_t r) {
 
 // Slot of a sparse group key in the open-addressing table (linear probing,
 // capacity a power of two).  Every probe sequence ends: at most `cap` probes.
-__device__ __forceinline__ int64_t table_slot(int64_t key, int64_t *slot_keys, int64_t cap, int64_t *n_used,
-                                              uint32_t *status) {
+// The number of occupied slots is counted after the pass (count_used), not
+// here: one counter incremented by every insert serialises a million inserts
+// on a single address.
+__device__ __forceinline__ int64_t table_slot(int64_t key, int64_t *slot_keys, int64_t cap, uint32_t *status) {
   uint64_t h = mix64((uint64_t)key ^ kSlotSalt) & (uint64_t)(cap - 1);
   for (int64_t probe = 0; probe < cap; ++probe) {
     // A slot's key is written once (EMPTY -> key), so a cached copy that is not
@@ -159,10 +161,7 @@ __device__ __forceinline__ int64_t table_slot(int64_t key, int64_t *slot_keys, i
       unsigned long long expected = (unsigned long long)PAC_EMPTY_KEY;
       const unsigned long long prev =
           atomicCAS((unsigned long long *)&slot_keys[h], expected, (unsigned long long)key);
-      if (prev == expected) {
-        atomicAdd((unsigned long long *)n_used, 1ull);
-        return (int64_t)h;
-      }
+      if (prev == expected) return (int64_t)h;
       if ((int64_t)prev == key) return (int64_t)h;
     }
     h = (h + 1) & (uint64_t)(cap - 1);
@@ -181,7 +180,7 @@ __device__ __forceinline__ int64_t row_group(const DevInput &in, const DevState 
       atomicOr(status, PAC_STATUS_BAD_GROUP);
       return -1;
     }
-    return table_slot(key, st.slot_keys, in.n_groups, st.n_used, status);
+    return table_slot(key, st.slot_keys, in.n_groups, status);
   }
   const int64_t g = dense_group(in, r);
   if (g == -2) {
@@ -250,6 +249,8 @@ hipError_t launch_hash(const LaunchEnv &env, const int64_t *keys, int64_t n, uin
                        uint64_t *out);
 hipError_t launch_fill_i64(const LaunchEnv &env, int64_t *p, int64_t n, int64_t v);
 hipError_t launch_fill_f64(const LaunchEnv &env, double *p, int64_t n, double v);
+// n_used = the number of occupied (non-EMPTY) slots of a sparse-key table.
+hipError_t launch_count_used(const LaunchEnv &env, const int64_t *slot_keys, int64_t cap, int64_t *n_used);
 hipError_t launch_agg_plain(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
                             size_t scratch_bytes);
 size_t plain_scratch_bytes(const LaunchEnv &env, const DevInput &in, bool minmax);
