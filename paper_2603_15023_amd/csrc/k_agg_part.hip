@@ -79,7 +79,11 @@ constexpr int kPartLdsTarget = 80 * 1024;  // two workgroups per CU
 #endif
 // Deterministic form: four workgroups per CU (its per-record loop is latency bound).
 constexpr int kPartLdsTargetDet = PART_DET_LDS_KB * 1024;
-constexpr int kPartWaves = 4;              // waves per workgroup of the aggregation
+constexpr int kPartWaves = 4;              // waves per workgroup of the aggregation (deterministic form)
+#ifndef PART_AGG_WAVES
+#define PART_AGG_WAVES 16
+#endif
+constexpr int kPartWavesNd = PART_AGG_WAVES;  // waves sharing one item's LDS counters (integer form)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -768,7 +772,7 @@ struct RecBatch {
 // NI / NF >= 0: the column counts are compile-time (no per-column branches in
 // the per-record loop); -1: taken from ni_rt / nf_rt.
 template <int W, int NI, int NF>
-__global__ __launch_bounds__(64 * kPartWaves) void part_aggregate(DevState st, int ni_rt, int nf_rt, int64_t n_slots,
+__global__ __launch_bounds__(64 * kPartWavesNd) void part_aggregate(DevState st, int ni_rt, int nf_rt, int64_t n_slots,
                                                       int SB, int64_t slot_words, int64_t cap,
                                                       const uint32_t *rec_slot, const uint64_t *rec_mk,
                                                       const uint64_t *rec_iv, const uint64_t *rec_fv,
@@ -1124,7 +1128,8 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
   const void *fn = p.det ? (const void *)dfn : (const void *)afn;
   if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_bytes)) != hipSuccess) return e;
   int per_cu = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kPartWaves, p.lds_bytes)) != hipSuccess)
+  const int agg_block = 64 * (p.det ? kPartWaves : kPartWavesNd);
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, agg_block, p.lds_bytes)) != hipSuccess)
     return e;
   const int agg_grid = std::max(1, env.n_cu * std::max(1, per_cu));
   if (p.det) {
@@ -1139,7 +1144,7 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
                        (const int64_t *)(base + p.off_pfirst), partial, fresh ? 1 : 0);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(afn, dim3(agg_grid), dim3(64 * kPartWaves), (size_t)p.lds_bytes, env.stream, st, in.n_icols,
+  hipLaunchKernelGGL(afn, dim3(agg_grid), dim3(agg_block), (size_t)p.lds_bytes, env.stream, st, in.n_icols,
                      in.n_fcols, p.n_slots, p.SB, p.slot_words, p.cap, rec_slot, rec_mk, rec_iv, rec_fv, items, meta,
                      fresh ? 1 : 0);
   return hipGetLastError();
