@@ -201,6 +201,25 @@ __global__ __launch_bounds__(256) void part_route(DevInput in, DevState st, uint
   }
 }
 
+// At most 64 partitions: the lanes holding a record of this lane's partition
+// (`same`), and the number of records of partition `lane` in the batch, from
+// six ballots of the partition id's bits instead of a loop over the
+// partitions present.
+__device__ __forceinline__ void part_masks64(bool valid, uint32_t part, int lane, uint64_t *same,
+                                             uint32_t *n_of_lane) {
+  const uint32_t pv = valid ? part : 0u;
+  const uint64_t vm = __ballot(valid);
+  uint64_t sm = vm, mine = vm;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const uint64_t b = __ballot(valid && ((pv >> k) & 1u));
+    sm &= ((pv >> k) & 1u) ? b : ~b;
+    mine &= ((lane >> k) & 1) ? b : ~b;
+  }
+  *same = sm;
+  *n_of_lane = (uint32_t)__popcll(mine);
+}
+
 // 1'. deterministic routing: wave w takes the contiguous chunks [w*cpw, (w+1)*cpw)
 // in order and counts its rows per partition in its own entry mat[part][w].
 __global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, uint32_t *status,
@@ -222,15 +241,19 @@ __global__ __launch_bounds__(256) void part_route_det(DevInput in, DevState st, 
       row_slot[r] = g >= 0 ? (uint32_t)g : kNoSlot;
     }
     const uint32_t part = g >= 0 ? (uint32_t)(g >> SB) : kNoSlot;
+    if (few) {
+      uint64_t same;
+      uint32_t n_lane;
+      part_masks64(g >= 0, part, lane, &same, &n_lane);
+      cnt += n_lane;
+      continue;
+    }
     uint64_t todo = __ballot(g >= 0);
     while (todo) {
       const int leader = __ffsll((unsigned long long)todo) - 1;
       const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
       const uint64_t same = __ballot(part == p0) & todo;
-      if (few)
-        cnt += lane == (int)p0 ? (uint32_t)__popcll(same) : 0u;
-      else if (lane == leader)
-        mat[(int64_t)p0 * n_waves + w] += (uint32_t)__popcll(same);  // only this wave writes it
+      if (lane == leader) mat[(int64_t)p0 * n_waves + w] += (uint32_t)__popcll(same);  // only this wave writes it
       todo &= ~same;
     }
   }
@@ -645,25 +668,32 @@ __global__ __launch_bounds__(256) void part_scatter_det(DevInput in, uint32_t *s
     const uint32_t s = r < in.n_rows ? row_slot[r] : kNoSlot;
     const uint32_t part = s != kNoSlot ? s >> SB : kNoSlot;
     int64_t pos = -1;
-    uint64_t todo = __ballot(s != kNoSlot);
+    if (few) {
+      // this lane's record goes after the earlier lanes of its partition, from
+      // that partition's running position (held by lane `part`)
+      uint64_t same;
+      uint32_t n_lane;
+      const bool valid = s != kNoSlot;
+      part_masks64(valid, part, lane, &same, &n_lane);
+      const int src = valid ? (int)part : 0;
+      const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)next, src), hi = (uint32_t)__shfl((int)(next >> 32), src);
+      const int64_t start = (int64_t)(((uint64_t)hi << 32) | lo);
+      if (valid) pos = start + __popcll(same & lanes_lt(lane));
+      next += (int64_t)n_lane;
+    }
+    uint64_t todo = few ? 0ull : __ballot(s != kNoSlot);
     while (todo) {
       const int leader = __ffsll((unsigned long long)todo) - 1;
       const uint32_t p0 = __builtin_amdgcn_readlane(part, leader);
       const uint64_t same = __ballot(part == p0) & todo;
       const uint32_t n0 = (uint32_t)__popcll(same);
-      int64_t start;
-      if (few) {
-        start = (int64_t)readlane_u64((uint64_t)next, (int)p0);
-        next += lane == (int)p0 ? (int64_t)n0 : 0;
-      } else {
-        uint32_t base = 0;
-        if (lane == leader) {
-          uint32_t *e = &mat[(int64_t)p0 * n_waves + w];
-          base = *e;
-          *e = base + n0;
-        }
-        start = off[p0] + __builtin_amdgcn_readlane(base, leader);
+      uint32_t base = 0;
+      if (lane == leader) {
+        uint32_t *e = &mat[(int64_t)p0 * n_waves + w];
+        base = *e;
+        *e = base + n0;
       }
+      const int64_t start = off[p0] + __builtin_amdgcn_readlane(base, leader);
       if ((same >> lane) & 1ull) pos = start + __popcll(same & lanes_lt(lane));
       todo &= ~same;
     }
