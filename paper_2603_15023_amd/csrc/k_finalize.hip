@@ -197,6 +197,23 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// Orders one wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Two sums over the 64 lanes at once (each in the order of wave_sum).
+__device__ __forceinline__ void wave_sum2(double &a, double &b) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a += dpp_f64(a, k);
+    b += dpp_f64(b, k);
+  }
+  a = (readlane_f64(a, 0) + readlane_f64(a, 16)) + (readlane_f64(a, 32) + readlane_f64(a, 48));
+  b = (readlane_f64(b, 0) + readlane_f64(b, 16)) + (readlane_f64(b, 32) + readlane_f64(b, 48));
+}
+
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_f64(v, 0));
   v = fmax(v, dpp_f64(v, 1));
@@ -205,13 +222,32 @@ __device__ __forceinline__ double wave_max(double v) {
   return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
-constexpr int kAhead = 4;  // cells in flight in the sequential phase
+// The world vectors reach the sequential phase through LDS, kChainChunk cells
+// at a time and double-buffered: the next chunk's vectors are loaded into
+// registers while the current chunk is released, and written to the other
+// buffer after it, so the wave waits for memory once per chunk instead of once
+// per cell.  Each cell's outcome stays in a register of lane (cell % 64) and a
+// batch of 64 outcomes is stored at once.
+constexpr int kChainChunk = 16;
+
+template <int W>
+__device__ __forceinline__ void chain_load(const double *ybuf, int64_t first, int64_t nc, int lane,
+                                           double (&r)[kChainChunk][W]) {
+  constexpr int m = 64 * W;
+#pragma unroll
+  for (int i = 0; i < kChainChunk; ++i) {
+    const int64_t ci = min(first + i, nc - 1);  // clamped: every chunk issues the same loads
+#pragma unroll
+    for (int w = 0; w < W; ++w) r[i][w] = ybuf[ci * m + lane + 64 * w];
+  }
+}
 
 template <int W>
 __global__ __launch_bounds__(64) void release_chain_kernel(FinParams fp, int64_t c0, int64_t nc, const double *ybuf,
                                                            const CellMeta *meta, double *out_val, uint8_t *out_null,
                                                            uint32_t *out_flags, double *post, int first_chunk) {
   constexpr int m = 64 * W;
+  __shared__ double s_y[2][kChainChunk][m];
   const int lane = threadIdx.x;
   double P[W], L[W];
   const bool prior = (fp.flags & PAC_FIN_PRIOR_IN) || !first_chunk;
@@ -227,101 +263,116 @@ __global__ __launch_bounds__(64) void release_chain_kernel(FinParams fp, int64_t
     jstar = (int)(a % (uint64_t)m);
   }
   const int js_w = jstar >> 6, js_l = jstar & 63;
-  // ring of prefetched world vectors: cell ci sits in slot ci % kAhead
-  double yq[kAhead][W];
+  if (nc > 0) {
+    double nxt[kChainChunk][W];
+    chain_load<W>(ybuf, 0, nc, lane, nxt);
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k)
+    for (int i = 0; i < kChainChunk; ++i)
 #pragma unroll
-    for (int w = 0; w < W; ++w) yq[k][w] = k < nc ? ybuf[(int64_t)k * m + lane + 64 * w] : 0.0;
-  // lane l holds z and the phase-1 flags of cell b + l of the current batch of 64
-  double zc = 0.0;
-  uint32_t fc = 0;
-  if (lane < nc) {
-    zc = meta[lane].z;
-    fc = meta[lane].flags;
-  }
-  for (int64_t b = 0; b < nc; b += 64) {
-    double zn = 0.0;
-    uint32_t fn = 0;
-    if (b + 64 + lane < nc) {  // next batch, in flight while this one is released
-      zn = meta[b + 64 + lane].z;
-      fn = meta[b + 64 + lane].flags;
-    }
-    const int nb = nc - b < 64 ? (int)(nc - b) : 64;
-    for (int k = 0; k < nb; k += kAhead) {
+      for (int w = 0; w < W; ++w) s_y[0][i][lane + 64 * w] = nxt[i][w];
+    wave_lds_sync();
+    // After a posterior update, the next cell's weighted mean sum_j P_j y_j
+    // is reduced together with the normaliser (as sum_j e_j y_j / sum_j e_j),
+    // which takes one of the four dependent wave reductions off that cell.
+    double mu_next = 0.0;
+    bool have_mu = false;
+    // lane l holds z and the phase-1 flags of cell b + l of the current batch of 64
+    double zc = meta[min((int64_t)lane, nc - 1)].z;
+    uint32_t fc = meta[min((int64_t)lane, nc - 1)].flags;
+    for (int64_t b = 0; b < nc; b += 64) {
+      // next batch's draws and flags (clamped: the same loads every batch), in flight
+      const int64_t mi = min(b + 64 + lane, nc - 1);
+      const double zn = meta[mi].z;
+      const uint32_t fn = meta[mi].flags;
+      const int nbc = nc - b < 64 ? (int)(nc - b) : 64;
+      double v_keep = 0.0;
+      uint32_t f_keep = 0, n_keep = 0;
+      for (int64_t cs = b; cs < b + nbc; cs += kChainChunk) {
+        const int buf = (int)((cs / kChainChunk) & 1);
+        chain_load<W>(ybuf, cs + kChainChunk, nc, lane, nxt);  // next chunk, in flight while this one runs
+        const int nk = nc - cs < kChainChunk ? (int)(nc - cs) : kChainChunk;
+        for (int i = 0; i < nk; ++i) {
+          const int64_t ci = cs + i;
+          const int kk = (int)(ci - b);
+          double y[W];
 #pragma unroll
-      for (int u = 0; u < kAhead; ++u) {
-        const int kk = k + u;
-        if (kk >= nb) break;
-        const int64_t ci = b + kk;
-        double y[W];
+          for (int w = 0; w < W; ++w) y[w] = s_y[buf][i][lane + 64 * w];
+          uint32_t cflags = (uint32_t)__builtin_amdgcn_readlane((int)fc, kk);
+          double val = 0.0;
+          uint32_t is_null = 0;
+          if (cflags & PAC_CELL_NULL) {
+            is_null = 1;
+            have_mu = false;
+          } else {
+            double mu = mu_next;
+            if (!have_mu) {
+              double pm = 0.0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) y[w] = yq[u][w];
-        const int64_t nx = ci + kAhead;
+              for (int w = 0; w < W; ++w) pm += P[w] * y[w];
+              mu = wave_sum(pm);
+            }
+            have_mu = false;
+            double part = 0.0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) yq[u][w] = nx < nc ? ybuf[nx * m + lane + 64 * w] : 0.0;
-        const uint32_t cflags = (uint32_t)__builtin_amdgcn_readlane((int)fc, kk);
-        const int64_t c = c0 + ci;
-        if (cflags & PAC_CELL_NULL) {
-          if (lane == 0) {
-            out_val[c] = 0.0;
-            out_null[c] = 1;
-            out_flags[c] = cflags;
+            for (int w = 0; w < W; ++w) part += P[w] * ((y[w] - mu) * (y[w] - mu));
+            const double s2 = wave_sum(part);
+            const double delta = s2 / (2.0 * fp.budget);
+            const double ys = readlane_f64(y[js_w], js_l);
+            if (!(delta > 0.0)) {
+              val = ys;
+              cflags |= PAC_CELL_ZERO_VARIANCE;
+            } else {
+              const double yrel = ys + sqrt(delta) * readlane_f64(zc, kk);
+              val = yrel;
+              if (!(fp.flags & PAC_FIN_FIXED_PRIOR)) {
+                const bool fuse = i + 1 < nk;  // the next cell's vector is in this chunk's buffer
+                double l[W];
+                double mx = -INFINITY;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                  const double d = yrel - y[w];
+                  l[w] = L[w] - (d * d) / (2.0 * delta);
+                  mx = fmax(mx, l[w]);
+                }
+                mx = wave_max(mx);
+                double e[W], se = 0.0, ey = 0.0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                  e[w] = exp(l[w] - mx);
+                  se += e[w];
+                  ey += fuse ? e[w] * s_y[buf][i + 1][lane + 64 * w] : 0.0;
+                }
+                wave_sum2(se, ey);
+                const double lse = mx + log(se);
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                  P[w] = e[w] / se;
+                  L[w] = P[w] > 0.0 ? l[w] - lse : -INFINITY;  // an underflowed world stays at zero
+                }
+                mu_next = ey / se;
+                have_mu = fuse;
+              }
+            }
           }
-          continue;
+          v_keep = lane == kk ? val : v_keep;
+          f_keep = lane == kk ? cflags : f_keep;
+          n_keep = lane == kk ? is_null : n_keep;
         }
-        double part = 0.0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) part += P[w] * y[w];
-        const double mu = wave_sum(part);
-        part = 0.0;
+        for (int i = 0; i < kChainChunk; ++i)
 #pragma unroll
-        for (int w = 0; w < W; ++w) part += P[w] * ((y[w] - mu) * (y[w] - mu));
-        const double s2 = wave_sum(part);
-        const double delta = s2 / (2.0 * fp.budget);
-        const double ys = readlane_f64(y[js_w], js_l);
-        if (!(delta > 0.0)) {
-          if (lane == 0) {
-            out_val[c] = ys;
-            out_null[c] = 0;
-            out_flags[c] = cflags | PAC_CELL_ZERO_VARIANCE;
-          }
-          continue;
-        }
-        const double yrel = ys + sqrt(delta) * readlane_f64(zc, kk);
-        if (lane == 0) {
-          out_val[c] = yrel;
-          out_null[c] = 0;
-          out_flags[c] = cflags;
-        }
-        if (!(fp.flags & PAC_FIN_FIXED_PRIOR)) {
-          double l[W];
-          double mx = -INFINITY;
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            const double d = yrel - y[w];
-            l[w] = L[w] - (d * d) / (2.0 * delta);
-            mx = fmax(mx, l[w]);
-          }
-          mx = wave_max(mx);
-          double e[W], se = 0.0;
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            e[w] = exp(l[w] - mx);
-            se += e[w];
-          }
-          se = wave_sum(se);
-          const double lse = mx + log(se);
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            P[w] = e[w] / se;
-            L[w] = P[w] > 0.0 ? l[w] - lse : -INFINITY;  // an underflowed world stays at zero
-          }
-        }
+          for (int w = 0; w < W; ++w) s_y[buf ^ 1][i][lane + 64 * w] = nxt[i][w];
+        wave_lds_sync();
       }
+      if (lane < nbc) {  // the batch's outcomes
+        const int64_t c = c0 + b + lane;
+        out_val[c] = v_keep;
+        out_null[c] = (uint8_t)n_keep;
+        out_flags[c] = f_keep;
+      }
+      zc = zn;
+      fc = fn;
     }
-    zc = zn;
-    fc = fn;
   }
 #pragma unroll
   for (int w = 0; w < W; ++w) post[lane + 64 * w] = P[w];
