@@ -143,10 +143,13 @@ class QueryResult:
 class _Slot:
     """One query in flight: its own context (scratch, status word), stream, PU words and pinned result area."""
 
-    def __init__(self, device_index: int, n_pu: int, m: int, max_cells: int):
+    def __init__(self, device_index: int, n_pu: int, m: int, max_cells: int, n_rows: int):
         dev = torch.device("cuda", device_index)
         self.ctx = Context(device_index)
-        self.ctx.reserve(256 << 20)  # no scratch growth (a device-wide synchronisation) while serving
+        # no scratch growth (a device-wide synchronisation) while serving: the partitioned form over the whole
+        # table needs up to about 80 bytes per row for the served column mixes (slots, records and the two-pass
+        # scatter's temporary records)
+        self.ctx.reserve(max(256 << 20, 80 * n_rows))
         self.stream = torch.cuda.Stream(device=dev)  # default priority
         self.masks = torch.empty((n_pu, m // 64), dtype=torch.int64, device=dev)
         self.max_cells = max_cells
@@ -180,7 +183,7 @@ class Server:
     def __init__(self, table: ResidentStar, n_slots: int = 4, pool_bytes: int = 8 << 30, m: int = 64,
                  mi_budget: float = 1.0 / 128, device_index: int = 0, max_cells: int = 300_000):
         self.table, self.m, self.budget = table, m, mi_budget
-        self.slots = [_Slot(device_index, table.pu_key.shape[0], m, max_cells) for _ in range(n_slots)]
+        self.slots = [_Slot(device_index, table.pu_key.shape[0], m, max_cells, table.n_rows) for _ in range(n_slots)]
         self.n_slots, self.pool_bytes = n_slots, pool_bytes
 
     def _launch(self, slot: _Slot, q):
