@@ -119,7 +119,8 @@ def main():
                         stats=stats)
     spec_kv.pu_keys = torch.from_numpy(t.pu_key[t.o_pu]).to(dev)
     state = P.new_state(spec, 64)
-    state2 = P.new_state(spec, 64)  # the second counter set of the pipelined steps
+    state2 = P.new_state(spec, 64)  # the second and third counter sets of the pipelined steps
+    state3 = P.new_state(spec, 64)
     cells = []
     for g in range(6):
         cells.append((g, P._abi.PAC_CELL_COUNT, 0))
@@ -148,21 +149,24 @@ def main():
     # Pipelined steps (a stream of queries over the resident tables): step i's
     # hash and counter clearing run on a preparation stream while step i - 1
     # aggregates, and its release (a7, one wave) on a release stream while step
-    # i + 1 aggregates.  Masks and counters are double-buffered; a buffer is
-    # reused only after the step that last read it has released.
+    # i + 1 aggregates.  Masks and counters are triple-buffered; a buffer is
+    # reused only after the step that last read it (three steps earlier) has
+    # released, so the preparation never waits for the release of the step just
+    # before, which only gets a CU when an aggregation leaves room.
+    n_buf = 3
     ctx_prep, ctx_rel = P.Context(0), P.Context(0)
     s_prep, s_rel = torch.cuda.Stream(), torch.cuda.Stream()
-    sets = [state, state2]
-    mask_sets = [masks, torch.empty_like(masks)]
-    specs = [spec, dataclasses.replace(spec, masks=mask_sets[1])]
-    ev_prep = [torch.cuda.Event(), torch.cuda.Event()]
-    ev_agg = [torch.cuda.Event(), torch.cuda.Event()]
-    ev_rel = [torch.cuda.Event(), torch.cuda.Event()]
+    sets = [state, state2, state3]
+    mask_sets = [masks] + [torch.empty_like(masks) for _ in range(n_buf - 1)]
+    specs = [spec] + [dataclasses.replace(spec, masks=mk) for mk in mask_sets[1:]]
+    ev_prep = [torch.cuda.Event() for _ in range(n_buf)]
+    ev_agg = [torch.cuda.Event() for _ in range(n_buf)]
+    ev_rel = [torch.cuda.Event() for _ in range(n_buf)]
     for e in ev_rel:
         e.record(stream)
 
     def step_pipelined(i, ev=None):
-        b = i % 2
+        b = i % n_buf
         st = sets[b]
         s_prep.wait_event(ev_rel[b])
         with torch.cuda.stream(s_prep):
