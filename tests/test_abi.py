@@ -62,7 +62,7 @@ def test_struct_sizes_match_header():
 def test_ctypes_layout_matches_c_header(tmp_path):
     """Compile a probe against include/pac.h with gcc and compare every field offset."""
     structs = {"pac_agg_input": A.AggInput, "pac_agg_state": A.AggState, "pac_cell": A.Cell,
-               "pac_finalize_params": A.FinalizeParams}
+               "pac_finalize_params": A.FinalizeParams, "pac_lift_op": A.LiftOp}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pac.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
