@@ -371,26 +371,39 @@ __global__ __launch_bounds__(256) void part_coarse_count(const uint32_t *count, 
 // staged tile: slot, bucket and payload words (PU words, int and float
 // values) of every record in bucket order.
 constexpr int kTileBuckets = 256;
-constexpr int kTileRecs = 1024;
+constexpr int kTileThreads = 1024;
+constexpr int kPayMax = 2 + kMaxCols;
+
+// Records per thread of a tile, and the payload words a record may carry at
+// that size: narrow records (C3's PU word and value) take 4 per thread, so a
+// bucket's run in a tile is 4 times longer.
+__host__ __device__ constexpr int tile_rpt(int words) { return words <= 2 ? 4 : words <= 5 ? 2 : 1; }
+template <int RPT>
+struct TilePw {
+  static constexpr int value = RPT == 4 ? 2 : RPT == 2 ? 5 : kPayMax;
+};
 
 __host__ __device__ constexpr size_t tile_lds_bytes(int words) {
-  return (size_t)(3 * kTileBuckets + 2 * kTileRecs) * 4 + (size_t)words * kTileRecs * 8;
+  return (size_t)(3 * kTileBuckets + 2) * 4 + (size_t)tile_rpt(words) * kTileThreads * (8 + 8 * (size_t)words);
 }
 
 struct TileLds {
-  uint32_t *base, *tcount, *toff, *s_slot, *s_q;
+  uint32_t *base, *tcount, *toff, *total, *s_slot, *s_q;
   uint64_t *s_pay;
-  __device__ explicit TileLds(uint8_t *raw) {
+  int T;  // records per tile
+  __device__ TileLds(uint8_t *raw, int recs) : T(recs) {
     base = (uint32_t *)raw;
     tcount = base + kTileBuckets;
     toff = tcount + kTileBuckets;
-    s_slot = toff + kTileBuckets;
-    s_q = s_slot + kTileRecs;
-    s_pay = (uint64_t *)(s_q + kTileRecs);
+    total = toff + kTileBuckets;  // 2 words: keeps the payload 8-byte aligned
+    s_slot = total + 2;
+    s_q = s_slot + T;
+    s_pay = (uint64_t *)(s_q + T);
   }
 };
 
-// Exclusive scan of tcount[0..nb) into toff (wave 0; nb <= 4 * 64).
+// Exclusive scan of tcount[0..nb) into toff, and the tile's record count
+// (wave 0; nb <= 4 * 64).
 __device__ __forceinline__ void tile_scan(const TileLds &L, int nb) {
   const int t = threadIdx.x;
   if (t < 64) {
@@ -411,51 +424,15 @@ __device__ __forceinline__ void tile_scan(const TileLds &L, int nb) {
       if (4 * t + k < nb) L.toff[4 * t + k] = ex;
       ex += a[k];
     }
+    if (t == 63) *L.total = incl;
   }
 }
 
 // Output pointers of the payload words: PU words, then int columns
 // (structure of arrays, `cap` records each).
-constexpr int kPayMax = 2 + kMaxCols;
 struct PayOut {
   uint64_t *p[kPayMax];
 };
-
-// One tile: each live thread holds a record (bucket q, output slot, payload
-// of `words` words); records are ranked in their bucket, staged in bucket
-// order, then written from the staged order to base[q] + rank.  Every thread
-// of the workgroup calls it (barriers inside).
-__device__ __forceinline__ void tile_place(const TileLds &L, int nb, bool live, uint32_t q, uint32_t slot_out,
-                                           const uint64_t (&pay)[kPayMax], int words, uint32_t *out_slot,
-                                           const PayOut &out) {
-  const int t = threadIdx.x;
-  for (int b = t; b < nb; b += blockDim.x) L.tcount[b] = 0;
-  __syncthreads();
-  const uint32_t lr = live ? atomicAdd(&L.tcount[q], 1u) : 0u;
-  __syncthreads();
-  tile_scan(L, nb);
-  __syncthreads();
-  if (live) {
-    const uint32_t si = L.toff[q] + lr;
-    L.s_slot[si] = slot_out;
-    L.s_q[si] = q;
-#pragma unroll
-    for (int k = 0; k < kPayMax; ++k)
-      if (k < words) L.s_pay[k * kTileRecs + si] = pay[k];
-  }
-  const uint32_t n_live = (uint32_t)__syncthreads_count(live);
-  if ((uint32_t)t < n_live) {
-    const uint32_t qq = L.s_q[t];
-    const int64_t pos = (int64_t)L.base[qq] + (t - (int64_t)L.toff[qq]);
-    out_slot[pos] = L.s_slot[t];
-#pragma unroll
-    for (int k = 0; k < kPayMax; ++k)
-      if (k < words) out.p[k][pos] = L.s_pay[k * kTileRecs + t];
-  }
-  __syncthreads();
-  for (int b = t; b < nb; b += blockDim.x) L.base[b] += L.tcount[b];
-  __syncthreads();
-}
 
 template <int W>
 __device__ __forceinline__ PayOut pay_out(int ni, int64_t cap, uint64_t *mk, uint64_t *iv) {
@@ -467,65 +444,129 @@ __device__ __forceinline__ PayOut pay_out(int ni, int64_t cap, uint64_t *mk, uin
   return o;
 }
 
+// One tile: each thread holds RPT records (bucket q, output slot, payload of
+// `words` words); records are ranked in their bucket, staged in bucket order,
+// then written from the staged order to base[q] + rank, consecutive threads
+// writing consecutive records.  Every thread of the workgroup calls it
+// (barriers inside).
+template <int RPT, int PW>
+__device__ __forceinline__ void tile_place(const TileLds &L, int nb, const bool (&live)[RPT],
+                                           const uint32_t (&q)[RPT], const uint32_t (&slot_out)[RPT],
+                                           const uint64_t (&pay)[RPT][PW], int words, uint32_t *out_slot,
+                                           const PayOut &out) {
+  const int t = threadIdx.x;
+  for (int b = t; b < nb; b += blockDim.x) L.tcount[b] = 0;
+  __syncthreads();
+  uint32_t lr[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) lr[i] = live[i] ? atomicAdd(&L.tcount[q[i]], 1u) : 0u;
+  __syncthreads();
+  tile_scan(L, nb);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    if (!live[i]) continue;
+    const uint32_t si = L.toff[q[i]] + lr[i];
+    L.s_slot[si] = slot_out[i];
+    L.s_q[si] = q[i];
+#pragma unroll
+    for (int k = 0; k < PW; ++k)
+      if (k < words) L.s_pay[k * L.T + si] = pay[i][k];
+  }
+  __syncthreads();
+  const uint32_t n_live = *L.total;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const uint32_t ts = (uint32_t)(i * kTileThreads + t);
+    if (ts < n_live) {
+      const uint32_t qq = L.s_q[ts];
+      const int64_t pos = (int64_t)L.base[qq] + ((int64_t)ts - (int64_t)L.toff[qq]);
+      out_slot[pos] = L.s_slot[ts];
+#pragma unroll
+      for (int k = 0; k < PW; ++k)
+        if (k < words) out.p[k][pos] = L.s_pay[k * L.T + ts];
+    }
+  }
+  __syncthreads();
+  for (int b = t; b < nb; b += blockDim.x) L.base[b] += L.tcount[b];
+  __syncthreads();
+}
+
 // Two-pass scatter (integer columns only), pass 1: rows -> coarse buckets
 // (nb <= kTileBuckets buckets of 2^SBC slots).  The workgroup counts its rows
 // per bucket, reserves one range per bucket, then places its rows tile by
-// tile.  Each record keeps its slot within the bucket.  A row the route gave
-// a slot has a valid FK chain, so every counted row is placed.
-template <int W>
+// tile (RPT rows per thread).  Each record keeps its slot within the bucket.
+// A row the route gave a slot has a valid FK chain, so every counted row is
+// placed.
+template <int W, int RPT>
 __global__ __launch_bounds__(1024) void part_scatter_coarse(DevInput in, uint32_t *status, const uint32_t *row_slot,
                                                             const int64_t *coff, uint32_t *ccur, int SBC, int nb,
                                                             int64_t cap, uint32_t *tmp_slot, uint64_t *tmp_mk,
                                                             uint64_t *tmp_iv) {
+  constexpr int PW = TilePw<RPT>::value;
+  constexpr int T = RPT * kTileThreads;
   extern __shared__ uint8_t tile_raw[];
-  const TileLds L(tile_raw);
+  const TileLds L(tile_raw, T);
   const int t = threadIdx.x;
   const int words = W + in.n_icols;
   const PayOut out = pay_out<W>(in.n_icols, cap, tmp_mk, tmp_iv);
   for (int b = t; b < nb; b += blockDim.x) L.base[b] = 0;
   __syncthreads();
-  const int64_t n = in.n_rows, stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + t; r < n; r += stride) {
-    const uint32_t sl = row_slot[r];
-    if (sl != kNoSlot) atomicAdd(&L.base[sl >> SBC], 1u);
+  const int64_t n = in.n_rows, stride = (int64_t)gridDim.x * T;
+  for (int64_t rt = (int64_t)blockIdx.x * T; rt < n; rt += stride) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int64_t r = rt + i * kTileThreads + t;
+      const uint32_t sl = r < n ? row_slot[r] : kNoSlot;
+      if (sl != kNoSlot) atomicAdd(&L.base[sl >> SBC], 1u);
+    }
   }
   __syncthreads();
   for (int b = t; b < nb; b += blockDim.x)
     if (L.base[b]) L.base[b] = (uint32_t)(coff[b] + atomicAdd(&ccur[b], L.base[b]));
   __syncthreads();
   const uint32_t lmask = (1u << SBC) - 1u;
-  for (int64_t rt = (int64_t)blockIdx.x * blockDim.x; rt < n; rt += stride) {
-    const int64_t r = rt + t;
-    const uint32_t sl = r < n ? row_slot[r] : kNoSlot;
-    const bool live = sl != kNoSlot;
-    uint64_t pay[kPayMax];
+  for (int64_t rt = (int64_t)blockIdx.x * T; rt < n; rt += stride) {
+    bool live[RPT];
+    uint32_t q[RPT], so[RPT];
+    uint64_t pay[RPT][PW];
 #pragma unroll
-    for (int k = 0; k < kPayMax; ++k) pay[k] = 0;
-    if (live) {
-      uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
-      if (load_payload<W>(in, r, status, mk, iv, fv)) {
+    for (int i = 0; i < RPT; ++i) {
+      const int64_t r = rt + i * kTileThreads + t;
+      const uint32_t sl = r < n ? row_slot[r] : kNoSlot;
+      live[i] = sl != kNoSlot;
+      q[i] = live[i] ? sl >> SBC : 0u;
+      so[i] = sl & lmask;
 #pragma unroll
-        for (int w = 0; w < W; ++w) pay[w] = mk[w];
+      for (int k = 0; k < PW; ++k) pay[i][k] = 0;
+      if (live[i]) {
+        uint64_t mk[W], iv[kMaxCols], fv[kMaxCols];
+        if (load_payload<W>(in, r, status, mk, iv, fv)) {
 #pragma unroll
-        for (int c = 0; c < kMaxCols; ++c)
-          if (c < in.n_icols) pay[W + c] = iv[c];
+          for (int w = 0; w < W; ++w) pay[i][w] = mk[w];
+#pragma unroll
+          for (int c = 0; c < kMaxCols; ++c)
+            if (W + c < PW && c < in.n_icols) pay[i][(W + c) < PW ? (W + c) : 0] = iv[c];
+        }
       }
     }
-    tile_place(L, nb, live, live ? sl >> SBC : 0u, sl & lmask, pay, words, tmp_slot, out);
+    tile_place<RPT, PW>(L, nb, live, q, so, pay, words, tmp_slot, out);
   }
 }
 
 // Two-pass scatter, pass 2: each work item is a run of one coarse bucket's
 // records; the workgroup counts them per fine partition (2^S2 of them),
 // reserves one range per fine partition, then places them tile by tile.
-template <int W>
+template <int W, int RPT>
 __global__ __launch_bounds__(1024) void part_scatter2(const PartItem *items2, const int64_t *meta2, int S2, int SB,
                                                       const int64_t *off, uint32_t *cur, int64_t cap, int ni,
                                                       const uint32_t *tmp_slot, const uint64_t *tmp_mk,
                                                       const uint64_t *tmp_iv, uint32_t *rec_slot, uint64_t *rec_mk,
                                                       uint64_t *rec_iv) {
+  constexpr int PW = TilePw<RPT>::value;
+  constexpr int T = RPT * kTileThreads;
   extern __shared__ uint8_t tile_raw[];
-  const TileLds L(tile_raw);
+  const TileLds L(tile_raw, T);
   const int t = threadIdx.x;
   const int nq = 1 << S2, words = W + ni;
   const uint32_t lmask = (1u << SB) - 1u;
@@ -534,28 +575,35 @@ __global__ __launch_bounds__(1024) void part_scatter2(const PartItem *items2, co
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const PartItem item = items2[it];
     const int64_t pbase = item.part << S2;
-    for (int q = t; q < nq; q += blockDim.x) L.base[q] = 0;
+    for (int qq = t; qq < nq; qq += blockDim.x) L.base[qq] = 0;
     __syncthreads();
     for (int64_t r = item.begin + t; r < item.end; r += blockDim.x) atomicAdd(&L.base[tmp_slot[r] >> SB], 1u);
     __syncthreads();
-    for (int q = t; q < nq; q += blockDim.x)
-      if (L.base[q]) L.base[q] = (uint32_t)(off[pbase + q] + atomicAdd(&cur[pbase + q], L.base[q]));
+    for (int qq = t; qq < nq; qq += blockDim.x)
+      if (L.base[qq]) L.base[qq] = (uint32_t)(off[pbase + qq] + atomicAdd(&cur[pbase + qq], L.base[qq]));
     __syncthreads();
-    for (int64_t rt = item.begin; rt < item.end; rt += blockDim.x) {
-      const int64_t r = rt + t;
-      const bool live = r < item.end;
-      const uint32_t sc = live ? tmp_slot[r] : 0u;
-      uint64_t pay[kPayMax];
+    for (int64_t rt = item.begin; rt < item.end; rt += T) {
+      bool live[RPT];
+      uint32_t q[RPT], so[RPT];
+      uint64_t pay[RPT][PW];
 #pragma unroll
-      for (int k = 0; k < kPayMax; ++k) pay[k] = 0;
-      if (live) {
+      for (int i = 0; i < RPT; ++i) {
+        const int64_t r = rt + i * kTileThreads + t;
+        live[i] = r < item.end;
+        const uint32_t sc = live[i] ? tmp_slot[r] : 0u;
+        q[i] = sc >> SB;
+        so[i] = sc & lmask;
 #pragma unroll
-        for (int w = 0; w < W; ++w) pay[w] = tmp_mk[w * cap + r];
+        for (int k = 0; k < PW; ++k) pay[i][k] = 0;
+        if (live[i]) {
 #pragma unroll
-        for (int c = 0; c < kMaxCols; ++c)
-          if (c < ni) pay[W + c] = tmp_iv[c * cap + r];
+          for (int w = 0; w < W; ++w) pay[i][w] = tmp_mk[w * cap + r];
+#pragma unroll
+          for (int c = 0; c < kMaxCols; ++c)
+            if (W + c < PW && c < ni) pay[i][(W + c) < PW ? (W + c) : 0] = tmp_iv[c * cap + r];
+        }
       }
-      tile_place(L, nq, live, sc >> SB, sc & lmask, pay, words, rec_slot, out);
+      tile_place<RPT, PW>(L, nq, live, q, so, pay, words, rec_slot, out);
     }
   }
 }
@@ -1113,26 +1161,33 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
       hipLaunchKernelGGL(part_scan, dim3(1), dim3(1024), 0, env.stream, ccount, p.n_coarse, p.chunk2, coff, ccur,
                          items2, meta2, nullptr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      const size_t tlds = tile_lds_bytes(in.W + in.n_icols);  // the two-pass form has no float columns
-      const void *cfn = in.W == 1 ? (const void *)part_scatter_coarse<1> : (const void *)part_scatter_coarse<2>;
-      const void *sfn2 = in.W == 1 ? (const void *)part_scatter2<1> : (const void *)part_scatter2<2>;
-      if ((e = hipFuncSetAttribute(cfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess ||
-          (e = hipFuncSetAttribute(sfn2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess)
-        return e;
-      const dim3 sgrid(env.n_cu * kScatterWgPerCu), sblock(kTileRecs);
+      const int words = in.W + in.n_icols;  // the two-pass form has no float columns
+      const size_t tlds = tile_lds_bytes(words);
+      const int rpt = tile_rpt(words);
+      const dim3 sgrid(env.n_cu * kScatterWgPerCu), sblock(kTileThreads);
+      auto two_pass = [&](auto cfn, auto sfn2) -> hipError_t {
+        hipError_t err;
+        if ((err = hipFuncSetAttribute((const void *)cfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) !=
+                hipSuccess ||
+            (err = hipFuncSetAttribute((const void *)sfn2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) !=
+                hipSuccess)
+          return err;
+        hipLaunchKernelGGL(cfn, sgrid, sblock, tlds, env.stream, in, env.status, row_slot, coff, ccur, p.SB + p.S2,
+                           (int)p.n_coarse, p.cap, tmp_slot, tmp_mk, tmp_iv);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        hipLaunchKernelGGL(sfn2, sgrid, sblock, tlds, env.stream, items2, meta2, p.S2, p.SB, off, cur, p.cap,
+                           in.n_icols, tmp_slot, tmp_mk, tmp_iv, rec_slot, rec_mk, rec_iv);
+        return hipGetLastError();
+      };
       if (in.W == 1)
-        hipLaunchKernelGGL(part_scatter_coarse<1>, sgrid, sblock, tlds, env.stream, in, env.status, row_slot, coff,
-                           ccur, p.SB + p.S2, (int)p.n_coarse, p.cap, tmp_slot, tmp_mk, tmp_iv);
+        e = rpt == 4 ? two_pass(part_scatter_coarse<1, 4>, part_scatter2<1, 4>)
+            : rpt == 2 ? two_pass(part_scatter_coarse<1, 2>, part_scatter2<1, 2>)
+                       : two_pass(part_scatter_coarse<1, 1>, part_scatter2<1, 1>);
       else
-        hipLaunchKernelGGL(part_scatter_coarse<2>, sgrid, sblock, tlds, env.stream, in, env.status, row_slot, coff,
-                           ccur, p.SB + p.S2, (int)p.n_coarse, p.cap, tmp_slot, tmp_mk, tmp_iv);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      if (in.W == 1)
-        hipLaunchKernelGGL(part_scatter2<1>, sgrid, sblock, tlds, env.stream, items2, meta2, p.S2, p.SB, off, cur,
-                           p.cap, in.n_icols, tmp_slot, tmp_mk, tmp_iv, rec_slot, rec_mk, rec_iv);
-      else
-        hipLaunchKernelGGL(part_scatter2<2>, sgrid, sblock, tlds, env.stream, items2, meta2, p.S2, p.SB, off, cur,
-                           p.cap, in.n_icols, tmp_slot, tmp_mk, tmp_iv, rec_slot, rec_mk, rec_iv);
+        e = rpt == 4 ? two_pass(part_scatter_coarse<2, 4>, part_scatter2<2, 4>)
+            : rpt == 2 ? two_pass(part_scatter_coarse<2, 2>, part_scatter2<2, 2>)
+                       : two_pass(part_scatter_coarse<2, 1>, part_scatter2<2, 1>);
+      if (e != hipSuccess) return e;
     } else if (few) {
       const void *sfn = in.W == 1 ? (const void *)part_scatter_lds<1> : (const void *)part_scatter_lds<2>;
       if ((e = hipFuncSetAttribute(sfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
