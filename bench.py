@@ -11,8 +11,8 @@ FK-chain gather + world-bit expansion + int8 matrix-core contraction + group
 counters (a2-a6), release of the 42 result cells with noise and posterior
 (a7).  Inputs are resident in HBM before timing starts.
 
-Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: this build runs
-on one GPU.
+Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: the benchmark
+runs on one GPU (how the path would shard is described with the design).
 """
 from __future__ import annotations
 
@@ -87,7 +87,7 @@ def measured_traffic():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
