@@ -262,7 +262,7 @@ int pac_world_values(pac_ctx *ctx, void *stream, const pac_agg_state *state, int
  * pac_group_aggregate over the same rows takes masks = out_masks,
  * n_masks = n_rows and no links.
  * When cols[0] is an int column with statistics (has_stats) spanning at most
- * 4096 values, and n_groups x values <= 32 n_rows, the comparison words of
+ * 4096 values within +-2^52, and n_groups x values <= 32 n_rows, the comparison words of
  * every (group, value) are first written to the context's scratch
  * (n_groups x values x m/8 bytes, at most 1 GiB) and each row reads its word
  * there; the result is the same, and rows whose value lies outside the stated

@@ -88,8 +88,9 @@ __global__ __launch_bounds__(256) void sel_table_kernel(const double *wv, int64_
 #pragma unroll
     for (int w = 0; w < W; ++w) mine[w] = 0;
     const int nb = R - v0 < 64 ? R - v0 : 64;
+    const double vb = (double)(lo + v0);  // exact: the host keeps the range within +-2^52
     for (int k = 0; k < nb; ++k) {
-      const double v = (double)(lo + v0 + k);
+      const double v = vb + (double)k;  // the same double as (double)(lo + v0 + k)
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const uint64_t bits = __ballot(sel_cmp(v, op, t[w]));

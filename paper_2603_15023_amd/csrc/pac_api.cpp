@@ -462,7 +462,8 @@ int pac_select_cmp(pac_ctx *ctx, void *stream, const pac_agg_input *rows, int m,
   int64_t lo = 0;
   int32_t R = 0;
   uint64_t *table = nullptr;
-  if (rows->has_stats && is_int(rows->col_type[0])) {
+  const int64_t kExactLim = (int64_t)1 << 52;  // integers the table kernel forms exactly as doubles
+  if (rows->has_stats && is_int(rows->col_type[0]) && rows->col_min[0] > -kExactLim && rows->col_max[0] < kExactLim) {
     const __int128 range = (__int128)rows->col_max[0] - (__int128)rows->col_min[0] + 1;
     const __int128 entries = range * (__int128)d.n_groups;
     if (range >= 1 && range <= kSelTableMaxRange && entries <= (__int128)d.n_rows * 32 &&
