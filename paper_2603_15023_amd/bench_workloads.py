@@ -3,7 +3,7 @@
     python -m paper_2603_15023_amd.bench_workloads zipf   [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads float  [--reps 3] [--algo auto]
     python -m paper_2603_15023_amd.bench_workloads serve  [--queries 64] [--slots 4] [--load 0.7]
-    python -m paper_2603_15023_amd.bench_workloads minmax [--reps 3] [--oracle-rows 20000000]
+    python -m paper_2603_15023_amd.bench_workloads minmax [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads nested [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads join   [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads ratio  [--reps 3] [--seeds 200]
@@ -31,7 +31,7 @@ ratio: the ratio rewrite on the 60M-row star schema: per group, the three
        (the paper's naive form).
 minmax: the float table's rows with 8 groups (its group column mod 8): COUNT,
        SUM, MIN and MAX of the FP64 column per world, m = 64, against the same
-       query without MIN/MAX, and the C oracle timed on a row prefix.
+       query without MIN/MAX.
 
 Each prints one JSON line per configuration: milliseconds per aggregation
 (mean of --reps after one warm-up) and the algorithmic bytes of the input.
@@ -126,15 +126,6 @@ def minmax(args):
                           "m": 64, "ms": ms, "rows_per_s": t.n_rows / (ms * 1e-3), "alg_bytes": alg,
                           "hbm_frac": alg / (ms * 1e-3) / 8e12}), flush=True)
     ctx.close()
-    if args.oracle_rows > 0:
-        from oracle import native as ON
-        n = min(args.oracle_rows, t.n_rows)
-        t0 = time.perf_counter()
-        ON.onepass(n, 64, pu_keys=t.pu_key, query_key=K, gcols=[t.gcols[0][:n]], gcards=[64], group_mod=8,
-                   n_groups=8, float_cols=[t.cols["v64"][:n]], minmax=True)
-        el = time.perf_counter() - t0
-        print(json.dumps({"workload": "C oracle, same query with MIN/MAX", "rows": n, "s": el,
-                          "rows_per_s": n / el, "threads": ON.default_threads()}), flush=True)
 
 
 def nested(args):
@@ -337,7 +328,6 @@ def main(argv=None):
     ap.add_argument("--queries", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--load", type=float, default=0.7)
-    ap.add_argument("--oracle-rows", type=int, default=20_000_000)
     args = ap.parse_args(argv)
     {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested, "join": join,
      "ratio": ratio}[args.what](args)
