@@ -83,3 +83,31 @@ def test_ctypes_layout_matches_c_header(tmp_path):
         assert got[(cname, "sizeof")] == C.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_product_code_does_not_use_the_oracle():
+    """The package and the shared input generators neither import nor build
+    anything under oracle/ (only the tests, smoke() and the CPU-baseline leg
+    of bench.py may), and the HIP sources include nothing from it."""
+    import ast
+
+    offenders = []
+    for sub in ("paper_2603_15023_amd", "workloads"):
+        for dirpath, _, files in os.walk(os.path.join(ROOT, sub)):
+            for f in files:
+                path = os.path.join(dirpath, f)
+                if f.endswith(".py"):
+                    tree = ast.parse(open(path).read(), path)
+                    for node in ast.walk(tree):
+                        names = []
+                        if isinstance(node, ast.Import):
+                            names = [a.name for a in node.names]
+                        elif isinstance(node, ast.ImportFrom) and node.level == 0:
+                            names = [node.module or ""]
+                        if any(n == "oracle" or n.startswith("oracle.") for n in names):
+                            offenders.append(f"{path}:{node.lineno}")
+                elif f.endswith((".hip", ".h", ".cpp", ".c")):
+                    for i, line in enumerate(open(path), 1):
+                        if line.lstrip().startswith("#include") and "oracle" in line:
+                            offenders.append(f"{path}:{i}")
+    assert not offenders, f"product code reaches the oracle: {offenders}"
