@@ -126,9 +126,32 @@ struct RegAcc {
     }
   }
 
-  // The batch's records of each of the S groups, in lane (row) order.
+  // Row rr of a batch held in the lanes' registers (broadcast by readlane).
+  struct LaneRows {
+    const uint64_t (&mk)[W];
+    const uint64_t (&iv)[NIa];
+    const uint64_t (&fv)[NFa];
+    __device__ __forceinline__ uint64_t mask(int w, int rr) const { return readlane_u64(mk[w], rr); }
+    __device__ __forceinline__ uint64_t ival(int k, int rr) const { return readlane_u64(iv[k], rr); }
+    __device__ __forceinline__ uint64_t fval(int k, int rr) const { return readlane_u64(fv[k], rr); }
+  };
+  // Row rr of a batch staged in LDS as [W][64], [NIa][64] and [NFa][64]
+  // (every lane reads the same address: a broadcast, no VALU work).
+  struct LdsRows {
+    const uint64_t *mk, *iv, *fv;
+    __device__ __forceinline__ uint64_t mask(int w, int rr) const { return mk[w * 64 + rr]; }
+    __device__ __forceinline__ uint64_t ival(int k, int rr) const { return iv[k * 64 + rr]; }
+    __device__ __forceinline__ uint64_t fval(int k, int rr) const { return fv[k * 64 + rr]; }
+  };
+
   __device__ __forceinline__ void batch(int64_t g, int64_t g0, int64_t G, const uint64_t (&mk)[W],
                                         const uint64_t (&iv)[NIa], const uint64_t (&fv)[NFa], int lane) {
+    batch_rows(g, g0, G, LaneRows{mk, iv, fv}, lane);
+  }
+
+  // The batch's records of each of the S groups, in lane (row) order.
+  template <class Rows>
+  __device__ __forceinline__ void batch_rows(int64_t g, int64_t g0, int64_t G, const Rows &rows, int lane) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       if (g0 + s >= G) break;
@@ -140,12 +163,12 @@ struct RegAcc {
         uint64_t u[NIa];
         double v[NFa];
 #pragma unroll
-        for (int k = 0; k < NI; ++k) u[k] = readlane_u64(iv[k], rr);
+        for (int k = 0; k < NI; ++k) u[k] = rows.ival(k, rr);
 #pragma unroll
-        for (int k = 0; k < NF; ++k) v[k] = __longlong_as_double((long long)readlane_u64(fv[k], rr));
+        for (int k = 0; k < NF; ++k) v[k] = __longlong_as_double((long long)rows.fval(k, rr));
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          const bool bit = (readlane_u64(mk[w], rr) >> lane) & 1ull;
+          const bool bit = (rows.mask(w, rr) >> lane) & 1ull;
           cn[s][w] += bit ? 1u : 0u;
 #pragma unroll
           for (int k = 0; k < NI; ++k) {
@@ -257,15 +280,8 @@ __global__ __launch_bounds__(64 * kRegShare) void agg_reg_shared(DevInput in, De
     }
     __syncthreads();
     for (int sub = 0; sub < P; ++sub) {  // the step's batches in row order
-      uint64_t mk[W], iv[Acc::NIa], fv[Acc::NFa];
       const int64_t g = s_g[sub][lane];
-#pragma unroll
-      for (int w = 0; w < W; ++w) mk[w] = s_mk[sub][w][lane];
-#pragma unroll
-      for (int k = 0; k < NI; ++k) iv[k] = s_iv[sub][k][lane];
-#pragma unroll
-      for (int k = 0; k < NF; ++k) fv[k] = s_fv[sub][k][lane];
-      if (g0 < G) acc.batch(g, g0, G, mk, iv, fv, lane);
+      if (g0 < G) acc.batch_rows(g, g0, G, typename Acc::LdsRows{&s_mk[sub][0][0], &s_iv[sub][0][0], &s_fv[sub][0][0]}, lane);
     }
     __syncthreads();
   }
