@@ -237,12 +237,27 @@ __global__ __launch_bounds__(256) void agg_reg(DevInput in, DevState st, uint32_
   const int64_t G = in.n_groups;
   const int64_t n_chunks = (in.n_rows + 63) >> 6, cpr = (n_chunks + n_ranges - 1) / n_ranges;
   const int64_t c0 = range * cpr, c1 = min(n_chunks, c0 + cpr);
+  // Each wavefront stages its batch in its own LDS slice and walks the
+  // records from there (broadcast reads), so only wavefront-level ordering
+  // is needed.
+  __shared__ uint64_t s_mk[4][W][64], s_iv[4][Acc::NIa][64], s_fv[4][Acc::NFa][64];
+  const int wv = threadIdx.x >> 6;
   Acc acc;
   acc.init();
   for (int64_t c = c0; c < c1; ++c) {
     uint64_t mk[W], iv[Acc::NIa], fv[Acc::NFa];
     const int64_t g = reg_row<W, NI, NF>(in, st, c * 64 + lane, status, mk, iv, fv);
-    acc.batch(g, 0, G, mk, iv, fv, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the previous batch's reads come first
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int w = 0; w < W; ++w) s_mk[wv][w][lane] = mk[w];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) s_iv[wv][k][lane] = iv[k];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) s_fv[wv][k][lane] = fv[k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    acc.batch_rows(g, 0, G, typename Acc::LdsRows{&s_mk[wv][0][0], &s_iv[wv][0][0], &s_fv[wv][0][0]}, lane);
   }
   acc.store(partial + range * (slot_words * S), slot_words, 0, G, lane);
 }
