@@ -950,9 +950,23 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
           for (int k = 0; k < CF; ++k) fs[sl][w][k] = 0.0;
         }
       }
+      // The batch is staged in the wave's own LDS slice and each record read
+      // from there at one address for all lanes (a broadcast).
+      __shared__ uint64_t s_rec[kPartWaves][W + (CI > 0 ? CI : 1) + (CF > 0 ? CF : 1)][64];
+      constexpr int kIv = W, kFv = W + (CI > 0 ? CI : 1);
       for (int64_t b = b0; b < b1; b += 64) {
         RecBatch<W, CI, CF> c;
         c.load(b + lane, b1, b0, cap, ni, nf, rec_slot, rec_mk, rec_iv, rec_fv);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the previous batch's reads come first
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int w = 0; w < W; ++w) s_rec[wave][w][lane] = c.mk[w];
+#pragma unroll
+        for (int k = 0; k < CI; ++k) s_rec[wave][kIv + k][lane] = c.iv[k];
+#pragma unroll
+        for (int k = 0; k < CF; ++k) s_rec[wave][kFv + k][lane] = c.fv[k];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int sl = 0; sl < S; ++sl) {
           uint64_t todo = __ballot(c.live && c.ls == (uint32_t)sl);
@@ -963,12 +977,12 @@ __global__ __launch_bounds__(64 * kPartWaves) void part_aggregate_det(
             uint64_t u[CI > 0 ? CI : 1];
             double v[CF > 0 ? CF : 1];
 #pragma unroll
-            for (int k = 0; k < CI; ++k) u[k] = readlane_u64(c.iv[k], rr);
+            for (int k = 0; k < CI; ++k) u[k] = s_rec[wave][kIv + k][rr];
 #pragma unroll
-            for (int k = 0; k < CF; ++k) v[k] = __longlong_as_double((long long)readlane_u64(c.fv[k], rr));
+            for (int k = 0; k < CF; ++k) v[k] = __longlong_as_double((long long)s_rec[wave][kFv + k][rr]);
 #pragma unroll
             for (int w = 0; w < W; ++w) {
-              const bool bit = (readlane_u64(c.mk[w], rr) >> lane) & 1ull;
+              const bool bit = (s_rec[wave][w][rr] >> lane) & 1ull;
               cn[sl][w] += bit ? 1u : 0u;
 #pragma unroll
               for (int k = 0; k < CI; ++k) is[sl][w][k] += bit ? u[k] : 0ull;
