@@ -48,14 +48,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv"])
+    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv", "mfma_generic"])
     ap.add_argument("--compare-steps", type=int, default=5, help="steps timed for the other GPU forms")
     ap.add_argument("--no-pipeline", dest="pipeline", action="store_false",
                     help="time the steps one after another on one stream only")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shuffled", action="store_true", help="fact rows in random order instead of by order")
-    ap.add_argument("--serve-queries", type=int, default=64, help="served-workload queries (0: skip serving)")
+    ap.add_argument("--serve-queries", type=int, default=2000, help="served-workload queries (0: skip serving)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-load", type=float, default=0.7, help="Poisson arrival rate / saturation throughput")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -230,10 +230,11 @@ def main():
     ctx.check()
     log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
 
-    # the other GPU forms on the same inputs (same counters; checked in the tests)
+    # the other GPU forms on the same inputs (same counters; checked in the tests): the plain per-bit form, the
+    # generic matrix-core kernel, the star kernel with the orders carrying their PU key
     forms = {}
     ref_state = {k: v.clone() for k, v in state.items()}
-    for algo in ("plain", "mfma", "mfma_kv"):
+    for algo in ("plain", "mfma", "mfma_generic", "mfma_kv"):
         if args.compare_steps <= 0:
             break
         if algo == args.algo:
@@ -244,6 +245,30 @@ def main():
         forms[algo] = {"ms_per_step": ms2, "aggregate_ms": agg2, "same_counters": bool(same)}
         log(f"{algo}: {ms2:.3f} ms/step, aggregate {agg2:.3f} ms, same counters {same}")
     ctx.check()
+    if args.compare_steps > 0 and not args.shuffled:
+        # the stress layout of the FK chain: the same fact rows in random order (same counters)
+        ts = gen.config2_star(shuffled=True)
+        sspec = dataclasses.replace(spec, links=[torch.from_numpy(ts.f_order).to(dev), links[1]],
+                                    gcols=[torch.from_numpy(g).to(dev) for g in ts.gcols],
+                                    cols=[torch.from_numpy(ts.cols[c]).to(dev) for c in names])
+        del ts
+        sagg = []
+        for i in range(args.compare_steps + 1):
+            P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+            for v in state.values():
+                v.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            P.pac_group_aggregate(ctx, sspec, state, m=64, query_key=K, algo="mfma", init=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if i > 0:
+                sagg.append(e0.elapsed_time(e1))
+        same = all(torch.equal(state[k], ref_state[k]) for k in ("count", "isum", "nrows"))
+        forms["mfma_shuffled"] = {"aggregate_ms": float(np.mean(sagg)), "same_counters": bool(same)}
+        log(f"mfma on shuffled fact rows: aggregate {forms['mfma_shuffled']['aggregate_ms']:.3f} ms, same {same}")
+        del sspec
+        ctx.check()
 
     if args.calibrate_copy_gib > 0:
         ne = int(args.calibrate_copy_gib * (1 << 30)) // 8
@@ -272,6 +297,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(t, K, args.cpu_seconds)
+        cpu["o1_bruteforce"] = bruteforce_timing()
 
     rows_per_s = n / (ms_step * 1e-3)
     out = {
@@ -400,9 +426,36 @@ def cpu_baseline(t, K, target_s):
         passes += 1
         total_rows += rows
     log(f"cpu oracle: {passes} pass(es) of {rows} rows in {el:.2f}s on {threads} threads")
-    return {"value": total_rows / el, "unit": "rows/s", "cores": threads, "kind": "oracle",
+    return {"value": total_rows / el, "unit": "rows/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{passes} pass(es) over the first {rows} of {t.n_rows} fact rows (hash of all 1.5M PU keys "
                       f"+ C one-pass counters per pass), {el:.1f} s wall"}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bruteforce_timing(rows: int = 20_000):
+    """The m-execution brute force of the oracle (the aggregate run once per sampled database, in Python) on
+    the first rows of the 1M-row ungrouped COUNT + SUM workload; a full-size estimate scales it by the rows."""
+    from oracle import pac_ref as R
+    from workloads import gen
+    t = gen.config1_flat()
+    K = gen.query_key(0)
+    g = np.zeros(rows, dtype=np.int64)
+    t0 = time.perf_counter()
+    R.brute_force_flat(t.pu_key[:rows], g, 1, [t.cols["value"][:rows]], [], K, 64)
+    el = time.perf_counter() - t0
+    log(f"o1 brute force: {rows} rows x 64 worlds in {el:.2f}s")
+    return {"rows": rows, "seconds": round(el, 3), "rows_per_s": rows / el,
+            "full_size_estimate_s": round(el * t.n_rows / rows, 1), "threads": 1,
+            "workload": "1M rows, 15K PU keys, int32 values in [1, 50], ungrouped COUNT + SUM, m=64"}
 
 
 if __name__ == "__main__":

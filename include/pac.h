@@ -47,6 +47,7 @@ extern "C" {
 #define PAC_STATUS_TABLE_FULL 4u   /* sparse group hash table out of slots: rows skipped */
 #define PAC_STATUS_DIVERSITY 8u    /* strict diversity check failed in pac_finalize */
 #define PAC_STATUS_DUPLICATE_KEY 16u /* pac_key_index: a key occurs twice in the referenced table */
+#define PAC_STATUS_OUT_OF_RANGE 32u /* an int value outside its stated [col_min, col_max]: row skipped */
 
 typedef struct pac_ctx pac_ctx;
 
@@ -100,7 +101,14 @@ enum pac_type { PAC_U8 = 1, PAC_U16 = 2, PAC_U32 = 3, PAC_I32 = 4, PAC_I64 = 5, 
  * Value columns: PAC_I32 / PAC_I64 sums are exact modulo 2^64 (exact whenever
  * the true sum fits int64); PAC_F32 / PAC_F64 sums accumulate in fp64.
  * has_stats != 0 promises col_min[c] <= value <= col_max[c] for every int
- * column c (host values); it lets the int8 matrix-core path drop zero bytes. */
+ * column c (host values); it lets the int8 matrix-core and ballot forms drop
+ * bytes and bits that are zero in every (value - col_min).  Those forms check
+ * every row's values against the promise on the device: a row with a value
+ * outside its column's range updates no counter and sets
+ * PAC_STATUS_OUT_OF_RANGE (pac_check then fails), so a broken promise never
+ * yields silently wrong counters.  The plain, register and partitioned forms
+ * add full 64-bit values, do not depend on the statistics and add such a row
+ * as given (the statistics there only feed the overflow check). */
 typedef struct {
   int64_t n_rows;
   const uint64_t *masks;   /* device [n_masks][W] or NULL */
@@ -159,6 +167,8 @@ typedef struct {
 #define PAC_ALGO_PARTITION 4u /* many groups: rows radix-partitioned by group slot, each partition in LDS */
 #define PAC_ALGO_REGISTER 5u  /* up to 64 dense groups at m = 64 (32 for some column mixes), 8 or 4 at m = 128: the
                                  plain form with every counter in registers; up to 3 columns (2 with MIN/MAX) */
+#define PAC_ALGO_MFMA_GENERIC 6u /* the int8 matrix-core form's generic kernel even where the kernel specialised
+                                   for the star-schema shape applies (the two compute the same counters) */
 #define PAC_AGG_INIT 1u     /* clear the state (and the sparse table) before aggregating */
 
 /* m in {64, 128}; query_key is used by the fused hash.  Returns

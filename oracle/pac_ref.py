@@ -580,7 +580,8 @@ def diversity_flag(nrows: int, or_pop: int, m: int) -> bool:
 
 def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows: Sequence[int], m: int,
                         budget: float, seed: int, j_star: Optional[int] = None, flags: int = FLAG_SCALE2,
-                        prior: Optional[np.ndarray] = None, first_cell: int = 0):
+                        prior: Optional[np.ndarray] = None, first_cell: int = 0,
+                        trace: Optional[list] = None):
     """Release the cells in order, each with pac_noised under the running posterior.
 
     For cell c with world values y (Sec. 4.1, noise function):
@@ -593,7 +594,9 @@ def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows:
     Reading: Delta = 0 releases y_{j*} exactly and skips step 4.
     The draws of cell c are those of cell index first_cell + c, so one query's
     cells may be released over several calls without reusing a draw.
-    Returns (values, is_null, cell_flags, final P).
+    Returns (values, is_null, cell_flags, final P).  ``trace``, if given, receives
+    (Delta, P before the cell) for each cell (Delta NaN for a NULL cell): test
+    bookkeeping, no arithmetic.
     """
     if j_star is None:
         j_star = secret_world(seed, m)
@@ -607,6 +610,8 @@ def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows:
                 raise ValueError(f"diversity check failed on cell {c}")
         p_null = (m - int(or_pops[c])) / m
         if null_uniform(seed, first_cell + c) < p_null:
+            if trace is not None:
+                trace.append((math.nan, P))
             vals.append(0.0)
             nulls.append(1)
             cflags.append(f | CELL_NULL)
@@ -615,6 +620,8 @@ def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows:
         mu = float(np.sum(P * y))
         s2 = float(np.sum(P * (y - mu) ** 2))
         delta = s2 / (2.0 * budget)
+        if trace is not None:
+            trace.append((delta, P))
         if not delta > 0.0:
             vals.append(float(y[j_star]))
             nulls.append(0)
@@ -635,7 +642,7 @@ def pac_noised_sequence(ys: Sequence[np.ndarray], or_pops: Sequence[int], nrows:
 
 def release(counters: Dict[str, np.ndarray], cells: Sequence[Tuple[int, int, int]], m: int, budget: float,
             seed: int, j_star: Optional[int] = None, flags: int = FLAG_SCALE2,
-            prior: Optional[np.ndarray] = None):
+            prior: Optional[np.ndarray] = None, trace: Optional[list] = None):
     """Finalize a list of cells (group, kind, col) against per-world counters.
 
     K_g is read off the counters: world j received an update of group g iff
@@ -646,7 +653,7 @@ def release(counters: Dict[str, np.ndarray], cells: Sequence[Tuple[int, int, int
         ys.append(cell_vector(counters, g, kind, col, flags))
         pops.append(int(np.count_nonzero(counters["count"][g])))
         ns.append(int(counters["nrows"][g]))
-    vals, nulls, cflags, P = pac_noised_sequence(ys, pops, ns, m, budget, seed, j_star, flags, prior)
+    vals, nulls, cflags, P = pac_noised_sequence(ys, pops, ns, m, budget, seed, j_star, flags, prior, trace=trace)
     return vals, nulls, cflags, P, np.array(ys)
 
 
@@ -750,7 +757,7 @@ def lift_np(inputs: Sequence[np.ndarray], program: Sequence[Tuple[int, int, floa
 
 def pac_noised(world_vectors: np.ndarray, m: int, budget: float, seed: int, j_star: Optional[int] = None,
                flags: int = 0, prior: Optional[np.ndarray] = None, cell_rows: Optional[Sequence[int]] = None,
-               first_cell: int = 0):
+               first_cell: int = 0, trace: Optional[list] = None):
     """pac_noised over given world vectors, one released cell per row of
     ``world_vectors`` ([n_cells][m]), in order, under the running posterior.
 
@@ -766,4 +773,4 @@ def pac_noised(world_vectors: np.ndarray, m: int, budget: float, seed: int, j_st
         pops.append(int(m - np.count_nonzero(null)))
     n = len(ys)
     rows = [0] * n if cell_rows is None else [int(r) for r in cell_rows]
-    return pac_noised_sequence(ys, pops, rows, m, budget, seed, j_star, flags, prior, first_cell)
+    return pac_noised_sequence(ys, pops, rows, m, budget, seed, j_star, flags, prior, first_cell, trace=trace)

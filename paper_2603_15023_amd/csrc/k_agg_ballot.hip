@@ -70,9 +70,23 @@ __global__ __launch_bounds__(256) void agg_ballot(DevInput in, DevState st, uint
         for (int w = 0; w < W; ++w) mk[w] = pu_of_index(in, idx, w);
       }
     }
+    // values outside the stated statistics would lose bits above icol_bits:
+    // such a row updates nothing and reports PAC_STATUS_OUT_OF_RANGE
+    bool out_of_range = false;
 #pragma unroll
     for (int c = 0; c < kMaxCols; ++c)
-      if (c < ni) x[c] = g >= 0 ? (uint64_t)load_icol(in.icols[c], in.icol_type[c], r) - (uint64_t)in.icol_lo[c] : 0;
+      if (c < ni) {
+        x[c] = g >= 0 ? (uint64_t)load_icol(in.icols[c], in.icol_type[c], r) - (uint64_t)in.icol_lo[c] : 0;
+        out_of_range |= x[c] > in.icol_range[c];
+      }
+    if (out_of_range) {
+      atomicOr(status, PAC_STATUS_OUT_OF_RANGE);
+      g = -1;
+#pragma unroll
+      for (int w = 0; w < W; ++w) mk[w] = 0;
+#pragma unroll
+      for (int c = 0; c < kMaxCols; ++c) x[c] = 0;
+    }
     uint64_t T[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) T[w] = transpose64(mk[w], lane);

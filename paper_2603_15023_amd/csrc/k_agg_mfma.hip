@@ -230,6 +230,22 @@ __device__ __forceinline__ void build_planes(const MfmaArgs &a, const MfmaPlan &
     for (int i = 0; i < 4; ++i) ok[i] = ok[i] && sg->f[i][lane] < a.filter_lt;
   }
   if (bad) atomicOr(status, PAC_STATUS_BAD_GROUP);
+  {  // a value outside the stated statistics would lose digits: the row updates nothing
+    bool oor = false;
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+      const bool wide = a.icol_bytes[c] == 8;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint64_t v = wide ? (((uint64_t)sg->v[c][2 * i + 1][lane] << 32) | sg->v[c][2 * i][lane])
+                                : (uint64_t)(int64_t)(int32_t)sg->v[c][i][lane];
+        const bool out = v - (uint64_t)pl.lo[c] > pl.range[c];
+        oor |= ok[i] && out;
+        ok[i] = ok[i] && !out;
+      }
+    }
+    if (oor) atomicOr(status, PAC_STATUS_OUT_OF_RANGE);
+  }
   uint32_t gid4 = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) gid4 |= (ok[i] ? gv[i] : 0xFFu) << (8 * i);
@@ -488,6 +504,7 @@ static bool mfma_plan(const DevInput &in, MfmaPlan *pl, int *nt_out) {
     p.dig[c] = in.icol_digits[c];
     p.doff[c] = D;
     p.lo[c] = in.icol_lo[c];
+    p.range[c] = in.icol_range[c];
     D += p.dig[c];
   }
   p.D = D;

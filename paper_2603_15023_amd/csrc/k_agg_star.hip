@@ -34,6 +34,7 @@ struct StarPlan {
   int32_t G;
   uint32_t lo[kMC];      // low 32 bits of each column's offset (all digits sit in (v - lo) mod 2^32)
   int64_t lo64[kMC];     // the offset itself, for the recombination
+  uint32_t range[kMC];   // max - lo of the statistics (< 2^24): a larger (v - lo) is out of range
   uint32_t card_rep[2];  // gcards[k] * 0x01010101
   uint32_t card1;        // cardinality of the second group column (1 if absent)
   int32_t n_planes;      // D + 3 + G
@@ -50,6 +51,7 @@ struct StarStage {
   uint64_t mk[256];      // PU words by plane position (qrow order)
   uint32_t g[NGC][64];   // group bytes of rows qrow(lane, 0..3)
   uint32_t v[NI][4][64]; // low 32 bits of the values of row qrow(lane, i)
+  uint32_t rv[64];       // non-zero: a value of one of the lane's rows lies outside the statistics
 };
 
 // FK chain of the four rows qrow(lane, 0..3) of a tile: table indices
@@ -112,7 +114,22 @@ struct StarRaw {
   uint32_t ok[4];
   uint32_t g[NGC];
   uint32_t v[NI][4];
+  uint32_t rv;  // see StarStage::rv
 };
+
+// Range check of one column's four values (lo and hi words): non-zero when
+// some (v - lo), taken as a 64-bit unsigned number, exceeds the range.
+__device__ __forceinline__ uint32_t star_range4(const uint32_t (&vl)[4], const uint32_t (&vh)[4], int64_t lo,
+                                                uint32_t range) {
+  uint32_t hor = 0, lmax = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint64_t d = (((uint64_t)vh[i] << 32) | vl[i]) - (uint64_t)lo;
+    hor |= (uint32_t)(d >> 32);
+    lmax = max(lmax, (uint32_t)d);
+  }
+  return hor | (lmax > range ? 1u : 0u);
+}
 
 // Transpose constants of one lane: the two bit stages use rotate + bitfield
 // insert, the byte and half-word stages a byte permutation.
@@ -167,8 +184,10 @@ __device__ __forceinline__ void star_issue_words(const MfmaArgs &a, const QChain
 
 // Column words of the full tile at row0 (no bounds checks).
 template <int NGC, int NI>
-__device__ __forceinline__ void star_issue_cols(const MfmaArgs &a, uint32_t row0, int lane, StarRaw<NGC, NI> &r) {
+__device__ __forceinline__ void star_issue_cols(const MfmaArgs &a, const StarPlan &pl, uint32_t row0, int lane,
+                                                StarRaw<NGC, NI> &r) {
   const uint32_t ra = row0 + 2 * lane, rb = row0 + 128 + 2 * lane;
+  uint32_t rv = 0;
 #pragma unroll
   for (int k = 0; k < NGC; ++k) {
     const uint32_t g0 = __builtin_nontemporal_load((const uint16_t *)(a.gcols[k] + ra));
@@ -183,12 +202,15 @@ __device__ __forceinline__ void star_issue_cols(const MfmaArgs &a, uint32_t row0
     r.v[c][1] = x[2];
     r.v[c][2] = y[0];
     r.v[c][3] = y[2];
+    const uint32_t vh[4] = {x[1], x[3], y[1], y[3]};
+    rv |= star_range4(r.v[c], vh, pl.lo64[c], pl.range[c]);
   }
+  r.rv = rv;
 }
 
 // Column words of a partial tile (rows >= n read as zero).
 template <int NGC, int NI>
-__device__ __forceinline__ void star_issue_cols_tail(const MfmaArgs &a, uint32_t row0, int lane,
+__device__ __forceinline__ void star_issue_cols_tail(const MfmaArgs &a, const StarPlan &pl, uint32_t row0, int lane,
                                                      StarRaw<NGC, NI> &r) {
   const uint32_t n = a.n_rows;
 #pragma unroll
@@ -201,13 +223,20 @@ __device__ __forceinline__ void star_issue_cols_tail(const MfmaArgs &a, uint32_t
     }
     r.g[k] = w;
   }
+  uint32_t rv = 0;
 #pragma unroll
-  for (int c = 0; c < NI; ++c)
+  for (int c = 0; c < NI; ++c) {
+    uint32_t vh[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 4; ++j) {  // rows past the end read as lo: never out of range
       const uint32_t row = row0 + qrow(lane, j);
-      r.v[c][j] = row < n ? ((const uint32_t *)a.icols[c])[2 * row] : 0u;
+      const uint64_t x = row < n ? ((const uint64_t *)a.icols[c])[row] : (uint64_t)pl.lo64[c];
+      r.v[c][j] = (uint32_t)x;
+      vh[j] = (uint32_t)(x >> 32);
     }
+    rv |= star_range4(r.v[c], vh, pl.lo64[c], pl.range[c]);
+  }
+  r.rv = rv;
 }
 
 template <int KV, int NGC, int NI>
@@ -224,6 +253,7 @@ __device__ __forceinline__ void star_stage_store(const MfmaArgs &a, StarStage<NG
   for (int c = 0; c < NI; ++c)
 #pragma unroll
     for (int i = 0; i < 4; ++i) sg->v[c][i][lane] = r.v[c][i];
+  sg->rv[lane] = r.rv;
 }
 
 // Per-byte flag 0x80 where byte >= card (card <= 128), else 0.
@@ -261,6 +291,19 @@ __device__ __forceinline__ void star_planes(const MfmaArgs &a, const StarPlan &p
     off |= past;
   }
   if (bad) atomicOr(status, PAC_STATUS_BAD_GROUP);
+  if (sg->rv[lane]) {  // rare: find the lane's rows whose values lie outside the statistics; they update nothing
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t row = row0 + qrow(lane, i);
+      bool out = false;
+      if (row < a.n_rows)
+#pragma unroll
+        for (int c = 0; c < NI; ++c)
+          out |= ((const uint64_t *)a.icols[c])[row] - (uint64_t)pl.lo64[c] > (uint64_t)pl.range[c];
+      off |= out ? 0x80u << (8 * i) : 0u;
+    }
+    atomicOr(status, PAC_STATUS_OUT_OF_RANGE);
+  }
   const uint32_t offb = off | (off - (off >> 7));
   gid = bfi(offb, 0x0C0C0C0Cu, gid);
 #pragma unroll
@@ -463,7 +506,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
       qchain_first(a, row_of(gi, k), lane, c);
       if (!KV) qchain_next(a, c, status);
       star_issue_words<KV>(a, c, r, status);
-      star_issue_cols(a, row_of(gi, k), lane, r);
+      star_issue_cols(a, pl, row_of(gi, k), lane, r);
       star_stage_store<KV>(a, stage + k, lane, r);
     }
     QChain l1[kStarTPI], l0[kStarTPI];  // group + stride after both links, group + 2 stride after the first
@@ -479,7 +522,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         star_issue_words<KV>(a, l1[k], r[k], status);
-        star_issue_cols(a, row_of(clampg(gi + stride), k), lane, r[k]);
+        star_issue_cols(a, pl, row_of(clampg(gi + stride), k), lane, r[k]);
       }
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
@@ -512,7 +555,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
     qchain_first_tail(a, row0, lane, c);
     if (!KV) qchain_next(a, c, status);
     star_issue_words<KV>(a, c, r, status);
-    star_issue_cols_tail(a, row0, lane, r);
+    star_issue_cols_tail(a, pl, row0, lane, r);
     star_stage_store<KV>(a, stage, lane, r);
     star_planes<NGC, NI, DIG>(a, pl, stage, row0, true, planes, lane, gcnt, status);
     wave_lds_fence();
@@ -577,6 +620,7 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   for (int c = 0; c < in.n_icols; ++c) {
     p.lo[c] = (uint32_t)in.icol_lo[c];
     p.lo64[c] = in.icol_lo[c];
+    p.range[c] = (uint32_t)in.icol_range[c];  // < 2^24: three digits
   }
   p.card_rep[0] = (uint32_t)in.gcards[0] * 0x01010101u;
   p.card_rep[1] = (uint32_t)in.gcards[1] * 0x01010101u;
@@ -589,7 +633,7 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   const int planes_bytes = p.n_planes * kPlaneStride;
   const int flush_bytes = 16 * NT * 16 * 4;
   p.stage_off = (std::max(planes_bytes, flush_bytes) + 15) & ~15;
-  const int stage_bytes = 64 * (8 * 4 + 4 * in.n_gcols + 16 * in.n_icols);
+  const int stage_bytes = 64 * (8 * 4 + 4 * in.n_gcols + 16 * in.n_icols + 4);
   p.wave_bytes = (p.stage_off + kStarTPI * stage_bytes + 15) & ~15;
   p.blk_off = kStarWPB * p.wave_bytes;
   p.blk_words = (int)G * (1 + in.n_icols) * 64 + (int)G;
@@ -607,7 +651,7 @@ bool star_supported(const DevInput &in) {
 
 template <int KV, int NGC, int NI, int DIG, int NT>
 static hipError_t launch_star_t(const LaunchEnv &env, const DevInput &in, const DevState &st, const StarPlan &pl) {
-  static_assert(sizeof(StarStage<NGC, NI>) == 64 * (8 * 4 + 4 * NGC + 16 * NI), "stage");
+  static_assert(sizeof(StarStage<NGC, NI>) == 64 * (8 * 4 + 4 * NGC + 16 * NI + 4), "stage");
   const int lds = pl.blk_off + pl.blk_words * 8;
   const void *fn = (const void *)agg_star<KV, NGC, NI, DIG, NT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -28,6 +28,7 @@ struct MfmaPlan {
   int32_t dig[kMaxCols];
   int32_t doff[kMaxCols];
   int64_t lo[kMaxCols];
+  uint64_t range[kMaxCols];  // max - lo of the statistics: (v - lo) above it is out of range
   int32_t wave_bytes;   // per-wave LDS: planes (reused as the flush buffer), then the staging area
   int32_t stage_off;
   int32_t blk_off;      // block-shared int64 counters [G][1+ni][m] + nrows[G]

@@ -167,6 +167,7 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
       }
       const uint64_t range = (uint64_t)hi - (uint64_t)lo;
       d->icol_lo[i] = lo;
+      d->icol_range[i] = range;
       d->icol_bits[i] = bit_length(range);
       d->icol_digits[i] = (bit_length(range) + 7) / 8;
     } else if (is_float(t)) {
@@ -266,10 +267,12 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
       e = pac::launch_agg_ballot(env, d, ds);
       break;
     case PAC_ALGO_MFMA_I8:
+    case PAC_ALGO_MFMA_GENERIC:
       if (!pac::mfma_supported(d))
         return fail(PAC_ERR_UNSUPPORTED, "int8 matrix-core form needs int columns, <= 254 dense groups and "
                                          "groups x (digits+1) within the tile");
-      e = pac::star_supported(d) ? pac::launch_agg_star(env, d, ds) : pac::launch_agg_mfma(env, d, ds);
+      e = algo == PAC_ALGO_MFMA_I8 && pac::star_supported(d) ? pac::launch_agg_star(env, d, ds)
+                                                              : pac::launch_agg_mfma(env, d, ds);
       break;
     case PAC_ALGO_PARTITION: {
       if (!pac::part_supported(d))

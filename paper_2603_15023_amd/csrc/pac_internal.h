@@ -43,6 +43,7 @@ struct DevInput {
   int64_t icol_lo[kMaxCols];     // digits are bytes of (v - lo) as unsigned
   int32_t icol_digits[kMaxCols]; // bytes of (max - lo) that can be non-zero
   int32_t icol_bits[kMaxCols];   // bits of (max - lo) that can be non-zero
+  uint64_t icol_range[kMaxCols]; // max - lo: a value v is within the statistics iff (v - lo) <= range (unsigned)
   const void *fcols[kMaxCols];
   int32_t fcol_type[kMaxCols];
 };

@@ -159,11 +159,14 @@ def test_minmax_release_matches_oracle(ctx, torch_mod, m):
                                                    mi_budget=1.0 / 128, noise_seed=seed, want_y=True)
     assert ctx.status() == 0
     counters = _star_want(t, K, m, ints=("v0",))
-    wv, wn, wf, wp, wy = R.release(counters, cells, m, 1.0 / 128, seed)
+    deltas = []
+    wv, wn, wf, wp, wy = R.release(counters, cells, m, 1.0 / 128, seed, trace=deltas)
     assert np.array_equal(ys.cpu().numpy(), wy)
     assert np.array_equal(nulls.cpu().numpy(), wn) and np.array_equal(cflags.cpu().numpy(), wf)
     np.testing.assert_allclose(vals.cpu().numpy(), wv, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(post.cpu().numpy(), wp, rtol=1e-9, atol=1e-300)
+    from cases import check_posterior
+    check_posterior(post.cpu().numpy(), wp, wy, wn, wv, vals.cpu().numpy(), deltas, m,
+                    rerun=lambda p: R.release(counters, cells, m, 1.0 / 128, seed, prior=p)[3])
 
 
 # Register form (one wavefront per row range for up to 8 (4) groups, eight

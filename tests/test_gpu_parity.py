@@ -13,7 +13,7 @@ from oracle import native as ON
 from oracle import pac_ref as R
 from workloads import gen
 
-from cases import compare_counters, gpu_star, star_definition, star_oracle
+from cases import check_posterior, compare_counters, gpu_star, star_definition, star_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -198,6 +198,50 @@ def test_star_kernel_flags_bad_links(ctx, which):
     assert got["status"] & 2
 
 
+OOR_CASES = {
+    # form -> (table shape, filter): the star kernel (no filter, 3 digits), the generic matrix-core kernel
+    # (a filter takes it off the star shape) and the ballot form
+    "star": dict(gcards=(3, 2), n_cols=3, value_range=(0, 9_999_999), filt=False, algo="mfma"),
+    "mfma": dict(gcards=(3, 2), n_cols=2, value_range=(-70_000, 9_000_000), filt=True, algo="mfma"),
+    "ballot": dict(gcards=(2,), n_cols=1, value_range=(1, 50), filt=False, algo="ballot"),
+}
+
+
+@pytest.mark.parametrize("form", sorted(OOR_CASES))
+def test_value_outside_stated_range_is_reported(ctx, form):
+    """A value outside the promised [col_min, col_max] sets PAC_STATUS_OUT_OF_RANGE and its row updates no
+    counter; every other row is aggregated as usual (the forms whose digits or bits come from the statistics)."""
+    import dataclasses
+    import paper_2603_15023_amd as P
+    c = OOR_CASES[form]
+    n_rows = 256 * 23 + 45  # full tiles and a ragged tail
+    t = gen.tiny_star(71, n_pu=400, n_orders=2500, n_rows=n_rows, gcards=c["gcards"], n_cols=c["n_cols"],
+                      value_range=c["value_range"], with_sel=c["filt"])
+    ints = [f"v{i}" for i in range(c["n_cols"])]
+    stats = [(int(t.cols[k].min()), int(t.cols[k].max())) for k in ints]
+    bad = np.array([7, 2049, n_rows - 2])  # the last one in the ragged tail
+    lo0, hi0 = stats[0]
+    t.cols["v0"][bad[0]] = hi0 + (1 << 40)   # high word set
+    t.cols["v0"][bad[1]] = lo0 - 1           # just below the minimum
+    t.cols[ints[-1]][bad[2]] = hi0 + 1 if len(ints) == 1 else stats[-1][1] + 1  # just above the maximum
+    K, lt = 0x0BAD, (3 << 30) if c["filt"] else None
+    if c["filt"]:
+        t.sel[bad] = 0  # the bad rows pass the filter
+    _say("out of range", form)
+    got = gpu_star(ctx, t, K, 64, filter_lt=lt, int_cols=ints, algo=c["algo"], stats=stats)
+    assert got["status"] & P._abi.PAC_STATUS_OUT_OF_RANGE, form
+    keep = np.ones(n_rows, dtype=bool)
+    keep[bad] = False
+    t2 = dataclasses.replace(t, f_order=t.f_order[keep], gcols=[g[keep] for g in t.gcols],
+                             cols={k: v[keep] for k, v in t.cols.items()},
+                             sel=None if t.sel is None else t.sel[keep])
+    compare_counters(got, star_definition(t2, K, 64, filter_lt=lt, int_cols=ints))
+    # with statistics that hold, the same rows aggregate without a status bit
+    ok = gpu_star(ctx, t, K, 64, filter_lt=lt, int_cols=ints, algo=c["algo"])
+    assert ok["status"] == 0
+    compare_counters(ok, star_definition(t, K, 64, filter_lt=lt, int_cols=ints))
+
+
 def test_bad_link_sets_status(ctx):
     t = gen.tiny_star(29, n_pu=10, n_orders=20, n_rows=300, gcards=(2,), n_cols=1)
     t.f_order = t.f_order.copy()
@@ -234,6 +278,21 @@ def test_config2_full_size(ctx, algo):
     got = gpu_star(ctx, t, K, 64, int_cols=ints, algo=algo)
     assert got["status"] == 0
     compare_counters(got, _config2_oracle())
+
+
+def test_config2_shuffled_full_size(ctx):
+    """The 60M-row star schema with its fact rows in random order (the stress layout of the FK chain):
+    the benchmark kernel's counters equal the oracle's.  A permutation of the rows leaves every per-world
+    sum unchanged, so the clustered table's oracle counters are the expected values; the C oracle also runs
+    on the shuffled table itself."""
+    t = gen.config2_star(shuffled=True)
+    K = gen.query_key(1)
+    ints = ["v1", "v2", "v3"]
+    _say("config2 shuffled")
+    got = gpu_star(ctx, t, K, 64, int_cols=ints, algo="mfma")
+    assert got["status"] == 0
+    compare_counters(got, _config2_oracle())
+    compare_counters(got, star_oracle(t, K, 64, int_cols=ints))
 
 
 def test_config2_key_valued_orders_full_size(ctx):
@@ -477,12 +536,14 @@ def test_finalize_matches_oracle(ctx, torch_mod, m):
     vals, nulls, flags, post, ys = P.pac_finalize(ctx, state, ct, len(cells), m=m, mi_budget=B, noise_seed=seed,
                                                  want_y=True)
     assert ctx.check() == 0
-    wv, wn, wf, wP, wy = R.release(counters, cells, m, B, seed)
+    deltas = []
+    wv, wn, wf, wP, wy = R.release(counters, cells, m, B, seed, trace=deltas)
     assert np.array_equal(ys.cpu().numpy(), wy)
     assert np.array_equal(nulls.cpu().numpy(), wn)
     assert np.array_equal(flags.cpu().numpy().astype(np.uint32), wf)
     np.testing.assert_allclose(vals.cpu().numpy(), wv, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(post.cpu().numpy(), wP, rtol=1e-9, atol=1e-300)
+    check_posterior(post.cpu().numpy(), wP, wy, wn, wv, vals.cpu().numpy(), deltas, m,
+                    rerun=lambda p: R.release(counters, cells, m, B, seed, prior=p)[3])
 
 
 def _release_case(ctx, torch_mod, m, cells, B, seed, flags, j_star=-1, prior=None):
@@ -509,11 +570,14 @@ def test_finalize_flags_prior_jstar(ctx, torch_mod, m, flags):
     prior = np.random.default_rng(m + flags).dirichlet(np.ones(m))
     counters, (v, n, f, post) = _release_case(ctx, torch_mod, m, cells, 1.0 / 64, 0xABCDEF + flags, flags,
                                                  j_star=m // 3, prior=prior)
-    wv, wn, wf, wP, _ = R.release(counters, cells, m, 1.0 / 64, 0xABCDEF + flags, j_star=m // 3, flags=flags,
-                                  prior=prior)
+    deltas = []
+    wv, wn, wf, wP, wy = R.release(counters, cells, m, 1.0 / 64, 0xABCDEF + flags, j_star=m // 3, flags=flags,
+                                   prior=prior, trace=deltas)
     assert np.array_equal(n, wn) and np.array_equal(f, wf)
     np.testing.assert_allclose(v, wv, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(post, wP, rtol=1e-9, atol=1e-300)
+    check_posterior(post, wP, wy, wn, wv, v, deltas, m, fixed_prior=bool(flags & R.FLAG_FIXED_PRIOR), prior=prior,
+                    rerun=lambda p: R.release(counters, cells, m, 1.0 / 64, 0xABCDEF + flags, j_star=m // 3,
+                                              flags=flags, prior=p)[3])
 
 
 def test_finalize_long_chain_crosses_chunks(ctx, torch_mod):
@@ -530,13 +594,15 @@ def test_finalize_long_chain_crosses_chunks(ctx, torch_mod):
     groups = rng.integers(0, 6, size=n_cells)
     cells = [(int(g), int(k), 0) for g, k in zip(groups, kinds)]
     counters, (v, n, f, post) = _release_case(ctx, torch_mod, 64, cells, 1e-6, 99, R.FLAG_SCALE2)
-    wv, wn, wf, wP, wy = R.release(counters, cells, 64, 1e-6, 99)
+    deltas = []
+    wv, wn, wf, wP, wy = R.release(counters, cells, 64, 1e-6, 99, trace=deltas)
     assert wP.min() > 1e-3  # the posterior never concentrated: no world underflows along the chain
     assert np.array_equal(n, wn) and np.array_equal(f, wf)
     y_js = wy[:, R.secret_world(99, 64)]
     bound = 1e-12 * (np.abs(y_js) + np.abs(wv - y_js))
     assert np.all(np.abs(v - wv) <= bound)
-    np.testing.assert_allclose(post, wP, rtol=1e-9, atol=1e-300)
+    check_posterior(post, wP, wy, wn, wv, v, deltas, 64, rerun=lambda p: R.release(counters, cells, 64, 1e-6, 99,
+                                                                                   prior=p)[3])
 
 
 def test_finalize_invalid_cells_are_null(ctx, torch_mod):
@@ -554,10 +620,12 @@ def test_finalize_invalid_cells_are_null(ctx, torch_mod):
     pops = pops[:3] + [0] * len(bad) + pops[3:]
     ns = [int(counters["nrows"][g]) for (g, _, _) in good]
     ns = ns[:3] + [0] * len(bad) + ns[3:]
-    wv, wn, wf, wP = R.pac_noised_sequence(ys, pops, ns, 64, 1.0 / 128, 5)
+    deltas = []
+    wv, wn, wf, wP = R.pac_noised_sequence(ys, pops, ns, 64, 1.0 / 128, 5, trace=deltas)
     assert np.array_equal(n, wn) and np.array_equal(f, wf)
     np.testing.assert_allclose(v, wv, rtol=1e-12, atol=0)
-    np.testing.assert_allclose(post, wP, rtol=1e-9, atol=1e-300)
+    check_posterior(post, wP, ys, wn, wv, v, deltas, 64,
+                    rerun=lambda p: R.pac_noised_sequence(ys, pops, ns, 64, 1.0 / 128, 5, prior=p)[3])
 
 
 @pytest.mark.parametrize("with_prior", [False, True])
