@@ -230,6 +230,27 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
                  int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
                  uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y);
 
+/* ---- release without allocation -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * pac_finalize_noalloc takes the arguments of pac_finalize and releases the
+ * same cells with the same kernels, so its outputs are bit-identical to
+ * pac_finalize's.  Its working memory (each cell's world vector and draws,
+ * at most PAC_NOALLOC_MAX_CELLS x (128 x 8 + 16) bytes, about 16.3 MiB) is a
+ * fixed device array of the library: every GPU the library runs on holds one
+ * copy until the process ends, and pac_ctx_create looks up its address once
+ * per device.  The call itself allocates nothing (no hipMalloc, no pool
+ * growth) and needs nothing cleared.
+ * n_cells > PAC_NOALLOC_MAX_CELLS returns PAC_ERR_INVALID before any launch.
+ * All calls on one GPU share the array and it keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, other
+ * contexts or host threads) race, and the caller must order them. */
+#define PAC_NOALLOC_MAX_CELLS 16384
+int pac_finalize_noalloc(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
+                         int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params,
+                         double *out_val, uint8_t *out_is_null, uint32_t *out_flags, double *posterior,
+                         double *out_y);
+
 /* ---- post-aggregation (Sec. 4.2 vector-lifted expressions and PAC
  * Selection; Sec. 3.2 categorical rewrites, fused pac_select_<cmp>) -------- */
 

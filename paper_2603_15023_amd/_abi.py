@@ -32,6 +32,7 @@ PAC_CELL_NULL, PAC_CELL_DIVERSITY, PAC_CELL_ZERO_VARIANCE = 1, 2, 4
 PAC_WV_RELEASE, PAC_WV_SCALE2, PAC_WV_AVG_TOTALCOUNT = 0x100, 0x200, 0x400
 PAC_LIFT_INPUT, PAC_LIFT_CONST, PAC_LIFT_ADD, PAC_LIFT_SUB, PAC_LIFT_MUL, PAC_LIFT_DIV, PAC_LIFT_NEG = range(7)
 PAC_LIFT_MAX_INPUTS, PAC_LIFT_MAX_OPS, PAC_LIFT_MAX_DEPTH = 8, 64, 8
+PAC_NOALLOC_MAX_CELLS = 16384
 
 
 class AggInput(C.Structure):
@@ -84,6 +85,9 @@ EXPORTS = {
     "pac_finalize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
                                C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pac_finalize_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int,
+                                       C.c_int, C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pac_world_values": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
                                    C.c_int32, C.c_int32, C.c_void_p]),
     "pac_key_index": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),

@@ -233,23 +233,31 @@ def cells_tensor(cells: Sequence[Tuple[int, int, int]], device=None) -> torch.Te
 def pac_finalize(ctx: Context, state: Dict[str, torch.Tensor], cells: torch.Tensor, n_cells: int, m: int = 64,
                  mi_budget: float = 1.0 / 128, noise_seed: int = 0, j_star: int = -1,
                  flags: int = A.PAC_FIN_SCALE2, prior: Optional[torch.Tensor] = None, want_y: bool = False,
-                 stream=None):
-    """a7: release ``n_cells`` cells; returns (values, is_null, cell_flags, posterior, y or None)."""
+                 stream=None, out=None, no_alloc: bool = False):
+    """a7: release ``n_cells`` cells; returns (values, is_null, cell_flags, posterior, y or None).
+
+    out: preallocated (values, is_null, cell_flags, posterior, y or None) to fill instead of new tensors.
+    no_alloc: call pac_finalize_noalloc (the library's fixed working memory, at most
+    PAC_NOALLOC_MAX_CELLS cells) instead of pac_finalize."""
     dev = state["count"].device
-    vals = torch.empty(n_cells, dtype=torch.float64, device=dev)
-    nulls = torch.empty(n_cells, dtype=torch.uint8, device=dev)
-    cflags = torch.empty(n_cells, dtype=torch.int32, device=dev)
-    post = torch.empty(m, dtype=torch.float64, device=dev)
+    if out is None:
+        vals = torch.empty(n_cells, dtype=torch.float64, device=dev)
+        nulls = torch.empty(n_cells, dtype=torch.uint8, device=dev)
+        cflags = torch.empty(n_cells, dtype=torch.int32, device=dev)
+        post = torch.empty(m, dtype=torch.float64, device=dev)
+        ys = torch.empty((n_cells, m), dtype=torch.float64, device=dev) if want_y else None
+    else:
+        vals, nulls, cflags, post, ys = out
     if prior is not None:
         post.copy_(prior)
         flags |= A.PAC_FIN_PRIOR_IN
-    ys = torch.empty((n_cells, m), dtype=torch.float64, device=dev) if want_y else None
     params = A.FinalizeParams(float(mi_budget), noise_seed & ((1 << 64) - 1), int(j_star), int(flags))
     cst = _state_c(state)
     G = int(state["count"].shape[0])
-    A.check(A.load().pac_finalize(ctx.handle, _stream_handle(stream), C.byref(cst), m, G,
-                                  int(state["isum"].shape[1]), int(state["fsum"].shape[1]), _ptr(cells), n_cells,
-                                  C.byref(params), _ptr(vals), _ptr(nulls), _ptr(cflags), _ptr(post), _ptr(ys)))
+    fn = A.load().pac_finalize_noalloc if no_alloc else A.load().pac_finalize
+    A.check(fn(ctx.handle, _stream_handle(stream), C.byref(cst), m, G, int(state["isum"].shape[1]),
+               int(state["fsum"].shape[1]), _ptr(cells), n_cells, C.byref(params), _ptr(vals), _ptr(nulls),
+               _ptr(cflags), _ptr(post), _ptr(ys)))
     return vals, nulls, cflags, post, ys
 
 

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "pac_internal.h"
@@ -18,9 +19,22 @@ struct pac_ctx {
   uint32_t *d_status;
   void *scratch;
   size_t scratch_bytes;
+  void *noalloc;  // device address of this device's copy of noalloc_scratch
 };
 
+// Working memory of pac_finalize_noalloc: a fixed array in the library's code
+// object, of which every device holds its own copy.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it passes the device address that hipGetSymbolAddress returns with
+// that device current, looked up once per device.
+constexpr size_t kNoAllocBytes = (size_t)PAC_NOALLOC_MAX_CELLS * (128 * sizeof(double) + 16) + 256;
+static __device__ __align__(256) uint8_t noalloc_scratch[kNoAllocBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_addr[kMaxDevices] = {};
 
 thread_local std::string g_err;
 
@@ -66,6 +80,21 @@ int ensure_scratch(pac_ctx *ctx, size_t bytes) {
     return fail(PAC_ERR_OOM, "scratch allocation of %zu bytes failed", want);
   }
   ctx->scratch_bytes = want;
+  return PAC_OK;
+}
+
+// Device address of noalloc_scratch on `device`, which must be current.
+int noalloc_address(int device, void **out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (device < 0 || device >= kMaxDevices) return fail(PAC_ERR_UNSUPPORTED, "device %d: above %d devices", device, kMaxDevices);
+  if (!g_noalloc_addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(noalloc_scratch)");
+    if (!p) return fail(PAC_ERR_HIP, "hipGetSymbolAddress(noalloc_scratch) returned null");
+    g_noalloc_addr[device] = p;
+  }
+  *out = g_noalloc_addr[device];
   return PAC_OK;
 }
 
@@ -319,9 +348,13 @@ int pac_ctx_create(int hip_device, pac_ctx **out) {
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, hip_device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  void *noalloc = nullptr;
+  const int rc = noalloc_address(hip_device, &noalloc);
+  if (rc != PAC_OK) return rc;
   pac_ctx *ctx = new pac_ctx();
   ctx->device = hip_device;
   ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  ctx->noalloc = noalloc;
   e = hipMalloc((void **)&ctx->d_status, sizeof(uint32_t));
   if (e != hipSuccess) {
     delete ctx;
@@ -512,9 +545,15 @@ int pac_key_index(pac_ctx *ctx, void *stream, const int64_t *keys, int64_t n_key
   return PAC_OK;
 }
 
-int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
-                 int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
-                 uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y) {
+}  // extern "C"
+
+namespace {
+
+// pac_finalize's argument checks; fills the kernel-side views.
+int finalize_args(pac_ctx *ctx, const pac_agg_state *state, int m, int64_t n_groups, int n_int, int n_float,
+                  const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
+                  uint8_t *out_is_null, uint32_t *out_flags, double *posterior, pac::DevState *ds,
+                  pac::FinParams *fp) {
   if (!ctx || !state || !params) return fail(PAC_ERR_INVALID, "null context, state or params");
   if (m != 64 && m != 128) return fail(PAC_ERR_INVALID, "m must be 64 or 128 (got %d)", m);
   if (n_cells < 0 || n_int < 0 || n_float < 0 || n_groups < 1) return fail(PAC_ERR_INVALID, "bad sizes");
@@ -526,15 +565,55 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
     return fail(PAC_ERR_INVALID, "null cell or output arrays");
   if (n_int > 0 && !state->isum) return fail(PAC_ERR_INVALID, "state.isum missing");
   if (n_float > 0 && !state->fsum) return fail(PAC_ERR_INVALID, "state.fsum missing");
+  *ds = pac::DevState{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used,
+                      state->imin,  state->imax, state->fmin, state->fmax,  0};
+  *fp = pac::FinParams{params->mi_budget, params->noise_seed, params->j_star, params->flags, m, n_int, n_float,
+                       n_cells, n_groups};
+  return PAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
+                 int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
+                 uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y) {
+  pac::DevState ds;
+  pac::FinParams fp;
+  int rc = finalize_args(ctx, state, m, n_groups, n_int, n_float, cells, n_cells, params, out_val, out_is_null,
+                         out_flags, posterior, &ds, &fp);
+  if (rc != PAC_OK) return rc;
   DeviceGuard guard(ctx->device);
-  pac::DevState ds{state->count, state->isum, state->fsum, state->nrows, state->slot_keys, state->n_used,
-                   state->imin,  state->imax, state->fmin, state->fmax,  0};
-  pac::FinParams fp{params->mi_budget, params->noise_seed, params->j_star, params->flags, m, n_int, n_float, n_cells, n_groups};
   pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
-  const int rc = ensure_scratch(ctx, pac::finalize_scratch_bytes(m, n_cells));
+  rc = ensure_scratch(ctx, pac::finalize_scratch_bytes(m, n_cells));
   if (rc != PAC_OK) return rc;
   hipError_t e =
       pac::launch_finalize(env, ds, cells, fp, out_val, out_is_null, out_flags, posterior, out_y, ctx->scratch);
+  if (e != hipSuccess) return hip_fail(e, "finalize launch");
+  return PAC_OK;
+}
+
+int pac_finalize_noalloc(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
+                         int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params,
+                         double *out_val, uint8_t *out_is_null, uint32_t *out_flags, double *posterior,
+                         double *out_y) {
+  pac::DevState ds;
+  pac::FinParams fp;
+  int rc = finalize_args(ctx, state, m, n_groups, n_int, n_float, cells, n_cells, params, out_val, out_is_null,
+                         out_flags, posterior, &ds, &fp);
+  if (rc != PAC_OK) return rc;
+  if (n_cells > PAC_NOALLOC_MAX_CELLS)
+    return fail(PAC_ERR_INVALID, "pac_finalize_noalloc releases at most %d cells per call (got %lld)",
+                PAC_NOALLOC_MAX_CELLS, (long long)n_cells);
+  if (pac::finalize_scratch_bytes(m, n_cells) > kNoAllocBytes)
+    return fail(PAC_ERR_INVALID, "pac_finalize_noalloc: %lld cells need more than the fixed %zu bytes",
+                (long long)n_cells, kNoAllocBytes);
+  if (!ctx->noalloc) return fail(PAC_ERR_INVALID, "context has no fixed working memory");
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e =
+      pac::launch_finalize(env, ds, cells, fp, out_val, out_is_null, out_flags, posterior, out_y, ctx->noalloc);
   if (e != hipSuccess) return hip_fail(e, "finalize launch");
   return PAC_OK;
 }
