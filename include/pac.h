@@ -230,6 +230,32 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
                  int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params, double *out_val,
                  uint8_t *out_is_null, uint32_t *out_flags, double *posterior, double *out_y);
 
+/* Batched release: several queries' cells in one call, each query exactly as
+ * pac_finalize releases it (its own state, cells, params, outputs and
+ * posterior; the same kernels, so the outputs are bit-identical).  Up to
+ * PAC_MAX_RELEASE_BATCH queries share each launch: phase 1 computes every
+ * query's world vectors in one grid, phase 2 runs one wavefront per query, so
+ * the queries' sequential chains (Sec. 4.1: each released cell updates the
+ * posterior of its query) proceed side by side on different CUs instead of one
+ * after another.  More jobs are taken PAC_MAX_RELEASE_BATCH at a time.
+ * jobs: host array of n_jobs descriptors holding device pointers; all jobs use
+ * the same m.  Errors: as pac_finalize, with the failing job named. */
+#define PAC_MAX_RELEASE_BATCH 16
+typedef struct {
+  pac_agg_state state;        /* the query's counters (device) */
+  int64_t n_groups;
+  int32_t n_int, n_float;
+  const pac_cell *cells;      /* device [n_cells] */
+  int64_t n_cells;
+  pac_finalize_params params;
+  double *out_val;            /* device [n_cells] */
+  uint8_t *out_is_null;       /* device [n_cells] */
+  uint32_t *out_flags;        /* device [n_cells] */
+  double *posterior;          /* device [m]: prior in with PAC_FIN_PRIOR_IN, final posterior out */
+  double *out_y;              /* device [n_cells][m] or NULL */
+} pac_release_job;
+int pac_finalize_batch(pac_ctx *ctx, void *stream, int m, const pac_release_job *jobs, int n_jobs);
+
 /* ---- release without allocation -------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.

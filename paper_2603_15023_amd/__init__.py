@@ -9,10 +9,12 @@ from ._abi import PacError  # noqa: F401
 from .api import (  # noqa: F401
     AggSpec,
     Context,
+    ReleaseRequest,
     cells_tensor,
     new_state,
     pac_filter,
     pac_finalize,
+    pac_finalize_batch,
     pac_group_aggregate,
     pac_group_aggregate_batch,
     pac_hash_mask,

@@ -69,6 +69,15 @@ class FinalizeParams(C.Structure):
                 ("flags", C.c_uint32)]
 
 
+class ReleaseJob(C.Structure):
+    _fields_ = [("state", AggState), ("n_groups", C.c_int64), ("n_int", C.c_int32), ("n_float", C.c_int32),
+                ("cells", C.c_void_p), ("n_cells", C.c_int64), ("params", FinalizeParams),
+                ("out_val", C.c_void_p), ("out_is_null", C.c_void_p), ("out_flags", C.c_void_p),
+                ("posterior", C.c_void_p), ("out_y", C.c_void_p)]
+
+
+PAC_MAX_RELEASE_BATCH = 16
+
 EXPORTS = {
     "pac_ctx_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
     "pac_ctx_destroy": (C.c_int, [C.c_void_p]),
@@ -85,6 +94,7 @@ EXPORTS = {
     "pac_finalize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
                                C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pac_finalize_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(ReleaseJob), C.c_int]),
     "pac_finalize_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int,
                                        C.c_int, C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

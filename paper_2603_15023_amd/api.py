@@ -261,6 +261,51 @@ def pac_finalize(ctx: Context, state: Dict[str, torch.Tensor], cells: torch.Tens
     return vals, nulls, cflags, post, ys
 
 
+@dataclasses.dataclass
+class ReleaseRequest:
+    """One query of pac_finalize_batch: its counters, cells and release parameters."""
+
+    state: Dict[str, torch.Tensor]
+    cells: torch.Tensor
+    n_cells: int
+    mi_budget: float = 1.0 / 128
+    noise_seed: int = 0
+    j_star: int = -1
+    flags: int = A.PAC_FIN_SCALE2
+    prior: Optional[torch.Tensor] = None
+    want_y: bool = False
+
+
+def pac_finalize_batch(ctx: Context, requests: Sequence[ReleaseRequest], m: int = 64, stream=None):
+    """Releases several queries at once (their chains side by side); returns one
+    (values, is_null, cell_flags, posterior, y or None) tuple per request, as pac_finalize."""
+    n = len(requests)
+    jobs = (A.ReleaseJob * max(1, n))()
+    outs = []
+    for i, r in enumerate(requests):
+        dev = r.state["count"].device
+        vals = torch.empty(r.n_cells, dtype=torch.float64, device=dev)
+        nulls = torch.empty(r.n_cells, dtype=torch.uint8, device=dev)
+        cflags = torch.empty(r.n_cells, dtype=torch.int32, device=dev)
+        post = torch.empty(m, dtype=torch.float64, device=dev)
+        ys = torch.empty((r.n_cells, m), dtype=torch.float64, device=dev) if r.want_y else None
+        flags = r.flags
+        if r.prior is not None:
+            post.copy_(r.prior)
+            flags |= A.PAC_FIN_PRIOR_IN
+        jb = jobs[i]
+        jb.state = _state_c(r.state)
+        jb.n_groups = int(r.state["count"].shape[0])
+        jb.n_int, jb.n_float = int(r.state["isum"].shape[1]), int(r.state["fsum"].shape[1])
+        jb.cells, jb.n_cells = _ptr(r.cells), int(r.n_cells)
+        jb.params = A.FinalizeParams(float(r.mi_budget), r.noise_seed & ((1 << 64) - 1), int(r.j_star), int(flags))
+        jb.out_val, jb.out_is_null, jb.out_flags = _ptr(vals), _ptr(nulls), _ptr(cflags)
+        jb.posterior, jb.out_y = _ptr(post), _ptr(ys)
+        outs.append((vals, nulls, cflags, post, ys))
+    A.check(A.load().pac_finalize_batch(ctx.handle, _stream_handle(stream), m, jobs, n))
+    return outs
+
+
 SELECT_OPS = {"<": A.PAC_SEL_LT, "<=": A.PAC_SEL_LE, "==": A.PAC_SEL_EQ, "!=": A.PAC_SEL_NE, ">": A.PAC_SEL_GT,
               ">=": A.PAC_SEL_GE}
 

@@ -7,6 +7,7 @@
     python -m paper_2603_15023_amd.bench_workloads nested [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads join   [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads ratio  [--reps 3] [--seeds 200]
+    python -m paper_2603_15023_amd.bench_workloads release [--reps 3]
 
 zipf:  100M rows, 2M PU keys per row, group keys Zipf(1.1) over 1M ranks
        (HBM hash table), SUM int64 + COUNT, m = 64.
@@ -29,6 +30,10 @@ ratio: the ratio rewrite on the 60M-row star schema: per group, the three
        timed; then, over --seeds noise seeds, the error of that release
        against noising each SUM on its own and combining the released values
        (the paper's naive form).
+release: the sequential release chain: 100 000 random cells through
+       pac_noised at m = 64 and 128 (microseconds per cell), then 16 queries of
+       20 000 cells each released one after another (pac_finalize) and in one
+       batched call (pac_finalize_batch).
 minmax: the float table's rows with 8 groups (its group column mod 8): COUNT,
        SUM, MIN and MAX of the FP64 column per world, m = 64, against the same
        query without MIN/MAX.
@@ -303,6 +308,52 @@ def ratio(args):
     ctx.close()
 
 
+def release(args):
+    from . import ReleaseRequest, cells_tensor, pac_finalize, pac_finalize_batch, pac_noised
+    from ._abi import PAC_CELL_AVG_I, PAC_CELL_COUNT, PAC_CELL_SUM_I
+    ctx = Context(0)
+    dev = torch.device("cuda")
+    g = np.random.default_rng(7)
+    for m in (64, 128):
+        n = 100_000
+        wv = torch.from_numpy(g.lognormal(10.0, 1.0, size=(n, m))).to(dev)
+        pac_noised(ctx, wv[:1000], m=m, noise_seed=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(args.reps):
+            pac_noised(ctx, wv, m=m, noise_seed=2 + r)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) * 1e6 / (args.reps * n)
+        print(json.dumps({"workload": f"release chain, {n} cells, m={m}", "us_per_cell": us}), flush=True)
+    # 16 queries x 20 000 cells (5000 groups x 4 aggregates) over random counters
+    m, G, nq = 64, 5000, 16
+    reqs = []
+    for q in range(nq):
+        cnt = torch.from_numpy(g.integers(0, 1000, size=(G, m), dtype=np.int64)).to(dev)
+        st = {"count": cnt, "isum": torch.from_numpy(g.integers(0, 10**9, size=(G, 2, m), dtype=np.int64)).to(dev),
+              "fsum": torch.empty((G, 0, m), dtype=torch.float64, device=dev), "nrows": cnt.sum(1)}
+        cells = [(gg, k, c) for gg in range(G) for k, c in ((PAC_CELL_COUNT, 0), (PAC_CELL_SUM_I, 0),
+                                                             (PAC_CELL_SUM_I, 1), (PAC_CELL_AVG_I, 0))]
+        reqs.append(ReleaseRequest(state=st, cells=cells_tensor(cells), n_cells=len(cells), noise_seed=100 + q))
+    for mode in ("one after another", "batched"):
+        times = []
+        for r in range(args.reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "batched":
+                pac_finalize_batch(ctx, reqs, m=m)
+            else:
+                for rq in reqs:
+                    pac_finalize(ctx, rq.state, rq.cells, rq.n_cells, m=m, noise_seed=rq.noise_seed)
+            torch.cuda.synchronize()
+            if r:
+                times.append((time.perf_counter() - t0) * 1e3)
+        print(json.dumps({"workload": f"{nq} queries x {reqs[0].n_cells} cells, m={m}", "mode": mode,
+                          "ms": float(np.mean(times))}), flush=True)
+    ctx.check()
+    ctx.close()
+
+
 def serve(args):
     from workloads import gen
     from .serve import ResidentStar, Server, latency_summary
@@ -321,7 +372,7 @@ def serve(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested", "join", "ratio"])
+    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested", "join", "ratio", "release"])
     ap.add_argument("--seeds", type=int, default=200)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--algo", default="auto")
@@ -330,7 +381,7 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.7)
     args = ap.parse_args(argv)
     {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested, "join": join,
-     "ratio": ratio}[args.what](args)
+     "ratio": ratio, "release": release}[args.what](args)
 
 
 if __name__ == "__main__":

@@ -14,6 +14,8 @@
 // Randomness is counter based (Philox4x32-10 keyed by the query's noise
 // seed, counter = (cell, purpose)), so every draw depends only on the seed
 // and the cell index, never on execution order.
+#include <algorithm>
+
 #include "pac_post.h"
 
 namespace pac {
@@ -53,14 +55,13 @@ struct CellMeta {
 
 constexpr int kCellChunk = 65536;
 
+// Phase 1 for cell c0 + ci of one query: its world vector into ybuf[ci],
+// its draws and flags into meta[ci].  One wavefront.
 template <int W>
-__global__ __launch_bounds__(256) void cell_vectors_kernel(DevState st, const pac_cell *__restrict__ cells,
-                                                           FinParams fp, int64_t c0, int64_t nc, double *ybuf,
-                                                           CellMeta *meta, double *out_y, uint32_t *status) {
+__device__ __forceinline__ void cell_vector(const DevState &st, const pac_cell *__restrict__ cells,
+                                            const FinParams &fp, int64_t c0, int64_t ci, double *ybuf,
+                                            CellMeta *meta, double *out_y, uint32_t *status, int lane) {
   constexpr int m = 64 * W;
-  const int lane = threadIdx.x & 63;
-  const int64_t ci = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (ci >= nc) return;
   const int64_t c = c0 + ci;
   const pac_cell cell = cells[c];
   const int64_t g = cell.group;
@@ -128,6 +129,15 @@ __global__ __launch_bounds__(256) void cell_vectors_kernel(DevState st, const pa
     const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * M_PI * u2);
     meta[ci] = CellMeta{z, flags, 0u};
   }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void cell_vectors_kernel(DevState st, const pac_cell *__restrict__ cells,
+                                                           FinParams fp, int64_t c0, int64_t nc, double *ybuf,
+                                                           CellMeta *meta, double *out_y, uint32_t *status) {
+  const int64_t ci = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (ci >= nc) return;
+  cell_vector<W>(st, cells, fp, c0, ci, ybuf, meta, out_y, status, threadIdx.x & 63);
 }
 
 // Phase 1 of pac_noised over given world vectors: as cell_vectors_kernel,
@@ -242,13 +252,16 @@ __device__ __forceinline__ void chain_load(const double *ybuf, int64_t first, in
   }
 }
 
+// Phase 2 for cells c0 .. c0 + nc - 1 of one query (one wavefront; s_y is
+// its LDS staging).  The posterior enters from `post` (the prior, or the
+// previous chunk's result) unless this is the first chunk without a prior.
 template <int W>
-__global__ __launch_bounds__(64) void release_chain_kernel(FinParams fp, int64_t c0, int64_t nc, const double *ybuf,
-                                                           const CellMeta *meta, double *out_val, uint8_t *out_null,
-                                                           uint32_t *out_flags, double *post, int first_chunk) {
+__device__ __forceinline__ void release_chain(const FinParams &fp, int64_t c0, int64_t nc, const double *ybuf,
+                                              const CellMeta *meta, double *out_val, uint8_t *out_null,
+                                              uint32_t *out_flags, double *post, int first_chunk,
+                                              double (&s_y)[2][kChainChunk][64 * W]) {
   constexpr int m = 64 * W;
-  __shared__ double s_y[2][kChainChunk][m];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   double P[W], L[W];
   const bool prior = (fp.flags & PAC_FIN_PRIOR_IN) || !first_chunk;
 #pragma unroll
@@ -378,6 +391,61 @@ __global__ __launch_bounds__(64) void release_chain_kernel(FinParams fp, int64_t
   for (int w = 0; w < W; ++w) post[lane + 64 * w] = P[w];
 }
 
+template <int W>
+__global__ __launch_bounds__(64) void release_chain_kernel(FinParams fp, int64_t c0, int64_t nc, const double *ybuf,
+                                                           const CellMeta *meta, double *out_val, uint8_t *out_null,
+                                                           uint32_t *out_flags, double *post, int first_chunk) {
+  __shared__ double s_y[2][kChainChunk][64 * W];
+  release_chain<W>(fp, c0, nc, ybuf, meta, out_val, out_null, out_flags, post, first_chunk, s_y);
+}
+
+// ---------------------------------------------------------------- batched release
+// Several queries' releases in one launch per phase: phase 1 has one grid row
+// per query, phase 2 one wavefront (workgroup) per query, so the sequential
+// chains of the batch run side by side on different CUs.  Each query's cells
+// go through the same code as a single pac_finalize, in chunks of kCellChunk
+// cells (round r covers cells [r kCellChunk, (r + 1) kCellChunk) of every
+// query), so the results are the same bit for bit.
+struct ReleaseJob {
+  DevState st;
+  const pac_cell *cells;
+  FinParams fp;
+  double *out_val;
+  uint8_t *out_null;
+  uint32_t *out_flags;
+  double *post;
+  double *out_y;
+  int64_t buf_off;  // this query's chunk of world vectors: ybuf + buf_off (doubles)
+  int64_t meta_off; // and of cell records: meta + meta_off
+};
+
+struct ReleaseBatch {
+  int32_t n;
+  ReleaseJob job[kMaxReleaseBatch];
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void cell_vectors_batch(ReleaseBatch b, int64_t c0, double *ybuf, CellMeta *meta,
+                                                          uint32_t *status) {
+  const ReleaseJob &jb = b.job[blockIdx.y];
+  const int64_t nc = min((int64_t)kCellChunk, jb.fp.n_cells - c0);
+  const int64_t ci = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (ci >= nc) return;
+  cell_vector<W>(jb.st, jb.cells, jb.fp, c0, ci, ybuf + jb.buf_off, meta + jb.meta_off, jb.out_y, status,
+                 threadIdx.x & 63);
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void release_chain_batch(ReleaseBatch b, int64_t c0, const double *ybuf,
+                                                          const CellMeta *meta) {
+  __shared__ double s_y[2][kChainChunk][64 * W];
+  const ReleaseJob &jb = b.job[blockIdx.x];
+  const int64_t nc = min((int64_t)kCellChunk, jb.fp.n_cells - c0);
+  if (nc < 0 || (nc == 0 && c0 > 0)) return;  // this query's cells ended in an earlier round
+  release_chain<W>(jb.fp, c0, nc, ybuf + jb.buf_off, meta + jb.meta_off, jb.out_val, jb.out_null, jb.out_flags,
+                   jb.post, c0 == 0 ? 1 : 0, s_y);
+}
+
 // Probabilistic filter (Sec. 3.2): one wave per group; lane j tests world j
 // (NaN: not true), the popcount of the ballot over m gives p_g, and the
 // group's coin (Philox at counter (g, filter)) keeps it with probability p_g.
@@ -461,6 +529,51 @@ hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_c
       hipLaunchKernelGGL(release_chain_kernel<2>, dim3(1), dim3(64), 0, env.stream, fp, c0, nc, ybuf, meta, out_val,
                          out_is_null, out_flags, posterior, c0 == 0 ? 1 : 0);
     e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t finalize_batch_scratch_bytes(int m, const int64_t *n_cells, int n) {
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) total += finalize_scratch_bytes(m, n_cells[i]) + 256;
+  return total;
+}
+
+hipError_t launch_finalize_batch(const LaunchEnv &env, int m, const ReleaseInput *in, int n, void *scratch) {
+  if (n <= 0) return hipSuccess;
+  if (n > kMaxReleaseBatch) return hipErrorInvalidValue;
+  ReleaseBatch b{};
+  b.n = n;
+  int64_t max_cells = 0, ybuf_total = 0, meta_total = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t chunk = in[i].fp.n_cells < kCellChunk ? in[i].fp.n_cells : kCellChunk;
+    b.job[i] = ReleaseJob{in[i].st,   in[i].cells,     in[i].fp,   in[i].out_val, in[i].out_null,
+                          in[i].out_flags, in[i].post, in[i].out_y, ybuf_total, meta_total};
+    ybuf_total += chunk * m;
+    meta_total += chunk;
+    max_cells = std::max(max_cells, in[i].fp.n_cells);
+  }
+  double *ybuf = (double *)scratch;
+  CellMeta *meta = (CellMeta *)(((uintptr_t)(ybuf + ybuf_total) + 255) & ~(uintptr_t)255);
+  const int64_t rounds = max_cells == 0 ? 1 : (max_cells + kCellChunk - 1) / kCellChunk;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t c0 = r * kCellChunk;
+    const int64_t nc = std::min<int64_t>(kCellChunk, max_cells - c0);
+    if (nc > 0) {
+      const dim3 grid((unsigned)((nc + 3) / 4), (unsigned)n);
+      if (m == 64)
+        hipLaunchKernelGGL(cell_vectors_batch<1>, grid, dim3(256), 0, env.stream, b, c0, ybuf, meta, env.status);
+      else
+        hipLaunchKernelGGL(cell_vectors_batch<2>, grid, dim3(256), 0, env.stream, b, c0, ybuf, meta, env.status);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (m == 64)
+      hipLaunchKernelGGL(release_chain_batch<1>, dim3((unsigned)n), dim3(64), 0, env.stream, b, c0, ybuf, meta);
+    else
+      hipLaunchKernelGGL(release_chain_batch<2>, dim3((unsigned)n), dim3(64), 0, env.stream, b, c0, ybuf, meta);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

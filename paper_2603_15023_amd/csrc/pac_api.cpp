@@ -594,6 +594,40 @@ int pac_finalize(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, 
   return PAC_OK;
 }
 
+int pac_finalize_batch(pac_ctx *ctx, void *stream, int m, const pac_release_job *jobs, int n_jobs) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(PAC_ERR_INVALID, "bad job array");
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  for (int j0 = 0; j0 < n_jobs; j0 += PAC_MAX_RELEASE_BATCH) {
+    const int n = std::min(PAC_MAX_RELEASE_BATCH, n_jobs - j0);
+    pac::ReleaseInput in[PAC_MAX_RELEASE_BATCH];
+    int64_t ncells[PAC_MAX_RELEASE_BATCH];
+    for (int i = 0; i < n; ++i) {
+      const pac_release_job &jb = jobs[j0 + i];
+      const int rc = finalize_args(ctx, &jb.state, m, jb.n_groups, jb.n_int, jb.n_float, jb.cells, jb.n_cells,
+                                   &jb.params, jb.out_val, jb.out_is_null, jb.out_flags, jb.posterior, &in[i].st,
+                                   &in[i].fp);
+      if (rc != PAC_OK) {
+        std::string msg = g_err;
+        return fail(rc, "job %d: %s", j0 + i, msg.c_str());
+      }
+      in[i].cells = jb.cells;
+      in[i].out_val = jb.out_val;
+      in[i].out_null = jb.out_is_null;
+      in[i].out_flags = jb.out_flags;
+      in[i].post = jb.posterior;
+      in[i].out_y = jb.out_y;
+      ncells[i] = jb.n_cells;
+    }
+    const int rc = ensure_scratch(ctx, pac::finalize_batch_scratch_bytes(m, ncells, n));
+    if (rc != PAC_OK) return rc;
+    const hipError_t e = pac::launch_finalize_batch(env, m, in, n, ctx->scratch);
+    if (e != hipSuccess) return hip_fail(e, "batched release launch");
+  }
+  return PAC_OK;
+}
+
 int pac_finalize_noalloc(pac_ctx *ctx, void *stream, const pac_agg_state *state, int m, int64_t n_groups, int n_int,
                          int n_float, const pac_cell *cells, int64_t n_cells, const pac_finalize_params *params,
                          double *out_val, uint8_t *out_is_null, uint32_t *out_flags, double *posterior,

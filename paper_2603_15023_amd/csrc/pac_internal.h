@@ -292,4 +292,19 @@ hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_c
                            double *out_y, void *scratch);
 size_t finalize_scratch_bytes(int m, int64_t n_cells);
 
+// One query of a batched release (pac_finalize_batch).
+constexpr int kMaxReleaseBatch = PAC_MAX_RELEASE_BATCH;
+struct ReleaseInput {
+  DevState st;
+  const pac_cell *cells;
+  FinParams fp;
+  double *out_val;
+  uint8_t *out_null;
+  uint32_t *out_flags;
+  double *post;
+  double *out_y;
+};
+size_t finalize_batch_scratch_bytes(int m, const int64_t *n_cells, int n);
+hipError_t launch_finalize_batch(const LaunchEnv &env, int m, const ReleaseInput *in, int n, void *scratch);
+
 }  // namespace pac
