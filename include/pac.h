@@ -177,9 +177,23 @@ typedef struct {
 int pac_group_aggregate(pac_ctx *ctx, void *stream, const pac_agg_input *in, int m, uint64_t query_key,
                         uint32_t algo, uint32_t flags, pac_agg_state *inout);
 
-/* Several independent queries in one call: query q reads in[q] with
- * query_keys[q] and accumulates into states[q].  Work of all queries is
- * enqueued back to back on one stream with no host synchronisation. */
+/* Several queries in one call (Sec. 4.2: each query is one pass that fills
+ * its per-world counters; queries over the same table share the rows and the
+ * FK path to the PU): query q reads in[q] with query_keys[q] and accumulates
+ * into states[q], with the same results as pac_group_aggregate.
+ * With algo == PAC_ALGO_AUTO, the queries that scan the same rows along the
+ * same links (equal n_rows, n_links, links and link_len), group by dense
+ * columns, have at most 4 int and 2 float columns and no MIN/MAX, and whose
+ * per-world counters fit together in the kernel's LDS (96 KB per launch,
+ * G x ((1 + columns) x m + 1) x 8 bytes per query) run in one persistent
+ * launch of up to PAC_MAX_AGG_BATCH queries: a shared scan that follows each
+ * row's FK chain once and then applies every query's filter, group, PU words
+ * (gathered, or the fused keyed hash) and adds.  Float sums of that launch
+ * use fp64 atomics, so their rounding (not their value within 1e-12) depends
+ * on the order of the adds.  The other queries, and every query under an
+ * explicit algo, run one after another as in pac_group_aggregate.  Everything
+ * is enqueued on one stream with no host synchronisation. */
+#define PAC_MAX_AGG_BATCH 16
 int pac_group_aggregate_batch(pac_ctx *ctx, void *stream, const pac_agg_input *in, const uint64_t *query_keys,
                               int n_queries, int m, uint32_t algo, uint32_t flags, pac_agg_state *states);
 

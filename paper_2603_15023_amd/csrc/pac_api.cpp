@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "pac_internal.h"
 #include "pac_join.h"
@@ -254,6 +255,24 @@ uint32_t choose_algo(const pac::DevInput &d, const pac::DevState &ds) {
   return PAC_ALGO_PLAIN;
 }
 
+// PAC_AGG_INIT: every state array cleared (fill kernels, no memset, so the
+// work can be captured in a graph); the sparse table emptied.
+int init_state(const pac::LaunchEnv &env, const pac::DevInput &d, const pac::DevState &ds) {
+  const int64_t G = d.n_groups, m = d.m;
+  hipError_t e = pac::launch_fill_i64(env, ds.count, G * m, 0);
+  if (e == hipSuccess && ds.isum) e = pac::launch_fill_i64(env, ds.isum, G * d.n_icols * m, 0);
+  if (e == hipSuccess && ds.fsum) e = pac::launch_fill_f64(env, ds.fsum, G * d.n_fcols * m, 0.0);
+  if (e == hipSuccess) e = pac::launch_fill_i64(env, ds.nrows, G, 0);
+  if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.slot_keys, G, PAC_EMPTY_KEY);
+  if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.n_used, 1, 0);
+  if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imin, G * d.n_icols * m, INT64_MAX);
+  if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imax, G * d.n_icols * m, INT64_MIN);
+  if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmin, G * d.n_fcols * m, INFINITY);
+  if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmax, G * d.n_fcols * m, -INFINITY);
+  if (e != hipSuccess) return hip_fail(e, "state init");
+  return PAC_OK;
+}
+
 int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, uint64_t qk, uint32_t algo,
             uint32_t flags, pac_agg_state *st) {
   pac::DevInput d;
@@ -263,17 +282,8 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
   pac::LaunchEnv env{stream, ctx->n_cu, ctx->d_status};
   const int64_t G = d.n_groups;
   if (flags & PAC_AGG_INIT) {
-    hipError_t e = pac::launch_fill_i64(env, ds.count, G * m, 0);
-    if (e == hipSuccess && ds.isum) e = pac::launch_fill_i64(env, ds.isum, G * d.n_icols * m, 0);
-    if (e == hipSuccess && ds.fsum) e = pac::launch_fill_f64(env, ds.fsum, G * d.n_fcols * m, 0.0);
-    if (e == hipSuccess) e = pac::launch_fill_i64(env, ds.nrows, G, 0);
-    if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.slot_keys, G, PAC_EMPTY_KEY);
-    if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.n_used, 1, 0);
-    if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imin, G * d.n_icols * m, INT64_MAX);
-    if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imax, G * d.n_icols * m, INT64_MIN);
-    if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmin, G * d.n_fcols * m, INFINITY);
-    if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmax, G * d.n_fcols * m, -INFINITY);
-    if (e != hipSuccess) return hip_fail(e, "state init");
+    rc = init_state(env, d, ds);
+    if (rc != PAC_OK) return rc;
   }
   if (d.n_rows == 0) return PAC_OK;
   if (algo == PAC_ALGO_AUTO) algo = choose_algo(d, ds);
@@ -432,8 +442,61 @@ int pac_group_aggregate_batch(pac_ctx *ctx, void *stream, const pac_agg_input *i
   if (n_queries > 0 && (!in || !query_keys || !states)) return fail(PAC_ERR_INVALID, "null batch arrays");
   if (flags & ~PAC_AGG_INIT) return fail(PAC_ERR_INVALID, "unknown aggregate flags 0x%x", flags);
   DeviceGuard guard(ctx->device);
+  const hipStream_t st = (hipStream_t)stream;
+  std::vector<char> shared(n_queries, 0);
+  if (algo == PAC_ALGO_AUTO) {
+    // validate every query first: nothing is enqueued for a batch with a bad query
+    std::vector<pac::DevInput> d(n_queries);
+    std::vector<pac::DevState> ds(n_queries);
+    for (int q = 0; q < n_queries; ++q) {
+      const int rc = plan_input(&in[q], m, query_keys[q], &states[q], &d[q], &ds[q]);
+      if (rc != PAC_OK) {
+        std::string msg = g_err;
+        return fail(rc, "query %d: %s", q, msg.c_str());
+      }
+    }
+    // greedy packing of the queries that can share a scan: same rows as the
+    // pack's first query, counters within the LDS budget, at most
+    // PAC_MAX_AGG_BATCH per launch
+    pac::LaunchEnv env{st, ctx->n_cu, ctx->d_status};
+    std::vector<int> pending;
+    for (int q = 0; q < n_queries; ++q)
+      if (d[q].n_rows > 0 && pac::batch_supported(d[q], ds[q])) pending.push_back(q);
+    while (pending.size() >= 2) {
+      std::vector<int> pack{pending[0]}, rest;
+      size_t bytes = pac::batch_counter_bytes(d[pending[0]]);
+      for (size_t i = 1; i < pending.size(); ++i) {
+        const int q = pending[i];
+        const size_t b = pac::batch_counter_bytes(d[q]);
+        if ((int)pack.size() < PAC_MAX_AGG_BATCH && pac::batch_same_rows(d[pack[0]], d[q]) &&
+            bytes + b <= pac::batch_lds_budget()) {
+          pack.push_back(q);
+          bytes += b;
+        } else {
+          rest.push_back(q);
+        }
+      }
+      pending.swap(rest);
+      if (pack.size() < 2) continue;  // alone: the single-query forms below
+      pac::DevInput pin[PAC_MAX_AGG_BATCH];
+      pac::DevState pst[PAC_MAX_AGG_BATCH];
+      for (size_t i = 0; i < pack.size(); ++i) {
+        const int q = pack[i];
+        pin[i] = d[q];
+        pst[i] = ds[q];
+        if (flags & PAC_AGG_INIT) {
+          const int rc = init_state(env, d[q], ds[q]);
+          if (rc != PAC_OK) return rc;
+        }
+        shared[q] = 1;
+      }
+      const hipError_t e = pac::launch_agg_batch(env, pin, pst, (int)pack.size());
+      if (e != hipSuccess) return hip_fail(e, "batched aggregate launch");
+    }
+  }
   for (int q = 0; q < n_queries; ++q) {
-    const int rc = run_one(ctx, (hipStream_t)stream, &in[q], m, query_keys[q], algo, flags, &states[q]);
+    if (shared[q]) continue;
+    const int rc = run_one(ctx, st, &in[q], m, query_keys[q], algo, flags, &states[q]);
     if (rc != PAC_OK) {
       std::string msg = g_err;
       return fail(rc, "query %d: %s", q, msg.c_str());

@@ -292,6 +292,14 @@ hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_c
                            double *out_y, void *scratch);
 size_t finalize_scratch_bytes(int m, int64_t n_cells);
 
+// Shared-scan aggregation of several queries in one launch (pac_group_aggregate_batch).
+constexpr int kMaxAggBatch = PAC_MAX_AGG_BATCH;
+bool batch_supported(const DevInput &in, const DevState &st);
+bool batch_same_rows(const DevInput &a, const DevInput &b);
+size_t batch_counter_bytes(const DevInput &in);
+size_t batch_lds_budget();
+hipError_t launch_agg_batch(const LaunchEnv &env, const DevInput *in, const DevState *st, int n);
+
 // One query of a batched release (pac_finalize_batch).
 constexpr int kMaxReleaseBatch = PAC_MAX_RELEASE_BATCH;
 struct ReleaseInput {
