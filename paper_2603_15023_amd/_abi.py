@@ -77,6 +77,7 @@ class ReleaseJob(C.Structure):
 
 
 PAC_MAX_RELEASE_BATCH = 16
+PAC_MAX_AGG_BATCH = 16
 
 EXPORTS = {
     "pac_ctx_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),

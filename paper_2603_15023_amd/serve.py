@@ -6,13 +6,18 @@ SUM / AVG over int64 or float64 columns, its own query key and noise seed) is
 one hash (a1), one aggregation (a2-a6) and one release (a7) through the C ABI.
 
 The server keeps a fixed number of slots.  Each slot owns a library context
-(scratch and status word), a HIP stream and a PU-word buffer, so the queries
-of different slots run concurrently on the device.  Queries wait in arrival
+(scratch and status word), a HIP stream and a PU-word buffer, so the work of
+different slots runs concurrently on the device.  Queries wait in arrival
 order; the head of the queue is admitted as soon as a slot is free and its
 counters fit in the counter pool (admission by counter memory), so queries
 that arrive while others are on the GPU join as resources free up instead of
-waiting for a batch to drain.  Completion is detected by polling events; the
-latency of a query is completion minus arrival on the host clock.
+waiting for a batch to drain.  When the head's counters are small enough for
+the shared-scan launch, the small queries waiting behind it join it in the
+same slot (up to PAC_MAX_AGG_BATCH, as long as their counters fit together):
+one pac_group_aggregate_batch call (one scan of the table for all of them, PU
+words hashed in the kernel) and one pac_finalize_batch call (their release
+chains side by side).  Completion is detected by polling events; the latency
+of a query is completion minus arrival on the host clock.
 """
 from __future__ import annotations
 
@@ -25,7 +30,8 @@ import numpy as np
 import torch
 
 from . import _abi as A
-from .api import AggSpec, Context, new_state, pac_finalize, pac_group_aggregate, pac_hash_mask
+from .api import (AggSpec, Context, ReleaseRequest, new_state, pac_finalize, pac_finalize_batch,
+                  pac_group_aggregate, pac_group_aggregate_batch, pac_hash_mask)
 
 CELL_DTYPE = np.dtype([("group", "<i8"), ("kind", "<i4"), ("col", "<i4")])
 INT_COLS = ("v1", "v2", "v3")
@@ -95,12 +101,46 @@ def counter_bytes(q, m: int = 64) -> int:
     return q.n_groups * ((1 + len(ints) + len(flts)) * m + 1) * 8
 
 
-def query_spec(table: ResidentStar, q, masks: torch.Tensor) -> AggSpec:
+def query_spec(table: ResidentStar, q, masks: Optional[torch.Tensor]) -> AggSpec:
+    """The query's aggregation input: PU words from ``masks`` (this query's pac_hash_mask of the PU keys),
+    or, with masks None, the PU keys hashed in the kernel with the query key."""
     ints, flts = query_columns(q)
-    return AggSpec(n_rows=table.n_rows, masks=masks, links=[table.f_order, table.o_pu], gcols=[table.gsrc],
+    spec = AggSpec(n_rows=table.n_rows, masks=masks, links=[table.f_order, table.o_pu], gcols=[table.gsrc],
                    gcards=[table.gsrc_card], group_mod=q.n_groups, n_groups=q.n_groups, filter_col=table.sel,
                    filter_lt=q.filter_lt, cols=[table.cols[c] for c in ints + flts],
                    stats=[table.stats[c] for c in ints] + [(0, 0)] * len(flts))
+    if masks is None:
+        spec.pu_keys = table.pu_key
+    return spec
+
+
+# the shared-scan launch's LDS budget and query count (include/pac.h, pac_group_aggregate_batch)
+BATCH_LDS_BYTES = 96 * 1024
+MAX_BATCH = A.PAC_MAX_AGG_BATCH
+
+
+def shared_scan_bytes(q, m: int = 64) -> int:
+    """LDS bytes of the query's counters in the shared-scan launch."""
+    ints, flts = query_columns(q)
+    return q.n_groups * ((1 + len(ints) + len(flts)) * m + 1) * 8
+
+
+def pick_batch(queries: Sequence, waiting: Sequence[int], m: int = 64, max_batch: int = MAX_BATCH) -> List[int]:
+    """The queries admitted together with the head of the queue (host logic): the head alone unless its
+    counters fit the shared-scan launch; then, in arrival order, every waiting query whose counters still
+    fit, up to max_batch."""
+    head = waiting[0]
+    if max_batch < 2 or shared_scan_bytes(queries[head], m) > BATCH_LDS_BYTES:
+        return [head]
+    out, used = [head], shared_scan_bytes(queries[head], m)
+    for i in list(waiting)[1:]:
+        if len(out) >= max_batch:
+            break
+        b = shared_scan_bytes(queries[i], m)
+        if used + b <= BATCH_LDS_BYTES:
+            out.append(i)
+            used += b
+    return out
 
 
 class Admission:
@@ -134,6 +174,7 @@ class QueryResult:
     arrival: float = 0.0
     admitted: float = 0.0
     done: float = 0.0
+    batch: int = 1  # queries launched together with this one (1: alone in its slot)
 
     @property
     def latency(self) -> float:
@@ -181,10 +222,11 @@ class Server:
     """Continuous-batching query server over one resident table on one GPU."""
 
     def __init__(self, table: ResidentStar, n_slots: int = 4, pool_bytes: int = 8 << 30, m: int = 64,
-                 mi_budget: float = 1.0 / 128, device_index: int = 0, max_cells: int = 300_000):
+                 mi_budget: float = 1.0 / 128, device_index: int = 0, max_cells: int = 300_000,
+                 max_batch: int = MAX_BATCH):
         self.table, self.m, self.budget = table, m, mi_budget
         self.slots = [_Slot(device_index, table.pu_key.shape[0], m, max_cells, table.n_rows) for _ in range(n_slots)]
-        self.n_slots, self.pool_bytes = n_slots, pool_bytes
+        self.n_slots, self.pool_bytes, self.max_batch = n_slots, pool_bytes, max_batch
 
     def _launch(self, slot: _Slot, q):
         s = slot.stream
@@ -205,7 +247,36 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(s)
         # device tensors stay referenced until completion
-        return ev, host, (state, cells_d, vals, nulls, flags)
+        return ev, [host], (state, cells_d, vals, nulls, flags)
+
+    def _launch_batch(self, slot: _Slot, qs: Sequence):
+        """Several small queries in one slot: one shared-scan aggregation, one batched release."""
+        s = slot.stream
+        with torch.cuda.stream(s):
+            specs = [query_spec(self.table, q, None) for q in qs]
+            states = [new_state(sp, self.m) for sp in specs]
+            pac_group_aggregate_batch(slot.ctx, specs, states, [q.query_key for q in qs], m=self.m, stream=s)
+            reqs, keep = [], []
+            for q, st in zip(qs, states):
+                n_cells = q.n_groups * len(q.aggs)
+                cells_d = device_cells(q, slot.masks.device)
+                reqs.append(ReleaseRequest(state=st, cells=cells_d, n_cells=n_cells, mi_budget=self.budget,
+                                           noise_seed=q.noise_seed))
+                keep.append(cells_d)
+            outs = pac_finalize_batch(slot.ctx, reqs, m=self.m, stream=s)
+            hosts, off = [], 0
+            for r, (vals, nulls, flags, _, _) in zip(reqs, outs):
+                n = r.n_cells
+                if off + n > slot.max_cells:
+                    raise ValueError(f"batch releases more than the slot's {slot.max_cells} cells")
+                host = (slot.h_vals[off:off + n], slot.h_null[off:off + n], slot.h_flags[off:off + n])
+                for h, x in zip(host, (vals, nulls, flags)):
+                    h.copy_(x, non_blocking=True)
+                hosts.append(host)
+                off += n
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ev, hosts, (states, keep, outs)
 
     def run(self, queries: Sequence, arrivals: Optional[Sequence[float]] = None,
             poll_sleep: float = 0.0) -> List[QueryResult]:
@@ -224,22 +295,28 @@ class Server:
                 waiting.append(int(order[nxt]))
                 nxt += 1
             while waiting:  # admit from the head while a slot and counter memory are free
-                i = waiting[0]
-                need = counter_bytes(queries[i], self.m)
+                group = pick_batch(queries, waiting, self.m, self.max_batch)
+                need = sum(counter_bytes(queries[i], self.m) for i in group)
                 slot_id = adm.try_admit(need)
                 if slot_id is None:
                     break
-                waiting.popleft()
-                ev, host, keep = self._launch(self.slots[slot_id], queries[i])
-                inflight[i] = (slot_id, need, ev, host, keep, time.perf_counter() - t0)
-            done = [i for i, rec in inflight.items() if rec[2].query()]
-            for i in done:
-                slot_id, need, ev, host, keep, t_adm = inflight.pop(i)
+                for i in group:
+                    waiting.remove(i)
+                if len(group) == 1:
+                    ev, hosts, keep = self._launch(self.slots[slot_id], queries[group[0]])
+                else:
+                    ev, hosts, keep = self._launch_batch(self.slots[slot_id], [queries[i] for i in group])
+                inflight[group[0]] = (slot_id, need, ev, hosts, keep, time.perf_counter() - t0, group)
+            done = [k for k, rec in inflight.items() if rec[2].query()]
+            for k in done:
+                slot_id, need, ev, hosts, keep, t_adm, group = inflight.pop(k)
                 t_done = time.perf_counter() - t0
                 st = self.slots[slot_id].ctx.status(self.slots[slot_id].stream)
-                results.append(QueryResult(qid=queries[i].qid, values=host[0].numpy().copy(),
-                                           is_null=host[1].numpy().copy(), flags=host[2].numpy().copy(),
-                                           status=st, arrival=float(arrivals[i]), admitted=t_adm, done=t_done))
+                for i, host in zip(group, hosts):
+                    results.append(QueryResult(qid=queries[i].qid, values=host[0].numpy().copy(),
+                                               is_null=host[1].numpy().copy(), flags=host[2].numpy().copy(),
+                                               status=st, arrival=float(arrivals[i]), admitted=t_adm, done=t_done,
+                                               batch=len(group)))
                 adm.release(slot_id, need)
             if not done and poll_sleep:
                 time.sleep(poll_sleep)

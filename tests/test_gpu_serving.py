@@ -78,9 +78,13 @@ def test_serving_results_same_alone_and_in_mix(torch_mod):
         alone[q.qid] = r
     srv1.close()
     srv = Server(table, n_slots=4, pool_bytes=1 << 30)
-    mix = srv.run(qs)  # all arrive at once: four in flight at a time
+    mix = srv.run(qs)  # all arrive at once: four slots in flight, small queries batched in a slot
     srv.close()
     assert sorted(r.qid for r in mix) == sorted(q.qid for q in qs)
+    # the work overlapped on the device: some query was admitted while another one was still in flight, and
+    # some small queries shared one scan and one release launch
+    assert any(s.admitted < r.admitted < s.done for r in mix for s in mix if r.qid != s.qid)
+    assert any(r.batch > 1 for r in mix)
     for r in mix:
         a = alone[r.qid]
         assert r.status == 0 and a.status == 0

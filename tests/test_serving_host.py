@@ -44,3 +44,21 @@ def test_served_workload_shape():
     # log-uniform: about half of the queries below the geometric middle
     assert 0.4 < np.mean(np.log10(G) < 2.5) < 0.6
     assert all(1 <= len(q.aggs) <= 3 for q in qs)
+
+
+def test_pick_batch_keeps_the_head_and_fills_the_shared_launch():
+    from paper_2603_15023_amd.serve import BATCH_LDS_BYTES, pick_batch, shared_scan_bytes
+
+    def q(i, G, aggs=(("count", None),)):
+        return gen.ServedQuery(qid=i, filter_lt=1 << 30, n_groups=G, aggs=list(aggs), query_key=i, noise_seed=i,
+                               gap=1.0)
+    big = q(0, 50_000)
+    small = [q(i, 3) for i in range(1, 30)]
+    qs = [big] + small
+    assert pick_batch(qs, [0, 1, 2]) == [0]            # a head too large for the shared launch goes alone
+    got = pick_batch(qs, list(range(1, 30)))
+    assert got[0] == 1 and got == list(range(1, 17))   # the head, then arrival order, at most 16
+    mid = [q(100 + i, 40, [("sum", "v1"), ("avg", "vf")]) for i in range(5)]  # 40 * 193 * 8 bytes each
+    got = pick_batch(mid, list(range(5)))
+    assert sum(shared_scan_bytes(mid[i]) for i in got) <= BATCH_LDS_BYTES < sum(shared_scan_bytes(x) for x in mid)
+    assert pick_batch(small, list(range(5)), max_batch=1) == [0]
