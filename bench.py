@@ -229,6 +229,8 @@ def main():
 
     ctx.check()
     log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
+    graph = graph_measurement(args, P, ctx, pu_key, K, masks, spec, state, cells_t, len(cells), seed) \
+        if args.algo != "mfma_kv" else None
 
     # the other GPU forms on the same inputs (same counters; checked in the tests): the plain per-bit form, the
     # generic matrix-core kernel, the star kernel with the orders carrying their PU key
@@ -322,6 +324,7 @@ def main():
         "step_latency_ms": ({"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                              "max": float(np.max(step_ms))} if step_ms else None),
         "aggregate_rows_per_s": n / (agg_ms * 1e-3),
+        "graph": graph,
         "forms": {k: dict(v, aggregate_rows_per_s=n / (v["aggregate_ms"] * 1e-3),
                           alg_bytes=alg_kv if k == "mfma_kv" else alg_bytes,
                           hbm_frac=round((alg_kv if k == "mfma_kv" else alg_bytes) / (v["aggregate_ms"] * 1e-3)
@@ -336,6 +339,46 @@ def main():
     ctx_prep.close()
     ctx_rel.close()
     ctx.close()
+
+
+def graph_measurement(args, P, ctx, pu_key, K, masks, spec, state, cells_t, n_cells, seed):
+    """The step captured once as a HIP graph (hash, counter clearing by fill kernels, aggregation, release on
+    the library's fixed memory) and replayed: launch overhead off the host; the same outputs as eagerly."""
+    import torch
+    dev = masks.device
+    out = (torch.empty(n_cells, dtype=torch.float64, device=dev), torch.empty(n_cells, dtype=torch.uint8, device=dev),
+           torch.empty(n_cells, dtype=torch.int32, device=dev), torch.empty(64, dtype=torch.float64, device=dev), None)
+
+    def step():
+        P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+        P.pac_group_aggregate(ctx, spec, state, m=64, query_key=K, algo=args.algo, init=True)
+        P.pac_finalize(ctx, state, cells_t, n_cells, m=64, mi_budget=1.0 / 128, noise_seed=seed, out=out,
+                       no_alloc=True)
+
+    step()
+    torch.cuda.synchronize()
+    want = {k: v.clone() for k, v in state.items()}
+    want_vals = out[0].clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    same = all(torch.equal(state[k], want[k]) for k in want) and torch.equal(out[0], want_vals)
+    log(f"graph replay: {ms:.3f} ms/step, same outputs {same}")
+    ctx.check()
+    return {"ms_per_step": ms, "rows_per_s": spec.n_rows / (ms * 1e-3), "same_outputs": bool(same),
+            "captured": "hash + counter clearing + aggregation + release (pac_finalize_noalloc), one stream"}
 
 
 def stream_read_gbs(dev, gib=2.0, reps=10):
