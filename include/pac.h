@@ -169,6 +169,13 @@ typedef struct {
                                  plain form with every counter in registers; up to 3 columns (2 with MIN/MAX) */
 #define PAC_ALGO_MFMA_GENERIC 6u /* the int8 matrix-core form's generic kernel even where the kernel specialised
                                    for the star-schema shape applies (the two compute the same counters) */
+#define PAC_ALGO_MFMA_BF16 7u /* an approximation, never chosen by AUTO: one float column (COUNT + SUM) over at most
+                                64 dense groups on the bf16 matrix cores.  Each value is rounded to fp32 and split
+                                into three bf16 terms (exact), rows are sorted by group in LDS, and the products are
+                                accumulated in fp32 and flushed to the fp64 state every 32768 rows of a workgroup.
+                                COUNT and nrows are exact; a float sum differs from the fp64 one by the fp32 rounding
+                                of the inputs plus the fp32 accumulation between flushes (measured relative error
+                                per cell and its bound: see the design notes) */
 #define PAC_AGG_INIT 1u     /* clear the state (and the sparse table) before aggregating */
 
 /* m in {64, 128}; query_key is used by the fused hash.  Returns

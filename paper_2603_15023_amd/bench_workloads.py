@@ -111,6 +111,25 @@ def float_(args):
         print(json.dumps({"workload": "float 200M rows, 64 groups: FP32 input vs FP64 input", "m": m,
                           "cells": int(ok.sum()), "rel_err_max": float(rel.max()),
                           "rel_err_median": float(np.median(rel))}), flush=True)
+        # the bf16 matrix-core form (approximate): time, and its error per cell against the FP64 sums, split into
+        # the input rounding (the FP32 copy summed in FP64) and the accumulation (bf16 form on the FP32 copy against
+        # the FP64 sum of the same FP32 values)
+        for name in ("v64", "v32"):
+            sp = AggSpec(n_rows=t.n_rows, pu_keys=pu, gcols=[g], gcards=[64], n_groups=64, cols=[cols[name]])
+            sb = new_state(sp, m)
+            ms = _time(ctx, sp, sb, m, gen.query_key(4), "mfma_bf16", args.reps)
+            alg = t.n_rows * (8 + 1 + cols[name].element_size())
+            fb = sb["fsum"].cpu().numpy()[:, 0, :]
+            same_count = bool(np.array_equal(sb["count"].cpu().numpy(), st["count"].cpu().numpy()))
+            ref = fs[:, 1, :] if name == "v32" else fs[:, 0, :]
+            acc = np.abs(fb - ref)[ok] / np.abs(ref)[ok]
+            tot = np.abs(fb - fs[:, 0, :])[ok] / np.abs(fs[:, 0, :])[ok]
+            print(json.dumps({"workload": f"float 200M rows, 64 groups, {name}", "m": m, "algo": "mfma_bf16",
+                              "ms": ms, "alg_bytes": alg, "hbm_frac": alg / (ms * 1e-3) / 8e12,
+                              "count_exact": same_count,
+                              "rel_err_vs_fp64": {"max": float(tot.max()), "median": float(np.median(tot))},
+                              "rel_err_accumulation": {"max": float(acc.max()), "median": float(np.median(acc))}}),
+                  flush=True)
     ctx.close()
 
 

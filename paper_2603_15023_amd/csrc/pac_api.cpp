@@ -330,6 +330,12 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
       e = pac::launch_agg_reg(env, d, ds, ctx->scratch, ctx->scratch_bytes);
       break;
     }
+    case PAC_ALGO_MFMA_BF16:
+      if (!pac::fmma_supported(d, ds))
+        return fail(PAC_ERR_UNSUPPORTED, "bf16 matrix-core form needs one float column, no int columns, no MIN/MAX "
+                                         "and at most 64 dense groups");
+      e = pac::launch_agg_fmma(env, d, ds);
+      break;
     default:
       return fail(PAC_ERR_INVALID, "unknown algorithm %u", algo);
   }

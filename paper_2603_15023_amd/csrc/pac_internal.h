@@ -292,6 +292,10 @@ hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_c
                            double *out_y, void *scratch);
 size_t finalize_scratch_bytes(int m, int64_t n_cells);
 
+// One float column on the bf16 matrix cores (approximate form).
+bool fmma_supported(const DevInput &in, const DevState &st);
+hipError_t launch_agg_fmma(const LaunchEnv &env, const DevInput &in, const DevState &st);
+
 // Shared-scan aggregation of several queries in one launch (pac_group_aggregate_batch).
 constexpr int kMaxAggBatch = PAC_MAX_AGG_BATCH;
 bool batch_supported(const DevInput &in, const DevState &st);
