@@ -204,6 +204,32 @@ int pac_group_aggregate(pac_ctx *ctx, void *stream, const pac_agg_input *in, int
 int pac_group_aggregate_batch(pac_ctx *ctx, void *stream, const pac_agg_input *in, const uint64_t *query_keys,
                               int n_queries, int m, uint32_t algo, uint32_t flags, pac_agg_state *states);
 
+/* ---- tuning: form and launch shape per input class, measured on the GPU --
+ * PAC_ALGO_AUTO picks a form by fixed rules unless the context holds a
+ * tuning table (pac_set_tuning) with an entry for the input's class; the
+ * table comes from the project's tuner (paper_2603_15023_amd/tune.py), which
+ * times every form that takes a class on synthetic inputs of it, keeps only
+ * those whose counters equal the others', and records the fastest, keyed by
+ * GPU architecture and class.  A class is the tuple of the first eight fields
+ * below; pac_tune_key fills them for an input (host only: it reads the
+ * descriptor, touches no device memory and needs no context).
+ * pac_set_tuning copies n entries into the context (n = 0 clears the table);
+ * an entry whose algo cannot run an input of its class is ignored for it. */
+typedef struct {
+  int32_t W;              /* m / 64 */
+  int32_t sparse;         /* 1: sparse group keys (hash table) */
+  int32_t gbits;          /* bit length of n_groups - 1 (0 for one group) */
+  int32_t n_int, n_float; /* value columns */
+  int32_t digits;         /* largest byte count of (max - min) over the int columns, 8 without statistics */
+  int32_t filter;         /* 1: a filter column */
+  int32_t minmax;         /* 1: the state has MIN / MAX arrays */
+  uint32_t algo;          /* PAC_ALGO_* other than AUTO */
+  int32_t blocks_per_cu;  /* matrix-core forms: workgroups per CU of the grid (0: as many as fit) */
+  int32_t scatter_wg_per_cu; /* partitioned form: scatter workgroups per CU (0: one) */
+} pac_tune_entry;
+int pac_tune_key(const pac_agg_input *in, int m, const pac_agg_state *state, pac_tune_entry *key);
+int pac_set_tuning(pac_ctx *ctx, const pac_tune_entry *entries, int n);
+
 /* ---- a7: release (Sec. 4.1 noise function pac_noised; Sec. 3.2 NULLs;
  * Sec. 5 Diversity Check; Sec. 2 adaptive composition) -------------------- */
 /* MIN / MAX cells release the world's extreme (a world without rows as 0,

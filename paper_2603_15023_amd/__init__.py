@@ -23,4 +23,5 @@ from .api import (  # noqa: F401
     pac_noised,
     pac_select_cmp,
     pac_world_values,
+    tune_key,
 )

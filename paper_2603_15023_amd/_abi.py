@@ -78,6 +78,15 @@ class ReleaseJob(C.Structure):
 
 
 PAC_MAX_RELEASE_BATCH = 16
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("W", C.c_int32), ("sparse", C.c_int32), ("gbits", C.c_int32), ("n_int", C.c_int32),
+                ("n_float", C.c_int32), ("digits", C.c_int32), ("filter", C.c_int32), ("minmax", C.c_int32),
+                ("algo", C.c_uint32), ("blocks_per_cu", C.c_int32), ("scatter_wg_per_cu", C.c_int32)]
+
+
+TUNE_KEY_FIELDS = ("W", "sparse", "gbits", "n_int", "n_float", "digits", "filter", "minmax")
 PAC_MAX_AGG_BATCH = 16
 
 EXPORTS = {
@@ -96,6 +105,8 @@ EXPORTS = {
     "pac_finalize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
                                C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pac_tune_key": (C.c_int, [C.POINTER(AggInput), C.c_int, C.POINTER(AggState), C.POINTER(TuneEntry)]),
+    "pac_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(TuneEntry), C.c_int]),
     "pac_finalize_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(ReleaseJob), C.c_int]),
     "pac_finalize_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int,
                                        C.c_int, C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p,

@@ -39,14 +39,31 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
 
 
 class Context:
-    """A pac_ctx on one device."""
+    """A pac_ctx on one device.  With ``tuning`` (the default) the tuning table measured for the device's
+    architecture (paper_2603_15023_amd/tuning/<arch>.json, written by ``python -m paper_2603_15023_amd.tune``)
+    is loaded, if there is one, and PAC_ALGO_AUTO follows it."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuning: bool = True):
         lib = A.load()
         h = C.c_void_p()
         A.check(lib.pac_ctx_create(int(device), C.byref(h)))
         self._h = h
         self.device = device
+        self.tuning_file = None
+        if tuning:
+            from .tune import load_table
+            self.tuning_file = load_table(self)
+
+    def set_tuning(self, entries: Sequence[dict]) -> None:
+        """Installs a tuning table: dicts with the class fields, "algo" (a name) and the launch shape."""
+        arr = (A.TuneEntry * max(1, len(entries)))()
+        for i, e in enumerate(entries):
+            for f in A.TUNE_KEY_FIELDS:
+                setattr(arr[i], f, int(e[f]))
+            arr[i].algo = A.ALGOS[e["algo"]]
+            arr[i].blocks_per_cu = int(e.get("blocks_per_cu", 0))
+            arr[i].scatter_wg_per_cu = int(e.get("scatter_wg_per_cu", 0))
+        A.check(A.load().pac_set_tuning(self._h, arr, len(entries)))
 
     @property
     def handle(self):
@@ -154,6 +171,18 @@ class AggSpec:
             for i, (lo, hi) in enumerate(self.stats):
                 s.col_min[i], s.col_max[i] = int(lo), int(hi)
         return s
+
+
+def tune_key(spec: AggSpec, m: int = 64, minmax: bool = False) -> Dict[str, int]:
+    """The tuning class of an aggregation input (pac_tune_key; host only)."""
+    cin = spec.to_c()
+    st = A.AggState()
+    if minmax:
+        for f in ("count", "isum", "fsum", "nrows", "slot_keys", "n_used", "imin", "imax", "fmin", "fmax"):
+            setattr(st, f, 16)
+    key = A.TuneEntry()
+    A.check(A.load().pac_tune_key(C.byref(cin), m, C.byref(st) if minmax else None, C.byref(key)))
+    return {f: int(getattr(key, f)) for f in A.TUNE_KEY_FIELDS}
 
 
 def new_state(spec: AggSpec, m: int = 64, device=None, minmax: bool = False) -> Dict[str, torch.Tensor]:

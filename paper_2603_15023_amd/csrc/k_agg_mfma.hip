@@ -545,6 +545,7 @@ static hipError_t launch_mfma_t(const LaunchEnv &env, const DevInput &in, const 
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
   if (e != hipSuccess) return e;
   per_cu = std::max(1, per_cu);
+  if (env.blocks_per_cu > 0) per_cu = std::min(per_cu, env.blocks_per_cu);
   const int64_t n_tiles = (in.n_rows + kTileRows - 1) / kTileRows;
   const int64_t want = (n_tiles + 3) / 4;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)env.n_cu * per_cu));

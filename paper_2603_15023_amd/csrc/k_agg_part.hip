@@ -67,23 +67,13 @@ struct PartPlan {
 
 // Above this many partitions the integer form scatters in two passes.
 constexpr int64_t kTwoPassParts = 1024;
-#ifndef PART_SCATTER_WG_PER_CU
-#define PART_SCATTER_WG_PER_CU 1
-#endif
-constexpr int kScatterWgPerCu = PART_SCATTER_WG_PER_CU;  // 1024-thread workgroups per CU in both passes
 
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr int kPartLdsTarget = 80 * 1024;  // two workgroups per CU
-#ifndef PART_DET_LDS_KB
-#define PART_DET_LDS_KB 40
-#endif
 // Deterministic form: four workgroups per CU (its per-record loop is latency bound).
-constexpr int kPartLdsTargetDet = PART_DET_LDS_KB * 1024;
+constexpr int kPartLdsTargetDet = 40 * 1024;
 constexpr int kPartWaves = 4;              // waves per workgroup of the aggregation (deterministic form)
-#ifndef PART_AGG_WAVES
-#define PART_AGG_WAVES 16
-#endif
-constexpr int kPartWavesNd = PART_AGG_WAVES;  // waves sharing one item's LDS counters (integer form)
+constexpr int kPartWavesNd = 16;  // waves sharing one item's LDS counters (integer form)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1178,7 +1168,8 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
       const int words = in.W + in.n_icols;  // the two-pass form has no float columns
       const size_t tlds = tile_lds_bytes(words);
       const int rpt = tile_rpt(words);
-      const dim3 sgrid(env.n_cu * kScatterWgPerCu), sblock(kTileThreads);
+      // 1024-thread scatter workgroups per CU in both passes (tuned; one by default)
+      const dim3 sgrid(env.n_cu * (env.scatter_wg_per_cu > 0 ? env.scatter_wg_per_cu : 1)), sblock(kTileThreads);
       auto two_pass = [&](auto cfn, auto sfn2) -> hipError_t {
         hipError_t err;
         if ((err = hipFuncSetAttribute((const void *)cfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) !=

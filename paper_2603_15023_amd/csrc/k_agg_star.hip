@@ -24,10 +24,7 @@ namespace pac {
 
 constexpr int kStarGM = 8;   // groups per scan (byte lookup into an 8-byte table)
 constexpr int kStarWPB = 4;  // waves per block
-#ifndef STAR_TPI
-#define STAR_TPI 1
-#endif
-constexpr int kStarTPI = STAR_TPI;  // tiles per loop iteration of a wave (loads in flight)
+constexpr int kStarTPI = 1;  // tiles per loop iteration of a wave (loads in flight)
 
 struct StarPlan {
   int32_t kv;            // 1: one link into per-order PU keys, hashed in the kernel
@@ -367,10 +364,6 @@ __device__ __forceinline__ void star_b(const uint8_t *planes, int roff, const in
   }
 }
 
-#ifndef STAR_SCHED
-#define STAR_SCHED 0
-#endif
-
 // The four K-chunks of a tile, software-pipelined: the B rows of chunk u + 1
 // are read and the A operands of chunk u + 1 built while the matrix cores
 // work on chunk u.
@@ -393,13 +386,6 @@ __device__ __forceinline__ void star_mfma(const StarStage<NGC, NI> *sg, int lane
         acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[c][mt], b, acc[mt][nt], 0, 0, 0);
     }
     if (u < 3) star_a(sg, lane, u + 1, tc, av[n]);
-#if STAR_SCHED
-#pragma unroll
-    for (int i = 0; i < 4 * NT; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);           // one MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, STAR_SCHED, 0);  // then VALU
-    }
-#endif
   }
 }
 
@@ -660,6 +646,7 @@ static hipError_t launch_star_t(const LaunchEnv &env, const DevInput &in, const 
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kStarWPB, lds);
   if (e != hipSuccess) return e;
   per_cu = std::max(1, per_cu);
+  if (env.blocks_per_cu > 0) per_cu = std::min(per_cu, env.blocks_per_cu);
   const int64_t n_tiles = (in.n_rows + kTileRows - 1) / kTileRows;
   const int64_t want = (n_tiles + kStarWPB * kStarTPI - 1) / (kStarWPB * kStarTPI);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)env.n_cu * per_cu));

@@ -21,6 +21,7 @@ struct pac_ctx {
   void *scratch;
   size_t scratch_bytes;
   void *noalloc;  // device address of this device's copy of noalloc_scratch
+  std::vector<pac_tune_entry> tuning;  // measured choices per input class (pac_set_tuning)
 };
 
 // Working memory of pac_finalize_noalloc: a fixed array in the library's code
@@ -236,6 +237,47 @@ int plan_input(const pac_agg_input *in, int m, uint64_t qk, const pac_agg_state 
   return PAC_OK;
 }
 
+// The input class of a tuning entry.
+void tune_key(const pac::DevInput &d, const pac::DevState &ds, pac_tune_entry *k) {
+  std::memset(k, 0, sizeof(*k));
+  k->W = d.W;
+  k->sparse = d.group_keys ? 1 : 0;
+  k->gbits = bit_length((uint64_t)(d.n_groups - 1));
+  k->n_int = d.n_icols;
+  k->n_float = d.n_fcols;
+  for (int c = 0; c < d.n_icols; ++c) k->digits = std::max(k->digits, (int32_t)d.icol_digits[c]);
+  k->filter = d.filter_col ? 1 : 0;
+  k->minmax = ds.minmax ? 1 : 0;
+}
+
+bool same_class(const pac_tune_entry &a, const pac_tune_entry &b) {
+  return a.W == b.W && a.sparse == b.sparse && a.gbits == b.gbits && a.n_int == b.n_int && a.n_float == b.n_float &&
+         a.digits == b.digits && a.filter == b.filter && a.minmax == b.minmax;
+}
+
+// Whether a form can run this input (the checks of run_one's dispatch).
+bool algo_runs(uint32_t algo, const pac::DevInput &d, const pac::DevState &ds) {
+  if (ds.minmax && algo != PAC_ALGO_PLAIN && algo != PAC_ALGO_REGISTER) return false;
+  switch (algo) {
+    case PAC_ALGO_PLAIN: return true;
+    case PAC_ALGO_BALLOT: return pac::ballot_supported(d);
+    case PAC_ALGO_MFMA_I8:
+    case PAC_ALGO_MFMA_GENERIC: return pac::mfma_supported(d);
+    case PAC_ALGO_PARTITION: return pac::part_supported(d);
+    case PAC_ALGO_REGISTER: return pac::reg_supported(d, ds.minmax != 0);
+    default: return false;  // the approximate bf16 form is only ever chosen explicitly
+  }
+}
+
+const pac_tune_entry *find_tuning(const pac_ctx *ctx, const pac::DevInput &d, const pac::DevState &ds) {
+  if (ctx->tuning.empty()) return nullptr;
+  pac_tune_entry k;
+  tune_key(d, ds, &k);
+  for (const pac_tune_entry &e : ctx->tuning)
+    if (same_class(e, k) && algo_runs(e.algo, d, ds)) return &e;
+  return nullptr;
+}
+
 uint32_t choose_algo(const pac::DevInput &d, const pac::DevState &ds) {
   // float columns or per-world MIN / MAX over a few groups: counters in registers
   if ((d.n_fcols > 0 || ds.minmax) && pac::reg_supported(d, ds.minmax != 0)) return PAC_ALGO_REGISTER;
@@ -286,7 +328,12 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
     if (rc != PAC_OK) return rc;
   }
   if (d.n_rows == 0) return PAC_OK;
-  if (algo == PAC_ALGO_AUTO) algo = choose_algo(d, ds);
+  const pac_tune_entry *tuned = find_tuning(ctx, d, ds);
+  if (algo == PAC_ALGO_AUTO) algo = tuned ? tuned->algo : choose_algo(d, ds);
+  if (tuned && tuned->algo == algo) {  // the launch shape measured for this class and form
+    env.blocks_per_cu = tuned->blocks_per_cu;
+    env.scatter_wg_per_cu = tuned->scatter_wg_per_cu;
+  }
   if (ds.minmax && algo != PAC_ALGO_PLAIN && algo != PAC_ALGO_REGISTER)
     return fail(PAC_ERR_UNSUPPORTED, "MIN/MAX counters need the plain or register form");
   hipError_t e = hipSuccess;
@@ -351,6 +398,36 @@ extern "C" {
 const char *pac_last_error(void) { return g_err.c_str(); }
 
 int pac_version(void) { return 1; }
+
+int pac_tune_key(const pac_agg_input *in, int m, const pac_agg_state *state, pac_tune_entry *key) {
+  if (!in || !key) return fail(PAC_ERR_INVALID, "null input or key");
+  pac::DevInput d;
+  pac::DevState ds{};
+  pac_agg_state probe{};
+  const pac_agg_state *st = state;
+  if (!st) {  // the class does not depend on the counter arrays, only on whether MIN/MAX is wanted
+    probe.count = probe.nrows = (int64_t *)16;
+    probe.isum = (int64_t *)16;
+    probe.fsum = (double *)16;
+    probe.slot_keys = probe.n_used = (int64_t *)16;
+    st = &probe;
+  }
+  const int rc = plan_input(in, m, 0, st, &d, &ds);
+  if (rc != PAC_OK) return rc;
+  tune_key(d, ds, key);
+  return PAC_OK;
+}
+
+int pac_set_tuning(pac_ctx *ctx, const pac_tune_entry *entries, int n) {
+  if (!ctx) return fail(PAC_ERR_INVALID, "null context");
+  if (n < 0 || (n > 0 && !entries)) return fail(PAC_ERR_INVALID, "bad tuning table");
+  for (int i = 0; i < n; ++i)
+    if (entries[i].algo == PAC_ALGO_AUTO || entries[i].algo > PAC_ALGO_MFMA_BF16 || entries[i].blocks_per_cu < 0 ||
+        entries[i].scatter_wg_per_cu < 0 || entries[i].scatter_wg_per_cu > 8)
+      return fail(PAC_ERR_INVALID, "tuning entry %d: bad algo or launch shape", i);
+  ctx->tuning.assign(entries, entries + n);
+  return PAC_OK;
+}
 
 int pac_ctx_create(int hip_device, pac_ctx **out) {
   if (!out) return fail(PAC_ERR_INVALID, "out is null");

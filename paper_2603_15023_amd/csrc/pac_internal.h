@@ -244,6 +244,8 @@ struct LaunchEnv {
   hipStream_t stream;
   int n_cu;
   uint32_t *status;
+  int blocks_per_cu = 0;      // matrix-core forms: workgroups per CU of the grid (0: as many as fit)
+  int scatter_wg_per_cu = 0;  // partitioned form: scatter workgroups per CU (0: one)
 };
 
 hipError_t launch_hash(const LaunchEnv &env, const int64_t *keys, int64_t n, uint64_t qk, int m, bool balanced,
