@@ -454,6 +454,18 @@ int pac_noised(pac_ctx *ctx, void *stream, const double *world_values, const int
 int pac_key_index(pac_ctx *ctx, void *stream, const int64_t *keys, int64_t n_keys, const int64_t *fk, int64_t n,
                   int32_t *out_index);
 
+/* ---- measurement ------------------------------------------------------------
+ * Not part of the method: the read rate that a plain streaming kernel with the
+ * scan kernels' load form (16-byte non-temporal loads, one contiguous 1 KB
+ * stretch per wavefront and step) reaches on this device is the achievable
+ * ceiling beside the datasheet peak, and the known byte counts of these two
+ * kernels calibrate the hardware traffic counters.
+ * pac_stream_read reads bytes (a multiple of 16, 16-byte aligned device
+ * buffer) and XORs a digest into *out (device uint64, caller-cleared) so the
+ * loads cannot be dropped; pac_stream_copy copies bytes from src to dst. */
+int pac_stream_read(pac_ctx *ctx, void *stream, const void *buf, int64_t bytes, uint64_t *out);
+int pac_stream_copy(pac_ctx *ctx, void *stream, const void *src, void *dst, int64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,5 +23,7 @@ from .api import (  # noqa: F401
     pac_noised,
     pac_select_cmp,
     pac_world_values,
+    stream_copy,
+    stream_read,
     tune_key,
 )

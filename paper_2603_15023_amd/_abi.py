@@ -105,6 +105,8 @@ EXPORTS = {
     "pac_finalize": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(AggState), C.c_int, C.c_int64, C.c_int, C.c_int,
                                C.c_void_p, C.c_int64, C.POINTER(FinalizeParams), C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pac_stream_read": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "pac_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "pac_tune_key": (C.c_int, [C.POINTER(AggInput), C.c_int, C.POINTER(AggState), C.POINTER(TuneEntry)]),
     "pac_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(TuneEntry), C.c_int]),
     "pac_finalize_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(ReleaseJob), C.c_int]),

@@ -173,6 +173,18 @@ class AggSpec:
         return s
 
 
+def stream_read(ctx: Context, buf: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    """Measurement: reads every byte of ``buf`` with the scan kernels' load form (digest XORed into ``out``)."""
+    A.check(A.load().pac_stream_read(ctx.handle, _stream_handle(stream), _ptr(buf), buf.numel() * buf.element_size(),
+                                     _ptr(out)))
+
+
+def stream_copy(ctx: Context, src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """Measurement: copies ``src`` into ``dst`` (same size)."""
+    A.check(A.load().pac_stream_copy(ctx.handle, _stream_handle(stream), _ptr(src), _ptr(dst),
+                                     src.numel() * src.element_size()))
+
+
 def tune_key(spec: AggSpec, m: int = 64, minmax: bool = False) -> Dict[str, int]:
     """The tuning class of an aggregation input (pac_tune_key; host only)."""
     cin = spec.to_c()

@@ -8,6 +8,7 @@
     python -m paper_2603_15023_amd.bench_workloads join   [--reps 3]
     python -m paper_2603_15023_amd.bench_workloads ratio  [--reps 3] [--seeds 200]
     python -m paper_2603_15023_amd.bench_workloads release [--reps 3]
+    python -m paper_2603_15023_amd.bench_workloads batch  [--reps 3] [--queries 16]
 
 zipf:  100M rows, 2M PU keys per row, group keys Zipf(1.1) over 1M ranks
        (HBM hash table), SUM int64 + COUNT, m = 64.
@@ -34,6 +35,10 @@ release: the sequential release chain: 100 000 random cells through
        pac_noised at m = 64 and 128 (microseconds per cell), then 16 queries of
        20 000 cells each released one after another (pac_finalize) and in one
        batched call (pac_finalize_batch).
+batch: the first --queries served queries whose counters fit the shared-scan
+       launch (the resident 100M-row table): their aggregations one after
+       another (pac_group_aggregate, forms chosen by AUTO) and in one
+       pac_group_aggregate_batch call (one launch, one scan of the table).
 minmax: the float table's rows with 8 groups (its group column mod 8): COUNT,
        SUM, MIN and MAX of the FP64 column per world, m = 64, against the same
        query without MIN/MAX.
@@ -373,6 +378,42 @@ def release(args):
     ctx.close()
 
 
+def batch(args):
+    from workloads import gen
+    from . import pac_group_aggregate_batch
+    from .serve import BATCH_LDS_BYTES, ResidentStar, query_spec, shared_scan_bytes
+    table = ResidentStar.from_table(gen.config5_star())
+    ctx = Context(0)
+    qs, used = [], 0
+    for q in gen.config5_queries(2000):
+        b = shared_scan_bytes(q)
+        if len(qs) < args.queries and used + b <= BATCH_LDS_BYTES:
+            qs.append(q)
+            used += b
+    specs = [query_spec(table, q, None) for q in qs]
+    states = [new_state(sp, 64) for sp in specs]
+    keys = [q.query_key for q in qs]
+    sel = float(np.mean([q.filter_lt / 2.0 ** 32 for q in qs]))
+    for mode in ("one after another", "one shared-scan launch"):
+        times = []
+        for r in range(args.reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "one shared-scan launch":
+                pac_group_aggregate_batch(ctx, specs, states, keys, m=64)
+            else:
+                for sp, st, k in zip(specs, states, keys):
+                    pac_group_aggregate(ctx, sp, st, m=64, query_key=k)
+            torch.cuda.synchronize()
+            if r:
+                times.append((time.perf_counter() - t0) * 1e3)
+        print(json.dumps({"workload": f"{len(qs)} served queries over 100M rows (groups "
+                                      f"{min(q.n_groups for q in qs)}-{max(q.n_groups for q in qs)}, mean filter "
+                                      f"{sel:.3f})", "mode": mode, "ms": float(np.mean(times))}), flush=True)
+    ctx.check()
+    ctx.close()
+
+
 def serve(args):
     from workloads import gen
     from .serve import ResidentStar, Server, latency_summary
@@ -391,7 +432,8 @@ def serve(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested", "join", "ratio", "release"])
+    ap.add_argument("what", choices=["zipf", "float", "serve", "minmax", "nested", "join", "ratio", "release",
+                                     "batch"])
     ap.add_argument("--seeds", type=int, default=200)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--algo", default="auto")
@@ -400,7 +442,7 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.7)
     args = ap.parse_args(argv)
     {"zipf": zipf, "float": float_, "serve": serve, "minmax": minmax, "nested": nested, "join": join,
-     "ratio": ratio, "release": release}[args.what](args)
+     "ratio": ratio, "release": release, "batch": batch}[args.what](args)
 
 
 if __name__ == "__main__":

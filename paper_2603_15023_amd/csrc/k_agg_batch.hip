@@ -28,7 +28,7 @@ namespace pac {
 constexpr int kBatchI = 4;  // int columns per query
 constexpr int kBatchF = 2;  // float columns per query
 constexpr int kBatchG = 2;  // group columns per query
-constexpr int kBatchWaves = 4;
+constexpr int kBatchWaves = 16;  // waves sharing a workgroup's LDS counters (latency of the gathers)
 constexpr int kBatchLdsBytes = 96 * 1024;
 
 struct BatchQuery {
@@ -44,6 +44,7 @@ struct BatchQuery {
   int32_t gcol_type[kBatchG];
   uint32_t gcards[kBatchG];
   uint32_t group_mod;
+  double inv_mod;  // 1 / group_mod, for the modulus without an integer division
   uint32_t G;
   int32_t ni, nf;
   const void *icols[kBatchI];
@@ -104,7 +105,13 @@ __global__ __launch_bounds__(64 * kBatchWaves) void agg_batch(BatchArgs a, uint3
           bad_group |= v >= Q.gcards[k];
           g = g * Q.gcards[k] + v;
         }
-        if (Q.group_mod) g %= Q.group_mod;
+        if (Q.group_mod) {  // g mod group_mod: a quotient from the fp64 reciprocal, corrected by one
+          uint32_t q = (uint32_t)((double)g * Q.inv_mod);
+          int64_t rem = (int64_t)g - (int64_t)q * Q.group_mod;
+          if (rem < 0) rem += Q.group_mod;
+          if (rem >= (int64_t)Q.group_mod) rem -= Q.group_mod;
+          g = (uint32_t)rem;
+        }
         bad_group |= g >= Q.G;
       }
       if (bad_group) atomicOr(status, PAC_STATUS_BAD_GROUP);
@@ -232,6 +239,7 @@ hipError_t launch_agg_batch(const LaunchEnv &env, const DevInput *in, const DevS
       q.gcards[k] = (uint32_t)d.gcards[k];
     }
     q.group_mod = (uint32_t)d.group_mod;
+    q.inv_mod = d.group_mod ? 1.0 / (double)d.group_mod : 0.0;
     q.G = (uint32_t)d.n_groups;
     q.ni = d.n_icols;
     q.nf = d.n_fcols;

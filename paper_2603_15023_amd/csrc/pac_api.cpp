@@ -399,6 +399,25 @@ const char *pac_last_error(void) { return g_err.c_str(); }
 
 int pac_version(void) { return 1; }
 
+int pac_stream_read(pac_ctx *ctx, void *stream, const void *buf, int64_t bytes, uint64_t *out) {
+  if (!ctx || (bytes > 0 && (!buf || !out))) return fail(PAC_ERR_INVALID, "null context, buffer or output");
+  if (bytes < 0 || (bytes & 15) || ((uintptr_t)buf & 15)) return fail(PAC_ERR_INVALID, "bytes must be a multiple of 16, buffer 16-byte aligned");
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e = pac::launch_stream_read(env, buf, bytes, out);
+  return e == hipSuccess ? PAC_OK : hip_fail(e, "stream read launch");
+}
+
+int pac_stream_copy(pac_ctx *ctx, void *stream, const void *src, void *dst, int64_t bytes) {
+  if (!ctx || (bytes > 0 && (!src || !dst))) return fail(PAC_ERR_INVALID, "null context or buffer");
+  if (bytes < 0 || (bytes & 15) || (((uintptr_t)src | (uintptr_t)dst) & 15))
+    return fail(PAC_ERR_INVALID, "bytes must be a multiple of 16, buffers 16-byte aligned");
+  DeviceGuard guard(ctx->device);
+  pac::LaunchEnv env{(hipStream_t)stream, ctx->n_cu, ctx->d_status};
+  const hipError_t e = pac::launch_stream_copy(env, src, dst, bytes);
+  return e == hipSuccess ? PAC_OK : hip_fail(e, "stream copy launch");
+}
+
 int pac_tune_key(const pac_agg_input *in, int m, const pac_agg_state *state, pac_tune_entry *key) {
   if (!in || !key) return fail(PAC_ERR_INVALID, "null input or key");
   pac::DevInput d;

@@ -294,6 +294,10 @@ hipError_t launch_finalize(const LaunchEnv &env, const DevState &st, const pac_c
                            double *out_y, void *scratch);
 size_t finalize_scratch_bytes(int m, int64_t n_cells);
 
+// Measurement kernels (streaming read / copy).
+hipError_t launch_stream_read(const LaunchEnv &env, const void *buf, int64_t bytes, uint64_t *out);
+hipError_t launch_stream_copy(const LaunchEnv &env, const void *src, void *dst, int64_t bytes);
+
 // One float column on the bf16 matrix cores (approximate form).
 bool fmma_supported(const DevInput &in, const DevState &st);
 hipError_t launch_agg_fmma(const LaunchEnv &env, const DevInput &in, const DevState &st);
