@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv", "mfma_generic"])
+    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv", "mfma_kw",
+                                                       "mfma_generic"])
     ap.add_argument("--compare-steps", type=int, default=5, help="steps timed for the other GPU forms")
     ap.add_argument("--no-pipeline", dest="pipeline", action="store_false",
                     help="time the steps one after another on one stream only")
@@ -118,6 +119,10 @@ def main():
     spec_kv = P.AggSpec(n_rows=n, links=[links[0]], gcols=gcols, gcards=t.gcards, n_groups=6, cols=cols,
                         stats=stats)
     spec_kv.pu_keys = torch.from_numpy(t.pu_key[t.o_pu]).to(dev)
+    # ... and with the orders' PU keys hashed once per query into per-order words (one link, no hash per row)
+    omask = torch.empty((n_orders, 1), dtype=torch.int64, device=dev)
+    spec_kw = P.AggSpec(n_rows=n, masks=omask, links=[links[0]], gcols=gcols, gcards=t.gcards, n_groups=6, cols=cols,
+                        stats=stats)
     state = P.new_state(spec, 64)
     state2 = P.new_state(spec, 64)  # the second and third counter sets of the pipelined steps
     state3 = P.new_state(spec, 64)
@@ -134,13 +139,16 @@ def main():
 
     def step(algo, ev=None):
         kv = algo == "mfma_kv"
-        if not kv:
+        if algo == "mfma_kw":
+            P.pac_hash_mask(ctx, spec_kv.pu_keys, K, 64, out=omask)
+        elif not kv:
             P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
         for v in state.values():  # counters start at zero (fill kernels, outside the event bracket)
             v.zero_()
         if ev is not None:
             ev[0].record(stream)
-        P.pac_group_aggregate(ctx, spec_kv if kv else spec, state, m=64, query_key=K, algo="mfma" if kv else algo,
+        sp = spec_kv if kv else spec_kw if algo == "mfma_kw" else spec
+        P.pac_group_aggregate(ctx, sp, state, m=64, query_key=K, algo="mfma" if algo in ("mfma_kv", "mfma_kw") else algo,
                               init=False)
         if ev is not None:
             ev[1].record(stream)
@@ -223,20 +231,20 @@ def main():
 
     ms_step, agg_ms, step_ms = run(args.algo, args.steps, args.warmup, latency_steps=min(args.steps, 50))
     ms_step_seq = ms_step
-    if args.pipeline and args.algo != "mfma_kv":
+    if args.pipeline and args.algo not in ("mfma_kv", "mfma_kw"):
         ms_step, agg_ms = run_pipelined(args.steps, args.warmup)
         log(f"pipelined: {ms_step:.3f} ms/step (sequential {ms_step_seq:.3f}), aggregate kernel {agg_ms:.3f} ms")
 
     ctx.check()
     log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
     graph = graph_measurement(args, P, ctx, pu_key, K, masks, spec, state, cells_t, len(cells), seed) \
-        if args.algo != "mfma_kv" else None
+        if args.algo not in ("mfma_kv", "mfma_kw") else None
 
     # the other GPU forms on the same inputs (same counters; checked in the tests): the plain per-bit form, the
     # generic matrix-core kernel, the star kernel with the orders carrying their PU key
     forms = {}
     ref_state = {k: v.clone() for k, v in state.items()}
-    for algo in ("plain", "mfma", "mfma_generic", "mfma_kv"):
+    for algo in ("plain", "mfma", "mfma_generic", "mfma_kv", "mfma_kw"):
         if args.compare_steps <= 0:
             break
         if algo == args.algo:
@@ -290,11 +298,11 @@ def main():
 
     alg_bytes = 30 * n + 4 * n_orders + 8 * n_pu  # fact columns + o_pu + the PU word table, each once
     alg_kv = 30 * n + 8 * n_orders  # fact columns + the orders' PU keys
-    achieved = (alg_kv if args.algo == "mfma_kv" else alg_bytes) / (agg_ms * 1e-3) / 1e9
+    achieved = (alg_kv if args.algo in ("mfma_kv", "mfma_kw") else alg_bytes) / (agg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "agg_star (int8 matrix cores, star-schema form)",
-                "alg_bytes_per_launch": alg_kv if args.algo == "mfma_kv" else alg_bytes}
+                "alg_bytes_per_launch": alg_kv if args.algo in ("mfma_kv", "mfma_kw") else alg_bytes}
 
     serving = serve_measurement(args) if args.serve_queries > 0 else None
 
@@ -328,9 +336,12 @@ def main():
         "aggregate_rows_per_s": n / (agg_ms * 1e-3),
         "graph": graph,
         "forms": {k: dict(v, aggregate_rows_per_s=n / (v["aggregate_ms"] * 1e-3),
-                          alg_bytes=alg_kv if k == "mfma_kv" else alg_bytes,
-                          hbm_frac=round((alg_kv if k == "mfma_kv" else alg_bytes) / (v["aggregate_ms"] * 1e-3)
-                                         / 1e9 / HBM_PEAK_GBS, 4))
+                          alg_bytes=alg_kv if k in ("mfma_kv", "mfma_kw") else alg_bytes,
+                          hbm_frac=round((alg_kv if k in ("mfma_kv", "mfma_kw") else alg_bytes)
+                                         / (v["aggregate_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          step_hbm_frac=round((alg_kv if k in ("mfma_kv", "mfma_kw") else alg_bytes)
+                                              / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                          if "ms_per_step" in v else None)
                   for k, v in forms.items()},
         "roofline": roofline,
         "stream_read": dict(stream, frac_of_stream=round(achieved / stream["gbs"], 4)),

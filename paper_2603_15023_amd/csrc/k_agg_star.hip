@@ -3,7 +3,9 @@
 // orders -> PU; Sec. 4.2's per-world SUM/COUNT over the result):
 //   * either two FK links into the PU-word table (the words come from
 //     pac_hash_mask), or one FK link into a column that holds each order's PU
-//     key (hashed here, per row: no gather into a PU table);
+//     key (hashed here, per row: no gather into a PU table), or one FK link
+//     into per-order PU words (pac_hash_mask of the orders' PU keys: the
+//     clustered fact rows then read the words almost sequentially);
 //   * one or two u8 group columns whose product of cardinalities is <= 8;
 //   * NI int columns whose (v - lo) fits DIG <= 4 bytes (host statistics).
 // The contraction is the one of the generic matrix-core kernel
@@ -27,7 +29,8 @@ constexpr int kStarWPB = 4;  // waves per block
 constexpr int kStarTPI = 1;  // tiles per loop iteration of a wave (loads in flight)
 
 struct StarPlan {
-  int32_t kv;            // 1: one link into per-order PU keys, hashed in the kernel
+  int32_t kv;            // 0: two links into PU words; 1: one link into per-order PU keys, hashed in the
+                         // kernel; 2: one link into per-order PU words (the keys hashed beforehand)
   int32_t G;
   uint32_t lo[kMC];      // low 32 bits of each column's offset (all digits sit in (v - lo) mod 2^32)
   int64_t lo64[kMC];     // the offset itself, for the recombination
@@ -163,7 +166,7 @@ __device__ __forceinline__ uint32_t star_transpose(uint32_t x, const StarTc &tc)
   return x;
 }
 
-// PU words (KV = 0) or PU keys (KV = 1, hashed when staged) of the four rows.
+// PU words (KV = 0, 2) or PU keys (KV = 1, hashed when staged) of the four rows.
 template <int KV, int NGC, int NI>
 __device__ __forceinline__ void star_issue_words(const MfmaArgs &a, const QChain &c, StarRaw<NGC, NI> &r,
                                                  uint32_t *status) {
@@ -174,7 +177,7 @@ __device__ __forceinline__ void star_issue_words(const MfmaArgs &a, const QChain
     bad |= c.ok[j] && !in;
     r.ok[j] = c.ok[j] && in;
     const uint32_t i = r.ok[j] ? c.idx[j] : 0u;
-    r.mk[j] = KV ? (uint64_t)a.pu_keys[i] : a.masks[i];
+    r.mk[j] = KV == 1 ? (uint64_t)a.pu_keys[i] : a.masks[i];
   }
   if (bad) atomicOr(status, PAC_STATUS_BAD_LINK);
 }
@@ -241,7 +244,7 @@ __device__ __forceinline__ void star_stage_store(const MfmaArgs &a, StarStage<NG
                                                  const StarRaw<NGC, NI> &r) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint64_t w = KV ? pu_word((int64_t)r.mk[j], a.qk, 0, a.balanced != 0) : r.mk[j];
+    const uint64_t w = KV == 1 ? pu_word((int64_t)r.mk[j], a.qk, 0, a.balanced != 0) : r.mk[j];
     sg->mk[4 * lane + j] = r.ok[j] ? w : 0ull;
   }
 #pragma unroll
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
       StarRaw<NGC, NI> r;
       QChain c;
       qchain_first(a, row_of(gi, k), lane, c);
-      if (!KV) qchain_next(a, c, status);
+      if (KV == 0) qchain_next(a, c, status);
       star_issue_words<KV>(a, c, r, status);
       star_issue_cols(a, pl, row_of(gi, k), lane, r);
       star_stage_store<KV>(a, stage + k, lane, r);
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
 #pragma unroll
     for (int k = 0; k < kStarTPI; ++k) {
       qchain_first(a, row_of(clampg(gi + stride), k), lane, l1[k]);
-      if (!KV) qchain_next(a, l1[k], status);
+      if (KV == 0) qchain_next(a, l1[k], status);
       qchain_first(a, row_of(clampg(gi + 2 * stride), k), lane, l0[k]);
     }
     for (; gi < n_grp; gi += stride) {
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         n1[k] = l0[k];
-        if (!KV) qchain_next(a, n1[k], status);
+        if (KV == 0) qchain_next(a, n1[k], status);
         qchain_first(a, row_of(clampg(gi + 3 * stride), k), lane, l0[k]);
       }
 #pragma unroll
@@ -539,7 +542,7 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
     StarRaw<NGC, NI> r;
     QChain c;
     qchain_first_tail(a, row0, lane, c);
-    if (!KV) qchain_next(a, c, status);
+    if (KV == 0) qchain_next(a, c, status);
     star_issue_words<KV>(a, c, r, status);
     star_issue_cols_tail(a, pl, row0, lane, r);
     star_stage_store<KV>(a, stage, lane, r);
@@ -584,7 +587,8 @@ static int star_digits(const DevInput &in) {
 static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   if (in.W != 1 || in.filter_col || in.group_mod || in.group_keys) return false;
   const bool kv = in.n_links == 1 && !in.masks && in.pu_keys;  // orders carry the PU key
-  if (!kv && !(in.n_links == 2 && in.masks)) return false;
+  const bool kw = in.n_links == 1 && in.masks;                  // orders carry their PU words
+  if (!kv && !kw && !(in.n_links == 2 && in.masks)) return false;
   if (in.n_fcols > 0 || in.n_icols < 1 || in.n_icols > 3 || in.n_gcols != 2) return false;
   if (star_digits(in) != 3) return false;
   const int64_t lim = (int64_t)1 << 31;
@@ -601,7 +605,7 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   for (int c = 0; c < in.n_icols; ++c)
     if (in.icol_type[c] != PAC_I64) return false;
   StarPlan p{};
-  p.kv = kv ? 1 : 0;
+  p.kv = kv ? 1 : kw ? 2 : 0;
   p.G = (int)G;
   for (int c = 0; c < in.n_icols; ++c) {
     p.lo[c] = (uint32_t)in.icol_lo[c];
@@ -689,7 +693,11 @@ hipError_t launch_agg_star(const LaunchEnv &env, const DevInput &in, const DevSt
   StarPlan pl;
   int nt;
   if (!star_plan(in, &pl, &nt)) return hipErrorInvalidValue;
-  return pl.kv ? launch_star_kv<1>(env, in, st, pl, nt) : launch_star_kv<0>(env, in, st, pl, nt);
+  switch (pl.kv) {
+    case 1: return launch_star_kv<1>(env, in, st, pl, nt);
+    case 2: return launch_star_kv<2>(env, in, st, pl, nt);
+    default: return launch_star_kv<0>(env, in, st, pl, nt);
+  }
 }
 
 }  // namespace pac

@@ -167,6 +167,29 @@ def test_star_kernel_key_valued_orders(ctx, gcards, n_cols, balanced):
     compare_counters(got, star_definition(t, 0x77AA, 64, int_cols=ints, balanced=balanced))
 
 
+@pytest.mark.parametrize("gcards,n_cols", [((3, 2), 3), ((2, 4), 1), ((1, 1), 2)])
+def test_star_kernel_per_order_words(ctx, torch_mod, gcards, n_cols):
+    """The orders' PU keys hashed once into per-order words (pac_hash_mask of the orders' keys), then one FK
+    link from the fact rows into those words: the same counters as following both links."""
+    import paper_2603_15023_amd as P
+    from cases import order_keys
+    t = gen.tiny_star(80 + n_cols, n_pu=700, n_orders=4000, n_rows=256 * 33 + 91, gcards=gcards, n_cols=n_cols,
+                      value_range=(-6_000_000, 6_000_000))
+    ints = [f"v{i}" for i in range(n_cols)]
+    K = 0x0DE5
+    dev = torch_mod.device("cuda")
+    omask = P.pac_hash_mask(ctx, torch_mod.from_numpy(order_keys(t)).to(dev), K, 64)
+    G = int(np.prod(gcards))
+    spec = P.AggSpec(n_rows=t.n_rows, masks=omask, links=[torch_mod.from_numpy(t.f_order).to(dev)],
+                     gcols=[torch_mod.from_numpy(g).to(dev) for g in t.gcols], gcards=list(gcards), n_groups=G,
+                     cols=[torch_mod.from_numpy(t.cols[c]).to(dev) for c in ints],
+                     stats=[(int(t.cols[c].min()), int(t.cols[c].max())) for c in ints])
+    st = P.new_state(spec, 64)
+    P.pac_group_aggregate(ctx, spec, st, m=64, query_key=K, algo="mfma")
+    assert ctx.status() == 0
+    compare_counters({k: v.cpu().numpy() for k, v in st.items()}, star_definition(t, K, 64, int_cols=ints))
+
+
 def test_star_kernel_skips_bad_group_rows(ctx):
     import dataclasses
     t = gen.tiny_star(47, n_pu=300, n_orders=2000, n_rows=256 * 20 + 7, gcards=(3, 2), n_cols=3,
@@ -293,6 +316,25 @@ def test_config2_shuffled_full_size(ctx):
     assert got["status"] == 0
     compare_counters(got, _config2_oracle())
     compare_counters(got, star_oracle(t, K, 64, int_cols=ints))
+
+
+def test_config2_per_order_words_full_size(ctx, torch_mod):
+    """The 60M-row star schema with the orders' PU keys hashed into per-order words and one FK link."""
+    import paper_2603_15023_amd as P
+    from cases import order_keys
+    t = _config2()
+    K = gen.query_key(1)
+    dev = torch_mod.device("cuda")
+    _say("config2 per-order words")
+    omask = P.pac_hash_mask(ctx, torch_mod.from_numpy(order_keys(t)).to(dev), K, 64)
+    ints = ["v1", "v2", "v3"]
+    spec = P.AggSpec(n_rows=t.n_rows, masks=omask, links=[torch_mod.from_numpy(t.f_order).to(dev)],
+                     gcols=[torch_mod.from_numpy(g).to(dev) for g in t.gcols], gcards=list(t.gcards), n_groups=6,
+                     cols=[torch_mod.from_numpy(t.cols[c]).to(dev) for c in ints], stats=[(100, 10_000_000)] * 3)
+    st = P.new_state(spec, 64)
+    P.pac_group_aggregate(ctx, spec, st, m=64, query_key=K, algo="mfma")
+    assert ctx.status() == 0
+    compare_counters({k: v.cpu().numpy() for k, v in st.items()}, _config2_oracle())
 
 
 def test_config2_key_valued_orders_full_size(ctx):
