@@ -81,7 +81,7 @@ int pac_hash_mask(pac_ctx *ctx, void *stream, const int64_t *keys, int64_t n, ui
  * Sec. 5; Theorem 2 makes one scan equal to m executions) ------------------ */
 enum pac_type { PAC_U8 = 1, PAC_U16 = 2, PAC_U32 = 3, PAC_I32 = 4, PAC_I64 = 5, PAC_F32 = 6, PAC_F64 = 7 };
 
-#define PAC_MAX_LINKS 4
+#define PAC_MAX_LINKS 8
 #define PAC_MAX_GCOLS 4
 #define PAC_MAX_COLS 8
 #define PAC_EMPTY_KEY ((int64_t)0x8000000000000000ull) /* unused sparse slot; not a valid group key */

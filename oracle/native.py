@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "onepass.c")
 _LIB = os.path.join(_HERE, "libpac_oracle.so")
 
-MAX_LINKS, MAX_GCOLS, MAX_COLS = 4, 4, 8
+MAX_LINKS, MAX_GCOLS, MAX_COLS = 8, 4, 8
 
 
 class _In(C.Structure):

@@ -24,7 +24,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_MAX_LINKS 4
+#define OR_MAX_LINKS 8
 #define OR_MAX_GCOLS 4
 #define OR_MAX_COLS 8
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpac.so")
 HEADER = os.path.join(HERE, "..", "include", "pac.h")
 
-MAX_LINKS, MAX_GCOLS, MAX_COLS = 4, 4, 8
+MAX_LINKS, MAX_GCOLS, MAX_COLS = 8, 4, 8
 
 PAC_OK = 0
 ERRORS = {-1: "PAC_ERR_INVALID", -2: "PAC_ERR_OOM", -3: "PAC_ERR_HIP", -4: "PAC_ERR_OVERFLOW",

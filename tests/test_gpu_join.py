@@ -54,3 +54,33 @@ def test_aggregation_through_key_valued_foreign_keys(ctx, torch_mod, m):
                       gcards=t.gcards, n_groups=6, int_cols=[t.cols["v0"], t.cols["v1"]])
     for k in ("count", "isum", "nrows"):
         assert np.array_equal(st[k].cpu().numpy(), want[k]), k
+
+
+@pytest.mark.parametrize("algo", ["auto", "plain", "partition", "register"])
+def test_deep_unclustered_fk_chain(ctx, torch_mod, algo):
+    """Six foreign-key links from the fact rows to the PU table (the paper's multi-level PU chains, rows in random
+    order at every level), with a filter, 40 groups and an int and a float column, against the oracle."""
+    import paper_2603_15023_amd as P
+    g = np.random.default_rng(67)
+    sizes = [300_007, 120_000, 60_000, 30_000, 9000, 3000, 1500]
+    links = [g.integers(0, sizes[k + 1], size=sizes[k], dtype=np.int32) for k in range(6)]
+    pu_key = g.integers(1, 1 << 40, size=sizes[-1], dtype=np.int64)
+    grp = g.integers(0, 40, size=sizes[0], dtype=np.uint8)
+    sel = g.integers(0, 1 << 32, size=sizes[0], dtype=np.uint32)
+    v = g.integers(0, 10**7, size=sizes[0], dtype=np.int64)
+    f = g.lognormal(0.0, 1.0, size=sizes[0])
+    K, lt = 0xC4A1, 3 << 30
+    dev = torch_mod.device("cuda")
+    cols = [torch_mod.from_numpy(v).to(dev)] + ([torch_mod.from_numpy(f).to(dev)] if algo != "register" else [])
+    spec = P.AggSpec(n_rows=sizes[0], pu_keys=torch_mod.from_numpy(pu_key).to(dev),
+                     links=[torch_mod.from_numpy(l).to(dev) for l in links],
+                     gcols=[torch_mod.from_numpy(grp).to(dev)], gcards=[40], n_groups=40,
+                     filter_col=torch_mod.from_numpy(sel.view(np.int32)).to(dev), filter_lt=lt, cols=cols,
+                     stats=[(0, 10**7)] + [(0, 0)] * (len(cols) - 1))
+    st = P.new_state(spec, 64)
+    P.pac_group_aggregate(ctx, spec, st, m=64, query_key=K, algo=algo)
+    assert ctx.status() == 0
+    want = ON.onepass(sizes[0], 64, pu_keys=pu_key, query_key=K, links=links, gcols=[grp], gcards=[40], n_groups=40,
+                      filter_col=sel, filter_lt=lt, int_cols=[v], float_cols=[f] if algo != "register" else [])
+    from cases import compare_counters
+    compare_counters({k: x.cpu().numpy() for k, x in st.items()}, want)

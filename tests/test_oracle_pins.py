@@ -572,3 +572,27 @@ def test_pac_noised_split_over_two_calls_equals_one_call():
     # without the offset the second call would reuse the first call's draws
     vc, _, _, _ = R.pac_noised(wv[k:], 64, B, seed, prior=Pa, cell_rows=rows[k:])
     assert not np.array_equal(vb, vc)
+
+
+def test_deep_fk_chain_equals_its_composition():
+    """A PU chain of six foreign-key links (rows in random order at every level) gives the counters of the one
+    link that composes them, and those of the per-world definition over the composed PU column (the chain is
+    only a way of reaching each row's PU, Sec. 2 relational privacy unit)."""
+    from oracle import native as ON
+    g = np.random.default_rng(66)
+    sizes = [5000, 3000, 2000, 1500, 900, 400, 120]  # rows, then each referenced table; the last is the PU table
+    links = [g.integers(0, sizes[k + 1], size=sizes[k], dtype=np.int32) for k in range(6)]
+    pu_key = g.integers(-(1 << 60), 1 << 60, size=sizes[-1], dtype=np.int64)
+    grp = g.integers(0, 5, size=sizes[0], dtype=np.uint8)
+    v = g.integers(-10**9, 10**9, size=sizes[0], dtype=np.int64)
+    K = 0x600D
+    comp = np.arange(sizes[0])
+    for l in links:
+        comp = l[comp]
+    deep = ON.onepass(sizes[0], 64, pu_keys=pu_key, query_key=K, links=links, gcols=[grp], gcards=[5], n_groups=5,
+                      int_cols=[v])
+    one = ON.onepass(sizes[0], 64, pu_keys=pu_key, query_key=K, links=[comp.astype(np.int32)], gcols=[grp],
+                     gcards=[5], n_groups=5, int_cols=[v])
+    want = R.pac_agg_counters(R.pac_hash_np(pu_key[comp], K, 64), grp.astype(np.int64), 5, [v])
+    for k in ("count", "isum", "nrows"):
+        assert np.array_equal(deep[k], one[k]) and np.array_equal(deep[k], want[k]), k
