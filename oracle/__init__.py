@@ -17,4 +17,7 @@ Modules
 ``onepass.c``   the same per-world definition as a multi-threaded C loop
                 (``native``), used for full-size inputs and timed as the CPU
                 baseline.
+``approx_sum.c`` the approximate integer SUM of Sec. 5 (16-bit counters in
+                25 levels cascading every 4 bits, two-sided or signed), one
+                sequential pass per block of rows (``native.approx_sum``).
 """

@@ -1,7 +1,8 @@
-"""ctypes front of the C one-pass oracle (oracle/onepass.c) -- TEST INFRASTRUCTURE.
+"""ctypes front of the C oracles (oracle/onepass.c, oracle/approx_sum.c) -- TEST INFRASTRUCTURE.
 
-``build()`` compiles onepass.c with gcc into oracle/libpac_oracle.so;
-``onepass(...)`` runs it on numpy arrays and returns the per-world counters.
+``build()`` compiles them with gcc into oracle/libpac_oracle.so;
+``onepass(...)`` runs the exact per-world counters on numpy arrays and
+``approx_sum(...)`` the approximate 16-bit cascaded SUM of Sec. 5.
 """
 from __future__ import annotations
 
@@ -13,7 +14,7 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "onepass.c")
+_SRCS = [os.path.join(_HERE, "onepass.c"), os.path.join(_HERE, "approx_sum.c")]
 _LIB = os.path.join(_HERE, "libpac_oracle.so")
 
 MAX_LINKS, MAX_GCOLS, MAX_COLS = 8, 4, 8
@@ -42,10 +43,10 @@ class _Out(C.Structure):
 
 def build(force: bool = True) -> str:
     """Compile the C oracle (portable x86-64-v3 code, so the library also runs on other hosts)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(map(os.path.getmtime, _SRCS)):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-fPIC", "-shared", "-pthread",
-                               "-Wall", "-Wno-unused-variable", "-o", tmp, _SRC])
+                               "-Wall", "-Wno-unused-variable", "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -63,6 +64,9 @@ def lib():
         _lib.oracle_onepass.restype = C.c_int
         _lib.oracle_hash.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_int, C.c_int, C.c_void_p]
         _lib.oracle_hash.restype = None
+        _lib.oracle_approx_sum.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
+                                           C.c_int64, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.oracle_approx_sum.restype = C.c_int
     return _lib
 
 
@@ -165,3 +169,28 @@ def onepass(n_rows: int, m: int = 64, *, masks: Optional[np.ndarray] = None,
     for k, v in mm.items():
         res[k] = v[:ng]
     return res
+
+
+def approx_sum(group: np.ndarray, words: np.ndarray, values: np.ndarray, n_groups: int, m: int = 64, *,
+               block_rows: Optional[int] = None, two_sided: bool = True,
+               threads: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Approximate per-world SUM of one int column (Sec. 5, Approximation), see approx_sum.c.
+
+    ``group[r]`` is row r's group (-1: skipped), ``words[r]`` its PU bits ([n][m/64]
+    uint64), ``values[r]`` its value.  ``block_rows`` = None is one sequential pass.
+    Returns ``mod64`` [G][m] int64 (pos - neg mod 2^64), ``f64`` (the same as a
+    double) and ``exact`` (the exact per-world sum as a double)."""
+    group = np.ascontiguousarray(group, dtype=np.int64)
+    words = np.ascontiguousarray(words, dtype=np.uint64).reshape(group.shape[0], m // 64)
+    values = np.ascontiguousarray(values, dtype=np.int64)
+    n = group.shape[0]
+    assert values.shape[0] == n
+    G = int(n_groups)
+    out = {"mod64": np.zeros((G, m), np.int64), "f64": np.zeros((G, m)), "exact": np.zeros((G, m))}
+    R = int(block_rows) if block_rows else max(n, 1)
+    rc = lib().oracle_approx_sum(n, _ptr(group), _ptr(words), m, _ptr(values), G, R, int(two_sided),
+                                 threads or default_threads(), _ptr(out["mod64"]), _ptr(out["f64"]),
+                                 _ptr(out["exact"]))
+    if rc != 0:
+        raise RuntimeError(f"oracle_approx_sum failed: {rc}")
+    return out

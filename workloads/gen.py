@@ -253,3 +253,45 @@ def tiny_flat(seed: int, n_rows: int = 500, n_keys: int = 30, n_groups: int = 4,
         return FlatTable(pu_key=pu_key, cols=cols, group_keys=gk[g.integers(0, n_groups, size=n_rows)])
     grp = g.integers(0, n_groups, size=n_rows, dtype=np.uint8)
     return FlatTable(pu_key=pu_key, cols=cols, gcols=[grp], gcards=[n_groups])
+
+
+# Value distributions of the approximate-SUM accuracy study (Sec. 6.1, Approximation,
+# Table 1): the ten distribution kinds it names, with recipes of this module's own.
+APPROX_DISTRIBUTIONS = ("all_same", "bimodal", "exponential", "negative_mixed", "sparse_large",
+                        "uniform_bigint", "uniform_int", "uniform_smallint", "uniform_tinyint", "zipf_like")
+
+
+def approx_values(kind: str, n: int = 1_000_000, seed: int = CONFIG_SEEDS[0] + 0x300) -> np.ndarray:
+    """int64 values of one distribution kind of the approximate-SUM accuracy study."""
+    g = _rng(seed + APPROX_DISTRIBUTIONS.index(kind))
+    if kind == "all_same":
+        return np.full(n, 12_345, np.int64)
+    if kind == "bimodal":  # two normal modes two decades apart
+        lo = g.random(n) < 0.5
+        return np.where(lo, g.normal(1e4, 1e3, n), g.normal(1e6, 1e5, n)).round().astype(np.int64)
+    if kind == "exponential":
+        return g.exponential(1e5, n).round().astype(np.int64)
+    if kind == "negative_mixed":  # symmetric around zero: the per-world sums nearly cancel
+        return g.integers(-1_000_000, 1_000_001, n, dtype=np.int64)
+    if kind == "sparse_large":  # 1% non-zero, 1e11 .. 1e13
+        v = np.zeros(n, np.int64)
+        nz = g.random(n) < 0.01
+        v[nz] = g.integers(10 ** 11, 10 ** 13, int(nz.sum()), dtype=np.int64)
+        return v
+    if kind == "uniform_bigint":
+        return g.integers(0, 2 ** 62, n, dtype=np.int64)
+    if kind == "uniform_int":
+        return g.integers(0, 2 ** 31, n, dtype=np.int64)
+    if kind == "uniform_smallint":
+        return g.integers(0, 2 ** 15, n, dtype=np.int64)
+    if kind == "uniform_tinyint":
+        return g.integers(0, 2 ** 7, n, dtype=np.int64)
+    if kind == "zipf_like":  # heavy tail, capped at 1e9
+        return np.minimum(g.zipf(1.5, n), 10 ** 9).astype(np.int64)
+    raise ValueError(kind)
+
+
+def random_words(n: int, m: int = 64, seed: int = CONFIG_SEEDS[0] + 0x310) -> np.ndarray:
+    """[n][m/64] uint64 of independent fair bits (PU words for tests that need no hashing)."""
+    g = _rng(seed)
+    return g.integers(0, 2 ** 64, (n, m // 64), dtype=np.uint64)
