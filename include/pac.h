@@ -176,6 +176,19 @@ typedef struct {
                                 COUNT and nrows are exact; a float sum differs from the fp64 one by the fp32 rounding
                                 of the inputs plus the fp32 accumulation between flushes (measured relative error
                                 per cell and its bound: see the design notes) */
+#define PAC_ALGO_APPROX16 8u /* an approximation, never chosen by AUTO: the approximate integer SUM of Sec. 5
+                               (Approximation) with the two-sided state.  Per world, 16-bit counters in levels
+                               that cascade every 4 bits: v != 0 goes to level l = floor((msb(|v|) - 8) / 4) (0
+                               below 256) as |v| >> 4l, on the positive or the negative side; a counter that
+                               would pass 65535 first moves C >> 4 one level up (recursively) and restarts at 0.
+                               A side is worth sum_k C[k] 2^(4k); the sum is pos - neg.  Rows are taken in blocks
+                               of PAC_APPROX_BLOCK_ROWS consecutive indices: for each block, group and world a
+                               fresh state takes the block's rows in row order, and its value is added exactly
+                               (mod 2^64) to isum.  Each value loses less than 2^-8 of itself to the shift, each
+                               cascading level less than 2^-12 of its side.  COUNT and nrows are exact.  Int
+                               columns only (any type, statistics not needed), dense or sparse groups, no MIN/MAX;
+                               the same descriptor as every other form. */
+#define PAC_APPROX_BLOCK_ROWS 1024
 #define PAC_AGG_INIT 1u     /* clear the state (and the sparse table) before aggregating */
 
 /* m in {64, 128}; query_key is used by the fused hash.  Returns

@@ -17,11 +17,12 @@ ERRORS = {-1: "PAC_ERR_INVALID", -2: "PAC_ERR_OOM", -3: "PAC_ERR_HIP", -4: "PAC_
 PAC_U8, PAC_U16, PAC_U32, PAC_I32, PAC_I64, PAC_F32, PAC_F64 = 1, 2, 3, 4, 5, 6, 7
 PAC_HASH_BALANCED = 1
 PAC_ALGO_AUTO, PAC_ALGO_PLAIN, PAC_ALGO_BALLOT, PAC_ALGO_MFMA_I8, PAC_ALGO_PARTITION = 0, 1, 2, 3, 4
-PAC_ALGO_REGISTER, PAC_ALGO_MFMA_GENERIC, PAC_ALGO_MFMA_BF16 = 5, 6, 7
+PAC_ALGO_REGISTER, PAC_ALGO_MFMA_GENERIC, PAC_ALGO_MFMA_BF16, PAC_ALGO_APPROX16 = 5, 6, 7, 8
+PAC_APPROX_BLOCK_ROWS = 1024
 PAC_SEL_LT, PAC_SEL_LE, PAC_SEL_EQ, PAC_SEL_NE, PAC_SEL_GT, PAC_SEL_GE = 0, 1, 2, 3, 4, 5
 ALGOS = {"auto": PAC_ALGO_AUTO, "plain": PAC_ALGO_PLAIN, "ballot": PAC_ALGO_BALLOT, "mfma": PAC_ALGO_MFMA_I8,
          "partition": PAC_ALGO_PARTITION, "register": PAC_ALGO_REGISTER, "mfma_generic": PAC_ALGO_MFMA_GENERIC,
-         "mfma_bf16": PAC_ALGO_MFMA_BF16}
+         "mfma_bf16": PAC_ALGO_MFMA_BF16, "approx16": PAC_ALGO_APPROX16}
 PAC_AGG_INIT = 1
 PAC_EMPTY_KEY = -(1 << 63)
 PAC_STATUS_BAD_GROUP, PAC_STATUS_BAD_LINK, PAC_STATUS_TABLE_FULL, PAC_STATUS_DIVERSITY = 1, 2, 4, 8

@@ -383,6 +383,11 @@ int run_one(pac_ctx *ctx, hipStream_t stream, const pac_agg_input *in, int m, ui
                                          "and at most 64 dense groups");
       e = pac::launch_agg_fmma(env, d, ds);
       break;
+    case PAC_ALGO_APPROX16:
+      if (!pac::approx_supported(d, ds))
+        return fail(PAC_ERR_UNSUPPORTED, "approximate SUM form needs int columns only (no float columns, no MIN/MAX)");
+      e = pac::launch_agg_approx(env, d, ds);
+      break;
     default:
       return fail(PAC_ERR_INVALID, "unknown algorithm %u", algo);
   }

@@ -302,6 +302,11 @@ hipError_t launch_stream_copy(const LaunchEnv &env, const void *src, void *dst, 
 bool fmma_supported(const DevInput &in, const DevState &st);
 hipError_t launch_agg_fmma(const LaunchEnv &env, const DevInput &in, const DevState &st);
 
+// Approximate two-sided integer SUM in 16-bit cascading levels.
+size_t approx_lds_bytes(const DevInput &in);
+bool approx_supported(const DevInput &in, const DevState &st);
+hipError_t launch_agg_approx(const LaunchEnv &env, const DevInput &in, const DevState &st);
+
 // Shared-scan aggregation of several queries in one launch (pac_group_aggregate_batch).
 constexpr int kMaxAggBatch = PAC_MAX_AGG_BATCH;
 bool batch_supported(const DevInput &in, const DevState &st);
