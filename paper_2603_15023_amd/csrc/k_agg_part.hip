@@ -85,6 +85,12 @@ static int det_reg_slots(const DevInput &in) {
   return mix ? (in.W == 1 ? 8 : 4) : 0;
 }
 
+// Static LDS of the register-counter kernel beside its dynamic counters: the
+// per-wave record staging s_rec[kPartWaves][W + max(CI,1) + max(CF,1)][64] and s_item.
+static int64_t det_reg_static_lds(const DevInput &in) {
+  return (int64_t)kPartWaves * (in.W + std::max(in.n_icols, 1) + std::max(in.n_fcols, 1)) * 64 * 8 + 8;
+}
+
 static bool part_plan(const DevInput &in, PartPlan *pl) {
   PartPlan p{};
   p.n_slots = in.n_groups;
@@ -101,7 +107,7 @@ static bool part_plan(const DevInput &in, PartPlan *pl) {
   while (((int64_t)2 << SB) <= slots) ++SB;
   if (p.det && det_reg_slots(in)) {
     SB = det_reg_slots(in) == 8 ? 3 : 2;
-    if (((int64_t)1 << SB) * per_slot > 160 * 1024) return false;
+    if (((int64_t)1 << SB) * per_slot + det_reg_static_lds(in) > 160 * 1024) return false;
   }
   p.SB = SB;
   p.lds_bytes = (int)(((int64_t)1 << SB) * per_slot);
