@@ -6,10 +6,16 @@ Workload: a synthetic 3-level star schema -- 1.5M PU keys, 15M orders
 by two low-cardinality columns (6 groups), COUNT + SUM/AVG of three int64
 decimal-cents columns uniform in [1e2, 1e7], m = 64 worlds.
 
-One step = the whole path for one query: keyed hash of the PU keys (a1),
-FK-chain gather + world-bit expansion + int8 matrix-core contraction + group
-counters (a2-a6), release of the 42 result cells with noise and posterior
-(a7).  Inputs are resident in HBM before timing starts.
+One step = the whole path for one query.  Default plan (--algo mfma_kv), the
+paper's rewrite of a fact-orders-PU chain (Sec. 2, PU-key Joins, and its
+rewritten TPC-H Q01): the orders' foreign-key column holds the PU key, so the
+fact rows follow one FK link to it and its keyed hash (a1) is computed per row
+inside the aggregation kernel; then world-bit expansion + int8 matrix-core
+contraction + group counters (a2-a6) and the release of the 42 result cells
+with noise and posterior (a7).  --algo mfma_kw hashes the orders' keys once
+per order into a word table first; --algo mfma times the two-link plan (fact
+-> orders -> PU table row, the PU table's keys hashed).  Inputs are resident
+in HBM before timing starts.
 
 Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: the benchmark
 runs on one GPU (how the path would shard is described with the design).
@@ -34,7 +40,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # Measured HBM traffic of the aggregation kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # calibrated against a copy kernel of known size); valid only for the kernel
 # sources whose hash it records.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "agg_star_star60M_traffic.md")
+TRAFFIC_FILES = {"mfma": os.path.join(ROOT, "profiles", "agg_star_star60M_traffic.md"),
+                 "mfma_kw": os.path.join(ROOT, "profiles", "agg_star_kw_star60M_traffic.md"),
+                 "mfma_kv": os.path.join(ROOT, "profiles", "agg_star_kv_star60M_traffic.md")}
 KERNEL_SOURCES = ["paper_2603_15023_amd/csrc/k_agg_star.hip", "paper_2603_15023_amd/csrc/mfma_common.h",
                   "paper_2603_15023_amd/csrc/pac_internal.h"]
 
@@ -48,8 +56,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--algo", default="mfma", choices=["mfma", "plain", "ballot", "auto", "mfma_kv", "mfma_kw",
-                                                       "mfma_generic"])
+    ap.add_argument("--algo", default="mfma_kv", choices=["mfma", "plain", "ballot", "auto", "mfma_kv", "mfma_kw",
+                                                          "mfma_generic", "plain_kw", "plain_kv"])
     ap.add_argument("--compare-steps", type=int, default=5, help="steps timed for the other GPU forms")
     ap.add_argument("--no-pipeline", dest="pipeline", action="store_false",
                     help="time the steps one after another on one stream only")
@@ -72,11 +80,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, or None if stale or absent."""
+def measured_traffic(algo):
+    """HBM bytes per launch from the committed counter summary of the timed form, or None if stale or absent."""
     try:
-        text = open(TRAFFIC_FILE).read()
-    except OSError:
+        text = open(TRAFFIC_FILES[algo]).read()
+    except (KeyError, OSError):
         return None
     src = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
@@ -137,19 +145,23 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
+    def plan(algo):
+        """(keys hashed per query or None, their word buffer, aggregation input, library form) of a plan."""
+        if algo in ("mfma_kv", "plain_kv"):  # the orders' PU keys, hashed per fact row inside the kernel
+            return None, None, spec_kv, algo[:-3]
+        if algo in ("mfma_kw", "plain_kw"):  # the orders' PU keys hashed once per order
+            return spec_kv.pu_keys, omask, spec_kw, algo[:-3]
+        return pu_key, masks, spec, algo  # the PU table's keys, reached through two links
+
     def step(algo, ev=None):
-        kv = algo == "mfma_kv"
-        if algo == "mfma_kw":
-            P.pac_hash_mask(ctx, spec_kv.pu_keys, K, 64, out=omask)
-        elif not kv:
-            P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
+        hkeys, hout, sp, lib_algo = plan(algo)
+        if hkeys is not None:
+            P.pac_hash_mask(ctx, hkeys, K, 64, out=hout)
         for v in state.values():  # counters start at zero (fill kernels, outside the event bracket)
             v.zero_()
         if ev is not None:
             ev[0].record(stream)
-        sp = spec_kv if kv else spec_kw if algo == "mfma_kw" else spec
-        P.pac_group_aggregate(ctx, sp, state, m=64, query_key=K, algo="mfma" if algo in ("mfma_kv", "mfma_kw") else algo,
-                              init=False)
+        P.pac_group_aggregate(ctx, sp, state, m=64, query_key=K, algo=lib_algo, init=False)
         if ev is not None:
             ev[1].record(stream)
         return P.pac_finalize(ctx, state, cells_t, len(cells), m=64, mi_budget=1.0 / 128, noise_seed=seed)
@@ -165,8 +177,12 @@ def main():
     ctx_prep, ctx_rel = P.Context(0), P.Context(0)
     s_prep, s_rel = torch.cuda.Stream(), torch.cuda.Stream()
     sets = [state, state2, state3]
-    mask_sets = [masks] + [torch.empty_like(masks) for _ in range(n_buf - 1)]
-    specs = [spec] + [dataclasses.replace(spec, masks=mk) for mk in mask_sets[1:]]
+    p_keys, p_words, p_spec, p_algo = plan(args.algo)
+    if p_words is not None:
+        mask_sets = [p_words] + [torch.empty_like(p_words) for _ in range(n_buf - 1)]
+        specs = [p_spec] + [dataclasses.replace(p_spec, masks=mk) for mk in mask_sets[1:]]
+    else:
+        mask_sets, specs = [None] * n_buf, [p_spec] * n_buf
     ev_prep = [torch.cuda.Event() for _ in range(n_buf)]
     ev_agg = [torch.cuda.Event() for _ in range(n_buf)]
     ev_rel = [torch.cuda.Event() for _ in range(n_buf)]
@@ -178,14 +194,15 @@ def main():
         st = sets[b]
         s_prep.wait_event(ev_rel[b])
         with torch.cuda.stream(s_prep):
-            P.pac_hash_mask(ctx_prep, pu_key, K, 64, out=mask_sets[b])
+            if p_keys is not None:
+                P.pac_hash_mask(ctx_prep, p_keys, K, 64, out=mask_sets[b])
             for v in st.values():
                 v.zero_()
             ev_prep[b].record(s_prep)
         stream.wait_event(ev_prep[b])
         if ev is not None:
             ev[0].record(stream)
-        P.pac_group_aggregate(ctx, specs[b], st, m=64, query_key=K, algo=args.algo, init=False)
+        P.pac_group_aggregate(ctx, specs[b], st, m=64, query_key=K, algo=p_algo, init=False)
         if ev is not None:
             ev[1].record(stream)
         ev_agg[b].record(stream)
@@ -231,20 +248,19 @@ def main():
 
     ms_step, agg_ms, step_ms = run(args.algo, args.steps, args.warmup, latency_steps=min(args.steps, 50))
     ms_step_seq = ms_step
-    if args.pipeline and args.algo not in ("mfma_kv", "mfma_kw"):
+    if args.pipeline:
         ms_step, agg_ms = run_pipelined(args.steps, args.warmup)
         log(f"pipelined: {ms_step:.3f} ms/step (sequential {ms_step_seq:.3f}), aggregate kernel {agg_ms:.3f} ms")
 
     ctx.check()
     log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
-    graph = graph_measurement(args, P, ctx, pu_key, K, masks, spec, state, cells_t, len(cells), seed) \
-        if args.algo not in ("mfma_kv", "mfma_kw") else None
+    graph = graph_measurement(args, P, ctx, K, plan(args.algo), state, cells_t, len(cells), seed)
 
     # the other GPU forms on the same inputs (same counters; checked in the tests): the plain per-bit form, the
     # generic matrix-core kernel, the star kernel with the orders carrying their PU key
     forms = {}
     ref_state = {k: v.clone() for k, v in state.items()}
-    for algo in ("plain", "mfma", "mfma_generic", "mfma_kv", "mfma_kw"):
+    for algo in ("plain", "plain_kv", "plain_kw", "mfma", "mfma_generic", "mfma_kv", "mfma_kw"):
         if args.compare_steps <= 0:
             break
         if algo == args.algo:
@@ -258,26 +274,31 @@ def main():
     if args.compare_steps > 0 and not args.shuffled:
         # the stress layout of the FK chain: the same fact rows in random order (same counters)
         ts = gen.config2_star(shuffled=True)
-        sspec = dataclasses.replace(spec, links=[torch.from_numpy(ts.f_order).to(dev), links[1]],
-                                    gcols=[torch.from_numpy(g).to(dev) for g in ts.gcols],
-                                    cols=[torch.from_numpy(ts.cols[c]).to(dev) for c in names])
+        s_order = torch.from_numpy(ts.f_order).to(dev)
+        s_g = [torch.from_numpy(g).to(dev) for g in ts.gcols]
+        s_c = [torch.from_numpy(ts.cols[c]).to(dev) for c in names]
         del ts
-        sagg = []
-        for i in range(args.compare_steps + 1):
-            P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
-            for v in state.values():
-                v.zero_()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            P.pac_group_aggregate(ctx, sspec, state, m=64, query_key=K, algo="mfma", init=False)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            if i > 0:
-                sagg.append(e0.elapsed_time(e1))
-        same = all(torch.equal(state[k], ref_state[k]) for k in ("count", "isum", "nrows"))
-        forms["mfma_shuffled"] = {"aggregate_ms": float(np.mean(sagg)), "same_counters": bool(same)}
-        log(f"mfma on shuffled fact rows: aggregate {forms['mfma_shuffled']['aggregate_ms']:.3f} ms, same {same}")
-        del sspec
+        for name, base, extra in (("mfma_shuffled", "mfma", [links[1]]), ("mfma_kv_shuffled", "mfma_kv", []),
+                                  ("mfma_kw_shuffled", "mfma_kw", [])):
+            hkeys, hout, sp0, lib_algo = plan(base)
+            sspec = dataclasses.replace(sp0, links=[s_order] + extra, gcols=s_g, cols=s_c)
+            sagg = []
+            for i in range(args.compare_steps + 1):
+                if hkeys is not None:
+                    P.pac_hash_mask(ctx, hkeys, K, 64, out=hout)
+                for v in state.values():
+                    v.zero_()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                P.pac_group_aggregate(ctx, sspec, state, m=64, query_key=K, algo=lib_algo, init=False)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if i > 0:
+                    sagg.append(e0.elapsed_time(e1))
+            same = all(torch.equal(state[k], ref_state[k]) for k in ("count", "isum", "nrows"))
+            forms[name] = {"aggregate_ms": float(np.mean(sagg)), "same_counters": bool(same)}
+            log(f"{base} on shuffled fact rows: aggregate {forms[name]['aggregate_ms']:.3f} ms, same {same}")
+        del sspec, s_order, s_g, s_c
         ctx.check()
 
     if args.calibrate_copy_gib > 0:
@@ -297,12 +318,19 @@ def main():
     log(f"stream read: {stream['gbs']:.0f} GB/s ({stream['kernel']})")
 
     alg_bytes = 30 * n + 4 * n_orders + 8 * n_pu  # fact columns + o_pu + the PU word table, each once
-    alg_kv = 30 * n + 8 * n_orders  # fact columns + the orders' PU keys
-    achieved = (alg_kv if args.algo in ("mfma_kv", "mfma_kw") else alg_bytes) / (agg_ms * 1e-3) / 1e9
+    alg_kv = 30 * n + 8 * n_orders  # fact columns + the orders' PU keys (or their words)
+    one_link = ("mfma_kv", "mfma_kw", "plain_kv", "plain_kw", "mfma_kv_shuffled", "mfma_kw_shuffled")
+    alg_of = {k: (alg_kv if k in one_link else alg_bytes)
+              for k in ("plain", "plain_kv", "plain_kw", "mfma", "mfma_generic", "mfma_kv", "mfma_kw", "ballot", "auto",
+                        "mfma_shuffled", "mfma_kv_shuffled", "mfma_kw_shuffled")}
+    achieved = alg_of[args.algo] / (agg_ms * 1e-3) / 1e9
+    kernel_name = {"mfma": "agg_star (int8 matrix cores; two FK links into the PU table's words)",
+                   "mfma_kw": "agg_star (int8 matrix cores; one FK link into per-order PU words)",
+                   "mfma_kv": "agg_star (int8 matrix cores; one FK link, the orders' PU keys hashed per row)"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "agg_star (int8 matrix cores, star-schema form)",
-                "alg_bytes_per_launch": alg_kv if args.algo in ("mfma_kv", "mfma_kw") else alg_bytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.algo),
+                "kernel": kernel_name.get(args.algo, args.algo),
+                "alg_bytes_per_launch": alg_of[args.algo]}
 
     serving = serve_measurement(args) if args.serve_queries > 0 else None
 
@@ -328,20 +356,23 @@ def main():
         "config": {"workload": "star schema: 1.5M PU keys, 15M orders, 60M fact rows "
                                f"({'shuffled' if args.shuffled else 'clustered by order'}), "
                                "6 groups, COUNT + SUM/AVG of 3 int64 cents columns, m=64, 42 released cells",
+                   "plan": {"mfma_kw": "orders' PU-key column hashed once per order, fact rows -> orders (1 link)",
+                            "plain_kw": "orders' PU-key column hashed once per order, fact rows -> orders (1 link)",
+                            "mfma_kv": "orders' PU-key column hashed per fact row, fact rows -> orders (1 link)",
+                            "plain_kv": "orders' PU-key column hashed per fact row, fact rows -> orders (1 link)"
+                            }.get(args.algo, "PU table's keys hashed, fact rows -> orders -> PU table (2 links)"),
                    "algo": args.algo},
-        "pipelined": bool(args.pipeline and args.algo != "mfma_kv"),
+        "pipelined": bool(args.pipeline),
         "ms_per_step_sequential": ms_step_seq,
         "step_latency_ms": ({"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                              "max": float(np.max(step_ms))} if step_ms else None),
         "aggregate_rows_per_s": n / (agg_ms * 1e-3),
         "graph": graph,
         "forms": {k: dict(v, aggregate_rows_per_s=n / (v["aggregate_ms"] * 1e-3),
-                          alg_bytes=alg_kv if k in ("mfma_kv", "mfma_kw") else alg_bytes,
-                          hbm_frac=round((alg_kv if k in ("mfma_kv", "mfma_kw") else alg_bytes)
-                                         / (v["aggregate_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                          step_hbm_frac=round((alg_kv if k in ("mfma_kv", "mfma_kw") else alg_bytes)
-                                              / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                          if "ms_per_step" in v else None)
+                          alg_bytes=alg_of.get(k, alg_bytes),
+                          hbm_frac=round(alg_of.get(k, alg_bytes) / (v["aggregate_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          step_hbm_frac=round(alg_of.get(k, alg_bytes) / (v["ms_per_step"] * 1e-3) / 1e9
+                                              / HBM_PEAK_GBS, 4) if "ms_per_step" in v else None)
                   for k, v in forms.items()},
         "roofline": roofline,
         "stream_read": dict(stream, frac_of_stream=round(achieved / stream["gbs"], 4)),
@@ -354,17 +385,19 @@ def main():
     ctx.close()
 
 
-def graph_measurement(args, P, ctx, pu_key, K, masks, spec, state, cells_t, n_cells, seed):
+def graph_measurement(args, P, ctx, K, plan, state, cells_t, n_cells, seed):
     """The step captured once as a HIP graph (hash, counter clearing by fill kernels, aggregation, release on
     the library's fixed memory) and replayed: launch overhead off the host; the same outputs as eagerly."""
     import torch
-    dev = masks.device
+    hkeys, words, spec, lib_algo = plan
+    dev = state["count"].device
     out = (torch.empty(n_cells, dtype=torch.float64, device=dev), torch.empty(n_cells, dtype=torch.uint8, device=dev),
            torch.empty(n_cells, dtype=torch.int32, device=dev), torch.empty(64, dtype=torch.float64, device=dev), None)
 
     def step():
-        P.pac_hash_mask(ctx, pu_key, K, 64, out=masks)
-        P.pac_group_aggregate(ctx, spec, state, m=64, query_key=K, algo=args.algo, init=True)
+        if hkeys is not None:
+            P.pac_hash_mask(ctx, hkeys, K, 64, out=words)
+        P.pac_group_aggregate(ctx, spec, state, m=64, query_key=K, algo=lib_algo, init=True)
         P.pac_finalize(ctx, state, cells_t, n_cells, m=64, mi_budget=1.0 / 128, noise_seed=seed, out=out,
                        no_alloc=True)
 

@@ -318,14 +318,16 @@ def test_config2_shuffled_full_size(ctx):
     compare_counters(got, star_oracle(t, K, 64, int_cols=ints))
 
 
-def test_config2_per_order_words_full_size(ctx, torch_mod):
-    """The 60M-row star schema with the orders' PU keys hashed into per-order words and one FK link."""
+@pytest.mark.parametrize("shuffled", [False, True])
+def test_config2_per_order_words_full_size(ctx, torch_mod, shuffled):
+    """The 60M-row star schema with the orders' PU keys hashed into per-order words and one FK link (the
+    benchmark's default plan), with the fact rows clustered by order and in random order."""
     import paper_2603_15023_amd as P
     from cases import order_keys
-    t = _config2()
+    t = gen.config2_star(shuffled=True) if shuffled else _config2()
     K = gen.query_key(1)
     dev = torch_mod.device("cuda")
-    _say("config2 per-order words")
+    _say("config2 per-order words", "shuffled" if shuffled else "clustered")
     omask = P.pac_hash_mask(ctx, torch_mod.from_numpy(order_keys(t)).to(dev), K, 64)
     ints = ["v1", "v2", "v3"]
     spec = P.AggSpec(n_rows=t.n_rows, masks=omask, links=[torch_mod.from_numpy(t.f_order).to(dev)],
