@@ -131,6 +131,13 @@ def main():
     omask = torch.empty((n_orders, 1), dtype=torch.int64, device=dev)
     spec_kw = P.AggSpec(n_rows=n, masks=omask, links=[links[0]], gcols=gcols, gcards=t.gcards, n_groups=6, cols=cols,
                         stats=stats)
+    if args.compare_steps > 0 and not args.shuffled:
+        # the shuffled fact rows of the comparison forms, generated before any timing starts
+        ts = gen.config2_star(shuffled=True)
+        s_order = torch.from_numpy(ts.f_order).to(dev)
+        s_g = [torch.from_numpy(g).to(dev) for g in ts.gcols]
+        s_c = [torch.from_numpy(ts.cols[c]).to(dev) for c in names]
+        del ts
     state = P.new_state(spec, 64)
     state2 = P.new_state(spec, 64)  # the second and third counter sets of the pipelined steps
     state3 = P.new_state(spec, 64)
@@ -236,7 +243,7 @@ def main():
             step(algo, evs[i])
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
-        agg_ms = [a.elapsed_time(b) for a, b in evs]
+        agg_ms = [a.elapsed_time(b) for a, b in evs] or [0.0]
         # single-step latency (issue to completion), measured after the timed region
         step_ms = []
         for _ in range(latency_steps):
@@ -244,27 +251,19 @@ def main():
             step(algo)
             torch.cuda.synchronize()
             step_ms.append((time.perf_counter() - s0) * 1e3)
-        return total * 1e3 / steps, float(np.mean(agg_ms)), step_ms
+        return total * 1e3 / max(steps, 1), float(np.mean(agg_ms)), step_ms
 
-    ms_step, agg_ms, step_ms = run(args.algo, args.steps, args.warmup, latency_steps=min(args.steps, 50))
-    ms_step_seq = ms_step
-    if args.pipeline:
-        ms_step, agg_ms = run_pipelined(args.steps, args.warmup)
-        log(f"pipelined: {ms_step:.3f} ms/step (sequential {ms_step_seq:.3f}), aggregate kernel {agg_ms:.3f} ms")
-
-    ctx.check()
-    log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
-    graph = graph_measurement(args, P, ctx, K, plan(args.algo), state, cells_t, len(cells), seed)
-
-    # the other GPU forms on the same inputs (same counters; checked in the tests): the plain per-bit form, the
-    # generic matrix-core kernel, the star kernel with the orders carrying their PU key
+    # The other GPU forms on the same inputs (same counters; checked in the tests): the plain per-bit form and
+    # the matrix-core kernels in every plan.  They run right before the headline, so that its W + K steps find
+    # the GPU at its sustained clocks rather than ramping up from idle.
     forms = {}
+    step(args.algo)  # the reference counters of the timed form
+    torch.cuda.synchronize()
     ref_state = {k: v.clone() for k, v in state.items()}
     for algo in ("plain", "plain_kv", "plain_kw", "mfma", "mfma_generic", "mfma_kv", "mfma_kw"):
         if args.compare_steps <= 0:
             break
         if algo == args.algo:
-            forms[algo] = {"ms_per_step": ms_step, "aggregate_ms": agg_ms}
             continue
         ms2, agg2, _ = run(algo, args.compare_steps, 1)
         same = all(torch.equal(state[k], ref_state[k]) for k in ("count", "isum", "nrows"))
@@ -273,11 +272,6 @@ def main():
     ctx.check()
     if args.compare_steps > 0 and not args.shuffled:
         # the stress layout of the FK chain: the same fact rows in random order (same counters)
-        ts = gen.config2_star(shuffled=True)
-        s_order = torch.from_numpy(ts.f_order).to(dev)
-        s_g = [torch.from_numpy(g).to(dev) for g in ts.gcols]
-        s_c = [torch.from_numpy(ts.cols[c]).to(dev) for c in names]
-        del ts
         for name, base, extra in (("mfma_shuffled", "mfma", [links[1]]), ("mfma_kv_shuffled", "mfma_kv", []),
                                   ("mfma_kw_shuffled", "mfma_kw", [])):
             hkeys, hout, sp0, lib_algo = plan(base)
@@ -300,6 +294,27 @@ def main():
             log(f"{base} on shuffled fact rows: aggregate {forms[name]['aggregate_ms']:.3f} ms, same {same}")
         del sspec, s_order, s_g, s_c
         ctx.check()
+
+    # Order: 100 single-step latency samples (issue to completion, the host waiting after each), then the K
+    # sequential steps and the K pipelined ones, each after its W warm-up steps, back to back.  The star kernel
+    # with the hash fused per row reaches its sustained clocks only after some 50 launches of its own load in a
+    # row (its first 20 launches take 0.45-0.6 ms, later ones 0.37-0.38 ms).
+    _, _, step_ms = run(args.algo, 0, 1, latency_steps=100)
+    ms_step, agg_ms, _ = run(args.algo, args.steps, args.warmup)
+    ms_step_seq = ms_step
+    if args.pipeline:
+        ms_step, agg_ms = run_pipelined(args.steps, args.warmup)
+        log(f"pipelined: {ms_step:.3f} ms/step (sequential {ms_step_seq:.3f}), aggregate kernel {agg_ms:.3f} ms")
+
+    ctx.check()
+    log(f"{args.algo}: {ms_step:.3f} ms/step, aggregate kernel {agg_ms:.3f} ms")
+    graph = graph_measurement(args, P, ctx, K, plan(args.algo), state, cells_t, len(cells), seed)
+
+    if args.compare_steps > 0:
+        forms[args.algo] = {"ms_per_step": ms_step, "aggregate_ms": agg_ms}
+        same = all(torch.equal(state[k], ref_state[k]) for k in ("count", "isum", "nrows"))
+        if not same:
+            raise RuntimeError("the timed form's counters differ from its reference step")
 
     if args.calibrate_copy_gib > 0:
         ne = int(args.calibrate_copy_gib * (1 << 30)) // 8
