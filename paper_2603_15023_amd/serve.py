@@ -9,7 +9,8 @@ The server keeps a fixed number of slots.  Each slot owns a library context
 (scratch and status word), a HIP stream and a PU-word buffer, so the work of
 different slots runs concurrently on the device.  Queries wait in arrival
 order; the head of the queue is admitted as soon as a slot is free and its
-counters fit in the counter pool (admission by counter memory), so queries
+counters fit in the counter pool, one device buffer allocated when the server
+starts and handed out in ranges (admission by counter memory), so queries
 that arrive while others are on the GPU join as resources free up instead of
 waiting for a batch to drain.  When the head's counters are small enough for
 the shared-scan launch, the small queries waiting behind it join it in the
@@ -30,7 +31,7 @@ import numpy as np
 import torch
 
 from . import _abi as A
-from .api import (AggSpec, Context, ReleaseRequest, new_state, pac_finalize, pac_finalize_batch,
+from .api import (AggSpec, Context, ReleaseRequest, pac_finalize, pac_finalize_batch,
                   pac_group_aggregate, pac_group_aggregate_batch, pac_hash_mask)
 
 CELL_DTYPE = np.dtype([("group", "<i8"), ("kind", "<i4"), ("col", "<i4")])
@@ -101,6 +102,36 @@ def counter_bytes(q, m: int = 64) -> int:
     return q.n_groups * ((1 + len(ints) + len(flts)) * m + 1) * 8
 
 
+STATE_ALIGN = 256  # bytes: every counter array of a carved state starts on this boundary
+
+
+def _padded(nbytes: int) -> int:
+    return (nbytes + STATE_ALIGN - 1) // STATE_ALIGN * STATE_ALIGN
+
+
+def region_bytes(q, m: int = 64) -> int:
+    """Pool bytes of the query's state: count, int sums, float sums and row counts, each array aligned."""
+    ints, flts = query_columns(q)
+    G = q.n_groups
+    return (_padded(G * m * 8) + _padded(G * len(ints) * m * 8) + _padded(G * len(flts) * m * 8)
+            + _padded(G * 8))
+
+
+def carve_state(pool: torch.Tensor, offset: int, q, m: int = 64) -> Dict[str, torch.Tensor]:
+    """The query's counter arrays as views of the int64 pool buffer, starting ``offset`` bytes in
+    (region_bytes(q) bytes; the same layout as new_state; PAC_AGG_INIT clears them)."""
+    ints, flts = query_columns(q)
+    G, ni, nf = q.n_groups, len(ints), len(flts)
+    out, o = {}, offset
+    for name, shape, dt in (("count", (G, m), torch.int64), ("isum", (G, ni, m), torch.int64),
+                            ("fsum", (G, nf, m), torch.float64), ("nrows", (G,), torch.int64)):
+        n = int(np.prod(shape))
+        w = pool[o // 8:o // 8 + n]
+        out[name] = (w.view(torch.float64) if dt == torch.float64 else w).view(shape)
+        o += _padded(n * 8)
+    return out
+
+
 def query_spec(table: ResidentStar, q, masks: Optional[torch.Tensor]) -> AggSpec:
     """The query's aggregation input: PU words from ``masks`` (this query's pac_hash_mask of the PU keys),
     or, with masks None, the PU keys hashed in the kernel with the query key."""
@@ -143,24 +174,67 @@ def pick_batch(queries: Sequence, waiting: Sequence[int], m: int = 64, max_batch
     return out
 
 
+class CounterPool:
+    """Byte ranges of one device buffer (host bookkeeping): first fit, free ranges kept sorted and coalesced."""
+
+    def __init__(self, size: int, align: int = STATE_ALIGN):
+        self.size, self.align = size, align
+        self.free = [(0, size)]  # (offset, bytes), ascending, never adjacent
+
+    def _round(self, n: int) -> int:
+        return max(self.align, (n + self.align - 1) // self.align * self.align)
+
+    def alloc(self, n: int) -> Optional[int]:
+        n = self._round(n)
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (o + n, sz - n)
+                return o
+        return None
+
+    def release(self, offset: int, n: int) -> None:
+        n = self._round(n)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < offset:
+            i += 1
+        self.free.insert(i, (offset, n))
+        if i + 1 < len(self.free) and offset + n == self.free[i + 1][0]:  # merge with the next range
+            self.free[i] = (offset, n + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == offset:  # and with the previous one
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    @property
+    def free_bytes(self) -> int:
+        return sum(sz for _, sz in self.free)
+
+
 class Admission:
-    """FIFO admission by free slots and counter memory (host logic only)."""
+    """FIFO admission by free slots and counter memory (host logic only): a query is admitted with a slot and
+    a range of the counter pool, or waits."""
 
     def __init__(self, n_slots: int, pool_bytes: int):
         self.free_slots = list(range(n_slots))[::-1]
         self.pool_bytes = pool_bytes
-        self.used = 0
+        self.pool = CounterPool(pool_bytes)
 
-    def try_admit(self, need: int) -> Optional[int]:
+    def try_admit(self, need: int) -> Optional[tuple]:
+        """(slot, pool offset), or None when no slot or no contiguous range of `need` bytes is free."""
         if need > self.pool_bytes:
             raise ValueError(f"query needs {need} counter bytes, pool holds {self.pool_bytes}")
-        if not self.free_slots or self.used + need > self.pool_bytes:
+        if not self.free_slots:
             return None
-        self.used += need
-        return self.free_slots.pop()
+        off = self.pool.alloc(need)
+        if off is None:
+            return None
+        return self.free_slots.pop(), off
 
-    def release(self, slot: int, need: int) -> None:
-        self.used -= need
+    def release(self, slot: int, offset: int, need: int) -> None:
+        self.pool.release(offset, need)
         self.free_slots.append(slot)
 
 
@@ -227,13 +301,15 @@ class Server:
         self.table, self.m, self.budget = table, m, mi_budget
         self.slots = [_Slot(device_index, table.pu_key.shape[0], m, max_cells, table.n_rows) for _ in range(n_slots)]
         self.n_slots, self.pool_bytes, self.max_batch = n_slots, pool_bytes, max_batch
+        # the counter pool: every admitted query's state is a range of it (no allocation for counters while serving)
+        self.pool = torch.empty(pool_bytes // 8, dtype=torch.int64, device=torch.device("cuda", device_index))
 
-    def _launch(self, slot: _Slot, q):
+    def _launch(self, slot: _Slot, q, offset: int):
         s = slot.stream
         with torch.cuda.stream(s):
             pac_hash_mask(slot.ctx, self.table.pu_key, q.query_key, self.m, out=slot.masks, stream=s)
             spec = query_spec(self.table, q, slot.masks)
-            state = new_state(spec, self.m)
+            state = carve_state(self.pool, offset, q, self.m)
             pac_group_aggregate(slot.ctx, spec, state, m=self.m, query_key=q.query_key, algo="auto", stream=s)
             n_cells = q.n_groups * len(q.aggs)
             if n_cells > slot.max_cells:
@@ -249,12 +325,15 @@ class Server:
         # device tensors stay referenced until completion
         return ev, [host], (state, cells_d, vals, nulls, flags)
 
-    def _launch_batch(self, slot: _Slot, qs: Sequence):
+    def _launch_batch(self, slot: _Slot, qs: Sequence, offset: int):
         """Several small queries in one slot: one shared-scan aggregation, one batched release."""
         s = slot.stream
         with torch.cuda.stream(s):
             specs = [query_spec(self.table, q, None) for q in qs]
-            states = [new_state(sp, self.m) for sp in specs]
+            states, o = [], offset
+            for q in qs:
+                states.append(carve_state(self.pool, o, q, self.m))
+                o += region_bytes(q, self.m)
             pac_group_aggregate_batch(slot.ctx, specs, states, [q.query_key for q in qs], m=self.m, stream=s)
             reqs, keep = [], []
             for q, st in zip(qs, states):
@@ -296,20 +375,21 @@ class Server:
                 nxt += 1
             while waiting:  # admit from the head while a slot and counter memory are free
                 group = pick_batch(queries, waiting, self.m, self.max_batch)
-                need = sum(counter_bytes(queries[i], self.m) for i in group)
-                slot_id = adm.try_admit(need)
-                if slot_id is None:
+                need = sum(region_bytes(queries[i], self.m) for i in group)
+                got = adm.try_admit(need)
+                if got is None:
                     break
+                slot_id, offset = got
                 for i in group:
                     waiting.remove(i)
                 if len(group) == 1:
-                    ev, hosts, keep = self._launch(self.slots[slot_id], queries[group[0]])
+                    ev, hosts, keep = self._launch(self.slots[slot_id], queries[group[0]], offset)
                 else:
-                    ev, hosts, keep = self._launch_batch(self.slots[slot_id], [queries[i] for i in group])
-                inflight[group[0]] = (slot_id, need, ev, hosts, keep, time.perf_counter() - t0, group)
-            done = [k for k, rec in inflight.items() if rec[2].query()]
+                    ev, hosts, keep = self._launch_batch(self.slots[slot_id], [queries[i] for i in group], offset)
+                inflight[group[0]] = (slot_id, offset, need, ev, hosts, keep, time.perf_counter() - t0, group)
+            done = [k for k, rec in inflight.items() if rec[3].query()]
             for k in done:
-                slot_id, need, ev, hosts, keep, t_adm, group = inflight.pop(k)
+                slot_id, offset, need, ev, hosts, keep, t_adm, group = inflight.pop(k)
                 t_done = time.perf_counter() - t0
                 st = self.slots[slot_id].ctx.status(self.slots[slot_id].stream)
                 for i, host in zip(group, hosts):
@@ -317,7 +397,7 @@ class Server:
                                                is_null=host[1].numpy().copy(), flags=host[2].numpy().copy(),
                                                status=st, arrival=float(arrivals[i]), admitted=t_adm, done=t_done,
                                                batch=len(group)))
-                adm.release(slot_id, need)
+                adm.release(slot_id, offset, need)
             if not done and poll_sleep:
                 time.sleep(poll_sleep)
         return results

@@ -7,17 +7,57 @@ from workloads import gen
 
 def test_admission_respects_slots_and_memory():
     from paper_2603_15023_amd.serve import Admission
-    a = Admission(n_slots=2, pool_bytes=100)
-    s0 = a.try_admit(60)
-    assert s0 is not None
-    assert a.try_admit(50) is None          # memory: 60 + 50 > 100
-    s1 = a.try_admit(40)
-    assert s1 is not None and s1 != s0
-    assert a.try_admit(1) is None           # no slot left
-    a.release(s0, 60)
-    assert a.try_admit(50) == s0
+    a = Admission(n_slots=2, pool_bytes=1024)
+    s0, o0 = a.try_admit(600)
+    assert o0 == 0
+    assert a.try_admit(500) is None          # memory: 768 (600 rounded to 256 B) + 500 > 1024
+    s1, o1 = a.try_admit(200)
+    assert s1 != s0 and o1 == 768
+    assert a.try_admit(1) is None            # no slot left
+    a.release(s0, o0, 600)
+    assert a.try_admit(500) == (s0, 0)
     with pytest.raises(ValueError):
-        a.try_admit(101)                    # can never fit
+        a.try_admit(1025)                    # can never fit
+
+
+def test_counter_pool_first_fit_and_coalescing():
+    from paper_2603_15023_amd.serve import CounterPool
+    p = CounterPool(4096)
+    offs = [p.alloc(1000) for _ in range(4)]          # 1024 each after rounding
+    assert offs == [0, 1024, 2048, 3072] and p.alloc(1) is None
+    p.release(1024, 1000)
+    p.release(3072, 1000)
+    assert p.free_bytes == 2048 and p.alloc(1500) is None   # free, but not contiguous: the query waits
+    p.release(2048, 1000)                             # joins both neighbours
+    assert p.free == [(1024, 3072)]
+    assert p.alloc(3000) == 1024
+    p.release(0, 1000)
+    p.release(1024, 3000)
+    assert p.free == [(0, 4096)]
+
+
+def test_carved_states_do_not_overlap():
+    import torch
+    from paper_2603_15023_amd.serve import carve_state, region_bytes
+    qs = [gen.ServedQuery(qid=i, filter_lt=1 << 30, n_groups=G, aggs=aggs, query_key=i, noise_seed=i, gap=1.0)
+          for i, (G, aggs) in enumerate([(3, [("sum", "v1"), ("avg", "vf")]), (7, [("count", None)]),
+                                         (1, [("sum", "v2"), ("sum", "v3"), ("avg", "vf")])])]
+    pool = torch.zeros(sum(region_bytes(q) for q in qs) // 8, dtype=torch.int64)
+    off, seen = 0, set()
+    for q in qs:
+        st = carve_state(pool, off, q)
+        assert st["count"].shape == (q.n_groups, 64) and st["nrows"].shape == (q.n_groups,)
+        assert st["fsum"].dtype == torch.float64
+        for name, t in st.items():
+            if t.numel() == 0:  # a query without int or float sums
+                continue
+            base = t.data_ptr() - pool.data_ptr()
+            assert base % 256 == 0
+            span = set(range(base, base + t.numel() * 8, 8))
+            assert not (span & seen), name
+            seen |= span
+        off += region_bytes(q)
+    assert max(seen) < pool.numel() * 8
 
 
 def test_query_cells_order_and_columns():
