@@ -895,6 +895,225 @@ __global__ __launch_bounds__(64 * kPartWavesNd) void part_aggregate(DevState st,
   }
 }
 
+// 4''. integer columns, sorted runs: each chunk of kSortChunk records of a work
+// item is counting-sorted by slot in LDS; then each wave walks 64 consecutive
+// sorted records (read at one LDS address for all lanes), keeping the current
+// slot's per-world count and sums in registers (lane = world), and adds them to
+// the partition's LDS counters only when the slot changes.  The counters take
+// one add per (run, counter word) instead of one per (record, counter word);
+// integer sums are exact in any order, so the result equals the other forms'.
+// The next chunk's records are loaded into registers while the current chunk
+// is walked, and workgroups of 8 waves leave room for two per CU.
+constexpr int kSortWaves = 8;
+constexpr int kSortChunk = 64 * kSortWaves;
+constexpr int kSortMaxSlots = 256;
+constexpr int kWalkBatch = 4;  // sorted records whose LDS reads are in flight together (8 measured no faster)
+
+static size_t sorted_stage_bytes(int W, int ni) {
+  return (size_t)kSortChunk * (8 * W + 8 * ni + 4) + 4 * kSortMaxSlots;
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int W, int NI>
+struct SortRec {
+  bool live;
+  uint32_t ls;
+  uint64_t mk[W], iv[NI > 0 ? NI : 1];
+  __device__ __forceinline__ void load(int64_t c0, int64_t end, int t, int64_t cap, const uint32_t *rec_slot,
+                                       const uint64_t *rec_mk, const uint64_t *rec_iv) {
+    live = c0 + t < end;
+    const int64_t i = live ? c0 + t : c0;  // a dead lane reads the chunk's first record and ignores it
+    ls = rec_slot[i];
+#pragma unroll
+    for (int w = 0; w < W; ++w) mk[w] = rec_mk[w * cap + i];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) iv[k] = rec_iv[k * cap + i];
+  }
+};
+
+template <int W, int NI>
+__global__ __launch_bounds__(64 * kSortWaves) void part_aggregate_sorted(
+    DevState st, int64_t n_slots, int SB, int64_t slot_words, int64_t cap, const uint32_t *rec_slot,
+    const uint64_t *rec_mk, const uint64_t *rec_iv, const PartItem *items, int64_t *meta) {
+  extern __shared__ uint64_t lds[];
+  __shared__ int64_t s_item;
+  constexpr int m = 64 * W, CI = NI > 0 ? NI : 1, R = kSortChunk, T = 64 * kSortWaves;
+  constexpr int A = 1 + NI;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+  const int64_t words = slot_words << SB;
+  const int nslot = 1 << SB;
+  uint64_t *s_mk = lds + words;                          // [W][R] PU words, sorted by slot
+  uint64_t *s_iv = s_mk + (size_t)W * R;                 // [NI][R] values, sorted by slot
+  uint32_t *s_sl = (uint32_t *)(s_iv + (size_t)NI * R);  // [R] slots, sorted
+  uint32_t *hist = s_sl + R;                             // [nslot] counts, then start positions
+  const int64_t n_items = meta[0];
+  for (;;) {
+    __syncthreads();
+    if (t == 0) s_item = atomicAdd((unsigned long long *)&meta[1], 1ull);
+    __syncthreads();
+    // the item is the same in every thread: its fields in scalar registers, so the loops below are uniform
+    const int64_t it = uniform_i64(s_item);
+    if (it >= n_items) break;  // every wave leaves
+    PartItem item = items[it];
+    item.part = uniform_i64(item.part);
+    item.begin = uniform_i64(item.begin);
+    item.end = uniform_i64(item.end);
+    for (int64_t i = t; i < words; i += T) lds[i] = 0;
+    SortRec<W, NI> rec;
+    if (item.begin < item.end) rec.load(item.begin, item.end, t, cap, rec_slot, rec_mk, rec_iv);
+    for (int64_t c0 = item.begin; c0 < item.end; c0 += R) {
+      const int n = (int)min<int64_t>(R, item.end - c0);
+      for (int i = t; i < nslot; i += T) hist[i] = 0;
+      __syncthreads();
+      // rank among the chunk's records of the slot; a wave whose records share one slot takes one add
+      uint32_t rank = 0;
+      const uint64_t lv = __ballot(rec.live);
+      if (lv) {
+        const int first = __ffsll((unsigned long long)lv) - 1;
+        const uint32_t s0 = __builtin_amdgcn_readlane(rec.ls, first);
+        if (__ballot(rec.live && rec.ls == s0) == lv) {
+          uint32_t b = 0;
+          if (lane == first) b = atomicAdd(&hist[s0], (uint32_t)__popcll(lv));
+          b = __builtin_amdgcn_readlane(b, first);
+          rank = b + (uint32_t)__popcll(lv & ((1ull << lane) - 1ull));
+        } else if (rec.live) {
+          rank = atomicAdd(&hist[rec.ls], 1u);
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {  // exclusive prefix sum of the counts: nslot <= 256, four per lane
+        uint32_t c[4], tot = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int b = 4 * lane + i;
+          c[i] = b < nslot ? hist[b] : 0u;
+          tot += c[i];
+        }
+        uint32_t inc = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t o = (uint32_t)__shfl_up((int)inc, d, 64);
+          if (lane >= d) inc += o;
+        }
+        uint32_t run = inc - tot;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int b = 4 * lane + i;
+          if (b < nslot) hist[b] = run;
+          run += c[i];
+        }
+      }
+      __syncthreads();
+      if (rec.live) {
+        const uint32_t pos = hist[rec.ls] + rank;
+        s_sl[pos] = rec.ls;
+#pragma unroll
+        for (int w = 0; w < W; ++w) s_mk[w * R + pos] = rec.mk[w];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) s_iv[k * R + pos] = rec.iv[k];
+      }
+      __syncthreads();
+      if (c0 + R < item.end) rec.load(c0 + R, item.end, t, cap, rec_slot, rec_mk, rec_iv);  // in flight meanwhile
+      // this wave's sorted records [p0, p1), read kWalkBatch at a time; runs of one slot summed in registers
+      const int p0 = __builtin_amdgcn_readfirstlane(64 * wave), p1 = min(n, p0 + 64);
+      if (p0 < p1) {
+        uint32_t cur = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_sl[p0]);
+        uint32_t cnt[W], nr = 0;
+        uint64_t sum[W][CI];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          cnt[w] = 0;
+#pragma unroll
+          for (int k = 0; k < CI; ++k) sum[w][k] = 0;
+        }
+        for (int pb = p0; pb < p1; pb += kWalkBatch) {
+          uint32_t sl4[kWalkBatch];
+          uint64_t mk4[kWalkBatch][W], v4[kWalkBatch][CI];
+#pragma unroll
+          for (int i = 0; i < kWalkBatch; ++i) {
+            const int p = min(pb + i, p1 - 1);  // past the end: re-read the last record, not used
+            sl4[i] = s_sl[p];
+#pragma unroll
+            for (int w = 0; w < W; ++w) mk4[i][w] = s_mk[w * R + p];
+#pragma unroll
+            for (int k = 0; k < NI; ++k) v4[i][k] = s_iv[k * R + p];
+          }
+#pragma unroll
+          for (int i = 0; i < kWalkBatch; ++i) {
+            if (pb + i >= p1) break;
+            const uint32_t sl = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl4[i]);
+            if (sl != cur) {  // the run of slot `cur` ends: its counters into LDS
+              uint64_t *base = lds + (int64_t)cur * slot_words;
+              if (lane == 0)
+                __hip_atomic_fetch_add(&base[(int64_t)A * m], (uint64_t)nr, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+              for (int w = 0; w < W; ++w) {
+                const int j = w * 64 + lane;
+                if (cnt[w]) {
+                  __hip_atomic_fetch_add(&base[j], (uint64_t)cnt[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+                  for (int k = 0; k < NI; ++k)
+                    __hip_atomic_fetch_add(&base[(int64_t)(1 + k) * m + j], sum[w][k], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                cnt[w] = 0;
+#pragma unroll
+                for (int k = 0; k < CI; ++k) sum[w][k] = 0;
+              }
+              nr = 0;
+              cur = sl;
+            }
+            ++nr;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              const bool bit = (mk4[i][w] >> lane) & 1ull;
+              cnt[w] += bit ? 1u : 0u;
+#pragma unroll
+              for (int k = 0; k < NI; ++k) sum[w][k] += bit ? v4[i][k] : 0ull;
+            }
+          }
+        }
+        {  // the last run
+          uint64_t *base = lds + (int64_t)cur * slot_words;
+          if (lane == 0)
+            __hip_atomic_fetch_add(&base[(int64_t)A * m], (uint64_t)nr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            const int j = w * 64 + lane;
+            if (cnt[w]) {
+              __hip_atomic_fetch_add(&base[j], (uint64_t)cnt[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+              for (int k = 0; k < NI; ++k)
+                __hip_atomic_fetch_add(&base[(int64_t)(1 + k) * m + j], sum[w][k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+        }
+      }
+      __syncthreads();  // the staging is rewritten by the next chunk
+    }
+    __syncthreads();  // (an item without records: the counters were just cleared)
+    // non-zero counters of this partition -> global state
+    for (int64_t i = t; i < words; i += T) {
+      const uint64_t v = lds[i];
+      if (!v) continue;
+      const int64_t g = (item.part << SB) + i / slot_words, o = i % slot_words;
+      if (g >= n_slots) continue;
+      const int a = o == (int64_t)A * m ? -1 : (int)(o / m), j = (int)(o % m);
+      unsigned long long *dst = a < 0   ? (unsigned long long *)&st.nrows[g]
+                                : a == 0 ? (unsigned long long *)&st.count[g * m + j]
+                                         : (unsigned long long *)&st.isum[(g * NI + (a - 1)) * m + j];
+      atomicAdd(dst, (unsigned long long)v);
+    }
+  }
+}
+
 // 4'. deterministic per-partition aggregation (float columns): wave w sums the
 // w-th quarter of the partition's records, in record order, into its own LDS
 // region (lane = world: no two lanes touch one word); the regions are then
@@ -1078,6 +1297,26 @@ static AggFn agg_fn(int ni) {
   }
 }
 
+using SortedFn = void (*)(DevState, int64_t, int, int64_t, int64_t, const uint32_t *, const uint64_t *,
+                          const uint64_t *, const PartItem *, int64_t *);
+
+static SortedFn sorted_fn(int W, int ni) {
+  if (W == 1) {
+    switch (ni) {
+      case 0: return part_aggregate_sorted<1, 0>;
+      case 1: return part_aggregate_sorted<1, 1>;
+      case 2: return part_aggregate_sorted<1, 2>;
+      default: return part_aggregate_sorted<1, 3>;
+    }
+  }
+  switch (ni) {
+    case 0: return part_aggregate_sorted<2, 0>;
+    case 1: return part_aggregate_sorted<2, 1>;
+    case 2: return part_aggregate_sorted<2, 2>;
+    default: return part_aggregate_sorted<2, 3>;
+  }
+}
+
 // Float columns present: the common small mixes keep their counters in
 // registers (det_reg_slots slots per partition); others use the LDS loop.
 template <int W>
@@ -1218,6 +1457,22 @@ hipError_t launch_agg_part(const LaunchEnv &env, const DevInput &in, const DevSt
     }
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // integer columns: the sorted-runs aggregate when its staging fits beside the counters
+  const size_t sorted_lds = (size_t)p.lds_bytes + sorted_stage_bytes(in.W, in.n_icols);
+  if (!p.det && in.n_icols <= 3 && p.SB <= 8 && sorted_lds + 64 <= 160 * 1024) {
+    const SortedFn sfn = sorted_fn(in.W, in.n_icols);
+    if ((e = hipFuncSetAttribute((const void *)sfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sorted_lds)) !=
+        hipSuccess)
+      return e;
+    int per_cu = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)sfn, 64 * kSortWaves,
+                                                          sorted_lds)) != hipSuccess)
+      return e;
+    const int grid = std::max(1, env.n_cu * std::max(1, per_cu));
+    hipLaunchKernelGGL(sfn, dim3(grid), dim3(64 * kSortWaves), sorted_lds, env.stream, st, p.n_slots, p.SB,
+                       p.slot_words, p.cap, rec_slot, rec_mk, rec_iv, items, meta);
+    return hipGetLastError();
+  }
   const AggFn afn = p.det ? nullptr : (in.W == 1 ? agg_fn<1>(in.n_icols) : agg_fn<2>(in.n_icols));
   const AggDetFn dfn = p.det ? (in.W == 1 ? agg_det_fn<1>(in.n_icols, in.n_fcols) : agg_det_fn<2>(in.n_icols, in.n_fcols))
                              : nullptr;
