@@ -487,17 +487,30 @@ def serve_measurement(args):
     srv = Server(table, n_slots=args.serve_slots)
     srv.run(qs[:min(8, len(qs))])  # warm-up
     closed = latency_summary(srv.run(qs))
-    rate = args.serve_load * closed["qps"]
-    gaps = np.array([q.gap for q in qs]) / rate
-    opened = latency_summary(srv.run(qs, arrivals=np.cumsum(gaps) - gaps[0]))
+    gaps = np.array([q.gap for q in qs])
+
+    def open_loop(load):
+        rate = load * closed["qps"]
+        g = gaps / rate
+        return rate, latency_summary(srv.run(qs, arrivals=np.cumsum(g) - g[0]))
+
+    rate, opened = open_loop(args.serve_load)
+    others = {}
+    for load in (0.5, 0.9):  # the lighter and heavier loads beside the main one
+        if abs(load - args.serve_load) > 1e-9:
+            r, o = open_loop(load)
+            others[f"{load:g}"] = {"arrival_qps": r, "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
+                                   "max_ms": o["max_ms"], "qps": o["qps"]}
     srv.close()
     log(f"serving: saturation {closed['qps']:.1f} QPS; at {args.serve_load:.1f}x: p50 {opened['p50_ms']:.1f} ms, "
-        f"p99 {opened['p99_ms']:.1f} ms")
+        f"p99 {opened['p99_ms']:.1f} ms; " +
+        "; ".join(f"at {k}x: p50 {v['p50_ms']:.1f} ms, p99 {v['p99_ms']:.1f} ms" for k, v in others.items()))
     return {"workload": "served star: 100M fact rows, 2.5M PU, 25M orders; filter 0.1%-50%, 1-1e5 groups, "
                         "1-3 COUNT/SUM/AVG over int64/FP64, m=64",
             "queries": len(qs), "slots": args.serve_slots, "saturation_qps": closed["qps"],
+            "saturation_rows_queries_per_s": closed["qps"] * table.n_rows,
             "load": args.serve_load, "arrival_qps": rate, "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"],
-            "max_ms": opened["max_ms"], "qps": opened["qps"]}
+            "max_ms": opened["max_ms"], "qps": opened["qps"], "other_loads": others}
 
 
 def cpu_baseline(t, K, target_s):
