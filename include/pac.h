@@ -52,7 +52,10 @@ extern "C" {
 typedef struct pac_ctx pac_ctx;
 
 /* One context per (device, host thread).  Creates the device status word and
- * a scratch pool on device `hip_device`.  Not thread-safe. */
+ * a scratch pool on device `hip_device`.  Not thread-safe.  Calls through one
+ * context must not run at the same time on the device (work on several
+ * streams): they share its scratch pool, so each stream whose work may
+ * overlap another's gets its own context. */
 int pac_ctx_create(int hip_device, pac_ctx **out);
 int pac_ctx_destroy(pac_ctx *ctx);
 /* Grows the context's device scratch pool to at least `bytes` now.  Calls

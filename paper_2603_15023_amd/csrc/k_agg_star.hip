@@ -45,52 +45,58 @@ struct StarPlan {
   int32_t flush_tiles;
 };
 
-// Wave-private staging of one tile, field-major ([field][lane]).
+// Wave-private staging of one tile, field-major ([field][lane]).  The PU
+// words stay in registers (see QChain).
 template <int NGC, int NI>
 struct StarStage {
-  uint64_t mk[256];      // PU words by plane position (qrow order)
   uint32_t g[NGC][64];   // group bytes of rows qrow(lane, 0..3)
   uint32_t v[NI][4][64]; // low 32 bits of the values of row qrow(lane, i)
   uint32_t rv[64];       // non-zero: a value of one of the lane's rows lies outside the statistics
 };
 
-// FK chain of the four rows qrow(lane, 0..3) of a tile: table indices
-// and validity.  Every load is unconditional: an invalid row reads index 0 of
-// the (non-empty) table and stays marked invalid; a foreign key outside its
-// table also raises PAC_STATUS_BAD_LINK.
+// Row order inside a tile.  Lane l handles the rows 2l, 2l + 1, 128 + 2l and
+// 129 + 2l of the value and group columns, so that every column load of the
+// wave reads one contiguous stretch of the column; those rows sit at
+// positions 4l .. 4l + 3 of the byte planes (the contraction only needs the
+// two operands to agree on the order).
+__device__ __forceinline__ uint32_t qrow(int lane, int j) {
+  return (j < 2 ? 0u : 128u) + 2u * lane + (uint32_t)(j & 1);
+}
+
+// The row at plane position 64 u + l, whose PU word lane l holds for K-chunk
+// u of the contraction: qrow(16 u + l / 4, l mod 4).
+__device__ __forceinline__ uint32_t wrow(int lane, int u) {
+  return ((lane & 2) ? 128u : 0u) + 32u * u + 2u * (uint32_t)(lane >> 2) + (uint32_t)(lane & 1);
+}
+
+// FK chain of the four rows wrow(lane, 0..3) of a tile: table indices and
+// validity.  Every load is unconditional: an invalid row reads index 0 of the
+// (non-empty) table and stays marked invalid; a foreign key outside its
+// table also raises PAC_STATUS_BAD_LINK.  The words found at the end of the
+// chain stay in the lane's registers, already in the order of the A operand
+// (no staging through LDS).
 struct QChain {
   uint32_t idx[4];
   uint32_t ok[4];
 };
 
-// Row order inside a tile.  Lane l handles the rows 2l, 2l + 1, 128 + 2l and
-// 129 + 2l, so that every column load of the wave reads one contiguous
-// stretch of the column; those rows sit at positions 4l .. 4l + 3 of the
-// byte planes and of the staged PU words (the contraction only needs the two
-// operands to agree on the order).
-__device__ __forceinline__ uint32_t qrow(int lane, int j) {
-  return (j < 2 ? 0u : 128u) + 2u * lane + (uint32_t)(j & 1);
-}
-
-// First link of a full tile: the four foreign keys in two 8-byte loads.
+// First link of a full tile: each load of the wave reads two runs of 32
+// consecutive foreign keys.
 __device__ __forceinline__ void qchain_first(const MfmaArgs &a, uint32_t row0, int lane, QChain &c) {
-  const v2u32 f0 = __builtin_nontemporal_load((const v2u32 *)(a.links[0] + row0 + 2 * lane));
-  const v2u32 f1 = __builtin_nontemporal_load((const v2u32 *)(a.links[0] + row0 + 128 + 2 * lane));
-  c.idx[0] = f0[0];
-  c.idx[1] = f0[1];
-  c.idx[2] = f1[0];
-  c.idx[3] = f1[1];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) c.ok[j] = 1u;
+  for (int u = 0; u < 4; ++u) {
+    c.idx[u] = (uint32_t)__builtin_nontemporal_load(a.links[0] + row0 + wrow(lane, u));
+    c.ok[u] = 1u;
+  }
 }
 
 // First link of a partial tile (rows >= n invalid).
 __device__ __forceinline__ void qchain_first_tail(const MfmaArgs &a, uint32_t row0, int lane, QChain &c) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t r = row0 + qrow(lane, j);
-    c.ok[j] = r < a.n_rows && r < a.link_len[0];
-    c.idx[j] = (uint32_t)a.links[0][c.ok[j] ? r : 0u];
+  for (int u = 0; u < 4; ++u) {
+    const uint32_t r = row0 + wrow(lane, u);
+    c.ok[u] = r < a.n_rows && r < a.link_len[0];
+    c.idx[u] = (uint32_t)a.links[0][c.ok[u] ? r : 0u];
   }
 }
 
@@ -166,7 +172,7 @@ __device__ __forceinline__ uint32_t star_transpose(uint32_t x, const StarTc &tc)
   return x;
 }
 
-// PU words (KV = 0, 2) or PU keys (KV = 1, hashed when staged) of the four rows.
+// PU words (KV = 0, 2) or PU keys (KV = 1, hashed by star_words) of the four rows wrow(lane, 0..3).
 template <int KV, int NGC, int NI>
 __device__ __forceinline__ void star_issue_words(const MfmaArgs &a, const QChain &c, StarRaw<NGC, NI> &r,
                                                  uint32_t *status) {
@@ -239,14 +245,19 @@ __device__ __forceinline__ void star_issue_cols_tail(const MfmaArgs &a, const St
   r.rv = rv;
 }
 
+// The A-operand words of a staged tile: word u is the PU word of row
+// wrow(lane, u) (hashed here for KV = 1), zero for an invalid row.
 template <int KV, int NGC, int NI>
-__device__ __forceinline__ void star_stage_store(const MfmaArgs &a, StarStage<NGC, NI> *sg, int lane,
-                                                 const StarRaw<NGC, NI> &r) {
+__device__ __forceinline__ void star_words(const MfmaArgs &a, const StarRaw<NGC, NI> &r, uint64_t (&wk)[4]) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint64_t w = KV == 1 ? pu_word((int64_t)r.mk[j], a.qk, 0, a.balanced != 0) : r.mk[j];
-    sg->mk[4 * lane + j] = r.ok[j] ? w : 0ull;
+  for (int u = 0; u < 4; ++u) {
+    const uint64_t w = KV == 1 ? pu_word((int64_t)r.mk[u], a.qk, 0, a.balanced != 0) : r.mk[u];
+    wk[u] = r.ok[u] ? w : 0ull;
   }
+}
+
+template <int NGC, int NI>
+__device__ __forceinline__ void star_stage_store(StarStage<NGC, NI> *sg, int lane, const StarRaw<NGC, NI> &r) {
 #pragma unroll
   for (int k = 0; k < NGC; ++k) sg->g[k][lane] = r.g[k];
 #pragma unroll
@@ -339,12 +350,10 @@ __device__ __forceinline__ void star_planes(const MfmaArgs &a, const StarPlan &p
   }
 }
 
-// A operands of K-chunk u: M-tile 2 dw + h holds the worlds of word half dw
-// whose transposed bit sits in nibble half h (scaled by 16^h).
-template <int NGC, int NI>
-__device__ __forceinline__ void star_a(const StarStage<NGC, NI> *sg, int lane, int u, const StarTc &tc,
-                                       v4i (&av)[4]) {
-  const uint64_t word = sg->mk[64 * u + lane];
+// A operands of K-chunk u from the lane's word of plane position 64 u + lane:
+// M-tile 2 dw + h holds the worlds of word half dw whose transposed bit sits
+// in nibble half h (scaled by 16^h).
+__device__ __forceinline__ void star_a(uint64_t word, const StarTc &tc, v4i (&av)[4]) {
 #pragma unroll
   for (int dw = 0; dw < 2; ++dw) {
     const uint32_t t0 = star_transpose((uint32_t)(word >> (32 * dw)), tc);
@@ -370,13 +379,12 @@ __device__ __forceinline__ void star_b(const uint8_t *planes, int roff, const in
 // The four K-chunks of a tile, software-pipelined: the B rows of chunk u + 1
 // are read and the A operands of chunk u + 1 built while the matrix cores
 // work on chunk u.
-template <int NGC, int NI, int NT>
-__device__ __forceinline__ void star_mfma(const StarStage<NGC, NI> *sg, int lane, const uint8_t *planes,
-                                          const int (&boff_d)[NT], const int (&boff_g)[NT], const StarTc &tc,
-                                          int q, v4i (&acc)[4][NT]) {
+template <int NT>
+__device__ __forceinline__ void star_mfma(const uint64_t (&wk)[4], const uint8_t *planes, const int (&boff_d)[NT],
+                                          const int (&boff_g)[NT], const StarTc &tc, int q, v4i (&acc)[4][NT]) {
   v4i av[2][4], bd[2][NT], bg[2][NT];
   star_b<NT>(planes, 16 * q, boff_d, boff_g, bd[0], bg[0]);
-  star_a(sg, lane, 0, tc, av[0]);
+  star_a(wk[0], tc, av[0]);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int c = u & 1, n = c ^ 1;
@@ -388,7 +396,7 @@ __device__ __forceinline__ void star_mfma(const StarStage<NGC, NI> *sg, int lane
       for (int mt = 0; mt < 4; ++mt)
         acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[c][mt], b, acc[mt][nt], 0, 0, 0);
     }
-    if (u < 3) star_a(sg, lane, u + 1, tc, av[n]);
+    if (u < 3) star_a(wk[u + 1], tc, av[n]);
   }
 }
 
@@ -475,62 +483,75 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
 
-  // Tiles go to the waves in groups of kStarTPI consecutive tiles; the loads
-  // of the next group (kStarTPI tiles of columns and PU words) are in flight
-  // while the current group is contracted, so each wave keeps several tiles
-  // of HBM traffic outstanding.
+  // Tiles go to the waves in groups of kStarTPI consecutive tiles, group g to
+  // wave g mod stride; the loads of the next group (kStarTPI tiles of columns
+  // and PU words) are in flight while the current group is contracted, and
+  // the foreign keys of the two groups after it before that, so each wave
+  // keeps several tiles of HBM traffic outstanding.
   const uint32_t n_full = a.n_rows / kTileRows;
   const uint32_t n_grp = n_full / kStarTPI;
   const uint32_t stride = gridDim.x * kStarWPB;
   const uint32_t first = blockIdx.x * kStarWPB + wave;
-  if (first < n_grp) {
+  uint32_t g0 = first;
+  if (g0 < n_grp) {
     const uint32_t last = n_grp - 1;
     auto clampg = [&](uint32_t g) { return g < n_grp ? g : last; };
     auto row_of = [&](uint32_t g, int k) { return (g * kStarTPI + k) * kTileRows; };
-    uint32_t gi = first;
+    uint64_t wk[kStarTPI][4];  // A-operand words of the staged tiles
 #pragma unroll
-    for (int k = 0; k < kStarTPI; ++k) {  // prologue: stage group `first`
+    for (int k = 0; k < kStarTPI; ++k) {  // prologue: stage group g0
       StarRaw<NGC, NI> r;
       QChain c;
-      qchain_first(a, row_of(gi, k), lane, c);
+      qchain_first(a, row_of(g0, k), lane, c);
       if (KV == 0) qchain_next(a, c, status);
       star_issue_words<KV>(a, c, r, status);
-      star_issue_cols(a, pl, row_of(gi, k), lane, r);
-      star_stage_store<KV>(a, stage + k, lane, r);
+      star_issue_cols(a, pl, row_of(g0, k), lane, r);
+      star_stage_store(stage + k, lane, r);
+      star_words<KV>(a, r, wk[k]);
     }
-    QChain l1[kStarTPI], l0[kStarTPI];  // group + stride after both links, group + 2 stride after the first
+    // g1: the next group (after both links), g2 the one after it (after the
+    // first link); a group >= n_grp is past the end (its loads read the last
+    // group and are never used)
+    uint32_t g1 = g0 + stride, g2 = g1 + stride;
+    QChain l1[kStarTPI], l0[kStarTPI];
 #pragma unroll
     for (int k = 0; k < kStarTPI; ++k) {
-      qchain_first(a, row_of(clampg(gi + stride), k), lane, l1[k]);
+      qchain_first(a, row_of(clampg(g1), k), lane, l1[k]);
       if (KV == 0) qchain_next(a, l1[k], status);
-      qchain_first(a, row_of(clampg(gi + 2 * stride), k), lane, l0[k]);
+      qchain_first(a, row_of(clampg(g2), k), lane, l0[k]);
     }
-    for (; gi < n_grp; gi += stride) {
+    while (true) {
       StarRaw<NGC, NI> r[kStarTPI];
       QChain n1[kStarTPI];
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         star_issue_words<KV>(a, l1[k], r[k], status);
-        star_issue_cols(a, pl, row_of(clampg(gi + stride), k), lane, r[k]);
+        star_issue_cols(a, pl, row_of(clampg(g1), k), lane, r[k]);
       }
+      const uint32_t g3 = g2 + stride;
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         n1[k] = l0[k];
         if (KV == 0) qchain_next(a, n1[k], status);
-        qchain_first(a, row_of(clampg(gi + 3 * stride), k), lane, l0[k]);
+        qchain_first(a, row_of(clampg(g3), k), lane, l0[k]);
       }
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
-        star_planes<NGC, NI, DIG>(a, pl, stage + k, row_of(gi, k), false, planes, lane, gcnt, status);
+        star_planes<NGC, NI, DIG>(a, pl, stage + k, row_of(g0, k), false, planes, lane, gcnt, status);
         wave_lds_fence();
-        star_mfma<NGC, NI, NT>(stage + k, lane, planes, boff_d, boff_g, tc, q, acc);
+        star_mfma<NT>(wk[k], planes, boff_d, boff_g, tc, q, acc);
         wave_lds_fence();
       }
+      if (g1 >= n_grp) break;
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
-        star_stage_store<KV>(a, stage + k, lane, r[k]);
+        star_stage_store(stage + k, lane, r[k]);
+        star_words<KV>(a, r[k], wk[k]);
         l1[k] = n1[k];
       }
+      g0 = g1;
+      g1 = g2;
+      g2 = g3;
     }
   }
   // tiles after the last full group (at most kStarTPI - 1 full ones and a
@@ -545,10 +566,12 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
     if (KV == 0) qchain_next(a, c, status);
     star_issue_words<KV>(a, c, r, status);
     star_issue_cols_tail(a, pl, row0, lane, r);
-    star_stage_store<KV>(a, stage, lane, r);
+    star_stage_store(stage, lane, r);
+    uint64_t wt[4];
+    star_words<KV>(a, r, wt);
     star_planes<NGC, NI, DIG>(a, pl, stage, row0, true, planes, lane, gcnt, status);
     wave_lds_fence();
-    star_mfma<NGC, NI, NT>(stage, lane, planes, boff_d, boff_g, tc, q, acc);
+    star_mfma<NT>(wt, planes, boff_d, boff_g, tc, q, acc);
     wave_lds_fence();
   }
   star_flush<NI, DIG, NT>(acc, planes, blk, pl, lane);
@@ -594,8 +617,8 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   const int64_t lim = (int64_t)1 << 31;
   for (int k = 0; k < in.n_links; ++k)
     if (in.link_len[k] < 1 || in.link_len[k] >= lim) return false;
-  // full tiles read the first link four keys at a time, unchecked
-  if (in.link_len[0] < in.n_rows || ((uintptr_t)in.links[0] & 15u)) return false;
+  // full tiles read the first link without bounds checks
+  if (in.link_len[0] < in.n_rows) return false;
   const int64_t n_idx = kv ? in.n_pu_keys : in.n_masks;
   if (n_idx < 1 || n_idx >= lim) return false;
   for (int k = 0; k < in.n_gcols; ++k)
@@ -623,7 +646,7 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   const int planes_bytes = p.n_planes * kPlaneStride;
   const int flush_bytes = 16 * NT * 16 * 4;
   p.stage_off = (std::max(planes_bytes, flush_bytes) + 15) & ~15;
-  const int stage_bytes = 64 * (8 * 4 + 4 * in.n_gcols + 16 * in.n_icols + 4);
+  const int stage_bytes = 64 * (4 * in.n_gcols + 16 * in.n_icols + 4);
   p.wave_bytes = (p.stage_off + kStarTPI * stage_bytes + 15) & ~15;
   p.blk_off = kStarWPB * p.wave_bytes;
   p.blk_words = (int)G * (1 + in.n_icols) * 64 + (int)G;
@@ -641,7 +664,7 @@ bool star_supported(const DevInput &in) {
 
 template <int KV, int NGC, int NI, int DIG, int NT>
 static hipError_t launch_star_t(const LaunchEnv &env, const DevInput &in, const DevState &st, const StarPlan &pl) {
-  static_assert(sizeof(StarStage<NGC, NI>) == 64 * (8 * 4 + 4 * NGC + 16 * NI + 4), "stage");
+  static_assert(sizeof(StarStage<NGC, NI>) == 64 * (4 * NGC + 16 * NI + 4), "stage");
   const int lds = pl.blk_off + pl.blk_words * 8;
   const void *fn = (const void *)agg_star<KV, NGC, NI, DIG, NT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
