@@ -356,11 +356,13 @@ __device__ __forceinline__ void release_chain(const FinParams &fp, int64_t c0, i
                   ey += fuse ? e[w] * s_y[buf][i + 1][lane + 64 * w] : 0.0;
                 }
                 wave_sum2(se, ey);
-                const double lse = mx + log(se);
+                // L keeps the log posterior up to a constant (shifted so that its maximum is 0): the
+                // constant cancels when the next cell subtracts its own maximum, so no logarithm of the
+                // normaliser is needed per cell
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
                   P[w] = e[w] / se;
-                  L[w] = P[w] > 0.0 ? l[w] - lse : -INFINITY;  // an underflowed world stays at zero
+                  L[w] = P[w] > 0.0 ? l[w] - mx : -INFINITY;  // an underflowed world stays at zero
                 }
                 mu_next = ey / se;
                 have_mu = fuse;
