@@ -138,9 +138,22 @@ def main():
         s_g = [torch.from_numpy(g).to(dev) for g in ts.gcols]
         s_c = [torch.from_numpy(ts.cols[c]).to(dev) for c in names]
         del ts
-    state = P.new_state(spec, 64)
-    state2 = P.new_state(spec, 64)  # the second and third counter sets of the pipelined steps
-    state3 = P.new_state(spec, 64)
+
+    def flat_state():
+        """The counters of new_state as views of one int64 buffer (each array 256-byte aligned), so that one
+        fill kernel clears them all."""
+        G, ni, m = 6, 3, 64
+        pad = lambda k: (k + 31) // 32 * 32  # 32 int64 = 256 bytes
+        o_isum = pad(G * m)
+        o_nrows = o_isum + pad(G * ni * m)
+        flat = torch.empty(o_nrows + pad(G), dtype=torch.int64, device=dev)
+        return flat, {"count": flat[:G * m].view(G, m), "isum": flat[o_isum:o_isum + G * ni * m].view(G, ni, m),
+                      "fsum": torch.empty((G, 0, m), dtype=torch.float64, device=dev),
+                      "nrows": flat[o_nrows:o_nrows + G]}
+
+    flat1, state = flat_state()
+    flat2, state2 = flat_state()  # the second and third counter sets of the pipelined steps
+    flat3, state3 = flat_state()
     cells = []
     for g in range(6):
         cells.append((g, P._abi.PAC_CELL_COUNT, 0))
@@ -164,8 +177,7 @@ def main():
         hkeys, hout, sp, lib_algo = plan(algo)
         if hkeys is not None:
             P.pac_hash_mask(ctx, hkeys, K, 64, out=hout)
-        for v in state.values():  # counters start at zero (fill kernels, outside the event bracket)
-            v.zero_()
+        flat1.zero_()  # counters start at zero (one fill kernel, outside the event bracket)
         if ev is not None:
             ev[0].record(stream)
         P.pac_group_aggregate(ctx, sp, state, m=64, query_key=K, algo=lib_algo, init=False)
@@ -184,6 +196,7 @@ def main():
     ctx_prep, ctx_rel = P.Context(0), P.Context(0)
     s_prep, s_rel = torch.cuda.Stream(), torch.cuda.Stream()
     sets = [state, state2, state3]
+    flats = [flat1, flat2, flat3]
     p_keys, p_words, p_spec, p_algo = plan(args.algo)
     if p_words is not None:
         mask_sets = [p_words] + [torch.empty_like(p_words) for _ in range(n_buf - 1)]
@@ -203,8 +216,7 @@ def main():
         with torch.cuda.stream(s_prep):
             if p_keys is not None:
                 P.pac_hash_mask(ctx_prep, p_keys, K, 64, out=mask_sets[b])
-            for v in st.values():
-                v.zero_()
+            flats[b].zero_()
             ev_prep[b].record(s_prep)
         stream.wait_event(ev_prep[b])
         if ev is not None:
@@ -271,8 +283,7 @@ def main():
             for i in range(args.compare_steps + 1):
                 if hkeys is not None:
                     P.pac_hash_mask(ctx, hkeys, K, 64, out=hout)
-                for v in state.values():
-                    v.zero_()
+                flat1.zero_()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 P.pac_group_aggregate(ctx, sspec, state, m=64, query_key=K, algo=lib_algo, init=False)
