@@ -46,12 +46,16 @@ struct StarPlan {
 };
 
 // Wave-private staging of one tile, field-major ([field][lane]).  The PU
-// words stay in registers (see QChain).
-template <int NGC, int NI>
+// words stay in registers (see QChain), except in the variants with six
+// column tiles (MK), whose accumulators leave no room for them: there lane l
+// gathers the words of rows qrow(l, 0..3) and stages them here at plane
+// positions 4 l .. 4 l + 3.
+template <int NGC, int NI, bool MK>
 struct StarStage {
   uint32_t g[NGC][64];   // group bytes of rows qrow(lane, 0..3)
   uint32_t v[NI][4][64]; // low 32 bits of the values of row qrow(lane, i)
   uint32_t rv[64];       // non-zero: a value of one of the lane's rows lies outside the statistics
+  uint64_t mk[MK ? 256 : 1];
 };
 
 // Row order inside a tile.  Lane l handles the rows 2l, 2l + 1, 128 + 2l and
@@ -69,7 +73,8 @@ __device__ __forceinline__ uint32_t wrow(int lane, int u) {
   return ((lane & 2) ? 128u : 0u) + 32u * u + 2u * (uint32_t)(lane >> 2) + (uint32_t)(lane & 1);
 }
 
-// FK chain of the four rows wrow(lane, 0..3) of a tile: table indices and
+// FK chain of the four rows of a tile that the lane gathers words for
+// (wrow(lane, 0..3), or qrow(lane, 0..3) with MK): table indices and
 // validity.  Every load is unconditional: an invalid row reads index 0 of the
 // (non-empty) table and stays marked invalid; a foreign key outside its
 // table also raises PAC_STATUS_BAD_LINK.  The words found at the end of the
@@ -81,20 +86,33 @@ struct QChain {
 };
 
 // First link of a full tile: each load of the wave reads two runs of 32
-// consecutive foreign keys.
+// consecutive foreign keys (with MK: the lane's four keys in two 8-byte loads).
+template <bool MK>
 __device__ __forceinline__ void qchain_first(const MfmaArgs &a, uint32_t row0, int lane, QChain &c) {
+  if constexpr (MK) {
+    const v2u32 f0 = __builtin_nontemporal_load((const v2u32 *)(a.links[0] + row0 + 2 * lane));
+    const v2u32 f1 = __builtin_nontemporal_load((const v2u32 *)(a.links[0] + row0 + 128 + 2 * lane));
+    c.idx[0] = f0[0];
+    c.idx[1] = f0[1];
+    c.idx[2] = f1[0];
+    c.idx[3] = f1[1];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    c.idx[u] = (uint32_t)__builtin_nontemporal_load(a.links[0] + row0 + wrow(lane, u));
-    c.ok[u] = 1u;
+    for (int j = 0; j < 4; ++j) c.ok[j] = 1u;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c.idx[u] = (uint32_t)__builtin_nontemporal_load(a.links[0] + row0 + wrow(lane, u));
+      c.ok[u] = 1u;
+    }
   }
 }
 
 // First link of a partial tile (rows >= n invalid).
+template <bool MK>
 __device__ __forceinline__ void qchain_first_tail(const MfmaArgs &a, uint32_t row0, int lane, QChain &c) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const uint32_t r = row0 + wrow(lane, u);
+    const uint32_t r = row0 + (MK ? qrow(lane, u) : wrow(lane, u));
     c.ok[u] = r < a.n_rows && r < a.link_len[0];
     c.idx[u] = (uint32_t)a.links[0][c.ok[u] ? r : 0u];
   }
@@ -172,7 +190,7 @@ __device__ __forceinline__ uint32_t star_transpose(uint32_t x, const StarTc &tc)
   return x;
 }
 
-// PU words (KV = 0, 2) or PU keys (KV = 1, hashed by star_words) of the four rows wrow(lane, 0..3).
+// PU words (KV = 0, 2) or PU keys (KV = 1, hashed by star_words) of the lane's four rows.
 template <int KV, int NGC, int NI>
 __device__ __forceinline__ void star_issue_words(const MfmaArgs &a, const QChain &c, StarRaw<NGC, NI> &r,
                                                  uint32_t *status) {
@@ -245,19 +263,24 @@ __device__ __forceinline__ void star_issue_cols_tail(const MfmaArgs &a, const St
   r.rv = rv;
 }
 
-// The A-operand words of a staged tile: word u is the PU word of row
-// wrow(lane, u) (hashed here for KV = 1), zero for an invalid row.
-template <int KV, int NGC, int NI>
-__device__ __forceinline__ void star_words(const MfmaArgs &a, const StarRaw<NGC, NI> &r, uint64_t (&wk)[4]) {
+// The A-operand words of a staged tile (hashed here for KV = 1), zero for an
+// invalid row: word u of row wrow(lane, u) kept in wk, or (MK) the words of
+// rows qrow(lane, 0..3) staged at plane positions 4 lane .. 4 lane + 3.
+template <int KV, int NGC, int NI, bool MK>
+__device__ __forceinline__ void star_words(const MfmaArgs &a, const StarRaw<NGC, NI> &r, StarStage<NGC, NI, MK> *sg,
+                                           int lane, uint64_t (&wk)[4]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const uint64_t w = KV == 1 ? pu_word((int64_t)r.mk[u], a.qk, 0, a.balanced != 0) : r.mk[u];
-    wk[u] = r.ok[u] ? w : 0ull;
+    if constexpr (MK)
+      sg->mk[4 * lane + u] = r.ok[u] ? w : 0ull;
+    else
+      wk[u] = r.ok[u] ? w : 0ull;
   }
 }
 
-template <int NGC, int NI>
-__device__ __forceinline__ void star_stage_store(StarStage<NGC, NI> *sg, int lane, const StarRaw<NGC, NI> &r) {
+template <int NGC, int NI, bool MK>
+__device__ __forceinline__ void star_stage_store(StarStage<NGC, NI, MK> *sg, int lane, const StarRaw<NGC, NI> &r) {
 #pragma unroll
   for (int k = 0; k < NGC; ++k) sg->g[k][lane] = r.g[k];
 #pragma unroll
@@ -274,8 +297,8 @@ __device__ __forceinline__ uint32_t bytes_ge(uint32_t w, uint32_t card_rep) {
 
 // Byte planes of the staged tile: digits, then (after the ones and zeros
 // planes) one 0xFF/0x00 plane per group; counts rows per group.
-template <int NGC, int NI, int DIG>
-__device__ __forceinline__ void star_planes(const MfmaArgs &a, const StarPlan &pl, const StarStage<NGC, NI> *sg,
+template <int NGC, int NI, int DIG, bool MK>
+__device__ __forceinline__ void star_planes(const MfmaArgs &a, const StarPlan &pl, const StarStage<NGC, NI, MK> *sg,
                                             uint32_t row0, bool tail, uint8_t *planes, int lane,
                                             uint32_t (&gcnt)[kStarGM], uint32_t *status) {
   constexpr int D = NI * DIG;
@@ -379,12 +402,19 @@ __device__ __forceinline__ void star_b(const uint8_t *planes, int roff, const in
 // The four K-chunks of a tile, software-pipelined: the B rows of chunk u + 1
 // are read and the A operands of chunk u + 1 built while the matrix cores
 // work on chunk u.
-template <int NT>
-__device__ __forceinline__ void star_mfma(const uint64_t (&wk)[4], const uint8_t *planes, const int (&boff_d)[NT],
-                                          const int (&boff_g)[NT], const StarTc &tc, int q, v4i (&acc)[4][NT]) {
+template <int NGC, int NI, bool MK, int NT>
+__device__ __forceinline__ void star_mfma(const uint64_t (&wk)[4], const StarStage<NGC, NI, MK> *sg, int lane,
+                                          const uint8_t *planes, const int (&boff_d)[NT], const int (&boff_g)[NT],
+                                          const StarTc &tc, int q, v4i (&acc)[4][NT]) {
+  auto word = [&](int u) -> uint64_t {
+    if constexpr (MK)
+      return sg->mk[64 * u + lane];
+    else
+      return wk[u];
+  };
   v4i av[2][4], bd[2][NT], bg[2][NT];
   star_b<NT>(planes, 16 * q, boff_d, boff_g, bd[0], bg[0]);
-  star_a(wk[0], tc, av[0]);
+  star_a(word(0), tc, av[0]);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int c = u & 1, n = c ^ 1;
@@ -396,7 +426,7 @@ __device__ __forceinline__ void star_mfma(const uint64_t (&wk)[4], const uint8_t
       for (int mt = 0; mt < 4; ++mt)
         acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[c][mt], b, acc[mt][nt], 0, 0, 0);
     }
-    if (u < 3) star_a(wk[u + 1], tc, av[n]);
+    if (u < 3) star_a(word(u + 1), tc, av[n]);
   }
 }
 
@@ -447,10 +477,12 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
                                                            uint32_t *status) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   constexpr int D = NI * DIG, A = 1 + NI;
+  constexpr bool MK = NT > 4;
+  using Stage = StarStage<NGC, NI, MK>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, p = lane & 15;
   uint8_t *planes = smem + wave * pl.wave_bytes;
-  StarStage<NGC, NI> *stage = (StarStage<NGC, NI> *)(planes + pl.stage_off);
+  Stage *stage = (Stage *)(planes + pl.stage_off);
   int64_t *blk = (int64_t *)(smem + pl.blk_off);
   const int G = pl.G;
   const int nrows_off = G * A * 64;
@@ -492,66 +524,57 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
   const uint32_t n_grp = n_full / kStarTPI;
   const uint32_t stride = gridDim.x * kStarWPB;
   const uint32_t first = blockIdx.x * kStarWPB + wave;
-  uint32_t g0 = first;
-  if (g0 < n_grp) {
+  if (first < n_grp) {
     const uint32_t last = n_grp - 1;
     auto clampg = [&](uint32_t g) { return g < n_grp ? g : last; };
     auto row_of = [&](uint32_t g, int k) { return (g * kStarTPI + k) * kTileRows; };
-    uint64_t wk[kStarTPI][4];  // A-operand words of the staged tiles
+    uint32_t gi = first;
+    uint64_t wk[kStarTPI][4];  // A-operand words of the staged tiles (registers unless MK)
 #pragma unroll
-    for (int k = 0; k < kStarTPI; ++k) {  // prologue: stage group g0
+    for (int k = 0; k < kStarTPI; ++k) {  // prologue: stage group `first`
       StarRaw<NGC, NI> r;
       QChain c;
-      qchain_first(a, row_of(g0, k), lane, c);
+      qchain_first<MK>(a, row_of(gi, k), lane, c);
       if (KV == 0) qchain_next(a, c, status);
       star_issue_words<KV>(a, c, r, status);
-      star_issue_cols(a, pl, row_of(g0, k), lane, r);
+      star_issue_cols(a, pl, row_of(gi, k), lane, r);
       star_stage_store(stage + k, lane, r);
-      star_words<KV>(a, r, wk[k]);
+      star_words<KV>(a, r, stage + k, lane, wk[k]);
     }
-    // g1: the next group (after both links), g2 the one after it (after the
-    // first link); a group >= n_grp is past the end (its loads read the last
-    // group and are never used)
-    uint32_t g1 = g0 + stride, g2 = g1 + stride;
-    QChain l1[kStarTPI], l0[kStarTPI];
+    QChain l1[kStarTPI], l0[kStarTPI];  // group + stride after both links, group + 2 stride after the first
 #pragma unroll
     for (int k = 0; k < kStarTPI; ++k) {
-      qchain_first(a, row_of(clampg(g1), k), lane, l1[k]);
+      qchain_first<MK>(a, row_of(clampg(gi + stride), k), lane, l1[k]);
       if (KV == 0) qchain_next(a, l1[k], status);
-      qchain_first(a, row_of(clampg(g2), k), lane, l0[k]);
+      qchain_first<MK>(a, row_of(clampg(gi + 2 * stride), k), lane, l0[k]);
     }
-    while (true) {
+    for (; gi < n_grp; gi += stride) {
       StarRaw<NGC, NI> r[kStarTPI];
       QChain n1[kStarTPI];
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         star_issue_words<KV>(a, l1[k], r[k], status);
-        star_issue_cols(a, pl, row_of(clampg(g1), k), lane, r[k]);
+        star_issue_cols(a, pl, row_of(clampg(gi + stride), k), lane, r[k]);
       }
-      const uint32_t g3 = g2 + stride;
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         n1[k] = l0[k];
         if (KV == 0) qchain_next(a, n1[k], status);
-        qchain_first(a, row_of(clampg(g3), k), lane, l0[k]);
+        qchain_first<MK>(a, row_of(clampg(gi + 3 * stride), k), lane, l0[k]);
       }
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
-        star_planes<NGC, NI, DIG>(a, pl, stage + k, row_of(g0, k), false, planes, lane, gcnt, status);
+        star_planes<NGC, NI, DIG>(a, pl, stage + k, row_of(gi, k), false, planes, lane, gcnt, status);
         wave_lds_fence();
-        star_mfma<NT>(wk[k], planes, boff_d, boff_g, tc, q, acc);
+        star_mfma(wk[k], stage + k, lane, planes, boff_d, boff_g, tc, q, acc);
         wave_lds_fence();
       }
-      if (g1 >= n_grp) break;
 #pragma unroll
       for (int k = 0; k < kStarTPI; ++k) {
         star_stage_store(stage + k, lane, r[k]);
-        star_words<KV>(a, r[k], wk[k]);
+        star_words<KV>(a, r[k], stage + k, lane, wk[k]);
         l1[k] = n1[k];
       }
-      g0 = g1;
-      g1 = g2;
-      g2 = g3;
     }
   }
   // tiles after the last full group (at most kStarTPI - 1 full ones and a
@@ -562,16 +585,16 @@ __global__ __launch_bounds__(64 * kStarWPB, 2) void agg_star(MfmaArgs a, StarPla
     const uint32_t row0 = T * kTileRows;
     StarRaw<NGC, NI> r;
     QChain c;
-    qchain_first_tail(a, row0, lane, c);
+    qchain_first_tail<MK>(a, row0, lane, c);
     if (KV == 0) qchain_next(a, c, status);
     star_issue_words<KV>(a, c, r, status);
     star_issue_cols_tail(a, pl, row0, lane, r);
     star_stage_store(stage, lane, r);
     uint64_t wt[4];
-    star_words<KV>(a, r, wt);
+    star_words<KV>(a, r, stage, lane, wt);
     star_planes<NGC, NI, DIG>(a, pl, stage, row0, true, planes, lane, gcnt, status);
     wave_lds_fence();
-    star_mfma<NT>(wt, planes, boff_d, boff_g, tc, q, acc);
+    star_mfma(wt, stage, lane, planes, boff_d, boff_g, tc, q, acc);
     wave_lds_fence();
   }
   star_flush<NI, DIG, NT>(acc, planes, blk, pl, lane);
@@ -646,7 +669,7 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   const int planes_bytes = p.n_planes * kPlaneStride;
   const int flush_bytes = 16 * NT * 16 * 4;
   p.stage_off = (std::max(planes_bytes, flush_bytes) + 15) & ~15;
-  const int stage_bytes = 64 * (4 * in.n_gcols + 16 * in.n_icols + 4);
+  const int stage_bytes = 64 * (4 * in.n_gcols + 16 * in.n_icols + 4) + (NT > 4 ? 256 * 8 : 8);
   p.wave_bytes = (p.stage_off + kStarTPI * stage_bytes + 15) & ~15;
   p.blk_off = kStarWPB * p.wave_bytes;
   p.blk_words = (int)G * (1 + in.n_icols) * 64 + (int)G;
@@ -664,7 +687,8 @@ bool star_supported(const DevInput &in) {
 
 template <int KV, int NGC, int NI, int DIG, int NT>
 static hipError_t launch_star_t(const LaunchEnv &env, const DevInput &in, const DevState &st, const StarPlan &pl) {
-  static_assert(sizeof(StarStage<NGC, NI>) == 64 * (4 * NGC + 16 * NI + 4), "stage");
+  static_assert(sizeof(StarStage<NGC, NI, (NT > 4)>) == 64 * (4 * NGC + 16 * NI + 4) + (NT > 4 ? 256 * 8 : 8),
+                "stage");
   const int lds = pl.blk_off + pl.blk_words * 8;
   const void *fn = (const void *)agg_star<KV, NGC, NI, DIG, NT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -153,9 +153,11 @@ def test_star_kernel_shapes(ctx, gcards, n_cols):
     compare_counters(got, star_definition(t, 0x5151, 64, int_cols=ints))
 
 
-@pytest.mark.parametrize("gcards,n_cols,balanced", [((3, 2), 3, False), ((2, 4), 2, True), ((1, 1), 1, False)])
+@pytest.mark.parametrize("gcards,n_cols,balanced", [((3, 2), 3, False), ((2, 4), 2, True), ((1, 1), 1, False),
+                                                    ((4, 2), 3, False)])
 def test_star_kernel_key_valued_orders(ctx, gcards, n_cols, balanced):
-    """The orders carry their PU key: one FK link, the key hashed per row in the kernel."""
+    """The orders carry their PU key: one FK link, the key hashed per row in the kernel.  8 groups with 3
+    columns need six column tiles, the variant that stages the PU words in LDS."""
     from cases import gpu_star_kv
     t = gen.tiny_star(60 + n_cols, n_pu=700, n_orders=4000, n_rows=256 * 41 + 77, gcards=gcards, n_cols=n_cols,
                       value_range=(-6_000_000, 6_000_000))
@@ -167,7 +169,7 @@ def test_star_kernel_key_valued_orders(ctx, gcards, n_cols, balanced):
     compare_counters(got, star_definition(t, 0x77AA, 64, int_cols=ints, balanced=balanced))
 
 
-@pytest.mark.parametrize("gcards,n_cols", [((3, 2), 3), ((2, 4), 1), ((1, 1), 2)])
+@pytest.mark.parametrize("gcards,n_cols", [((3, 2), 3), ((2, 4), 1), ((1, 1), 2), ((2, 4), 3)])
 def test_star_kernel_per_order_words(ctx, torch_mod, gcards, n_cols):
     """The orders' PU keys hashed once into per-order words (pac_hash_mask of the orders' keys), then one FK
     link from the fact rows into those words: the same counters as following both links."""
