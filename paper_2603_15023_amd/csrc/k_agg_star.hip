@@ -77,9 +77,9 @@ __device__ __forceinline__ uint32_t wrow(int lane, int u) {
 // (wrow(lane, 0..3), or qrow(lane, 0..3) with MK): table indices and
 // validity.  Every load is unconditional: an invalid row reads index 0 of the
 // (non-empty) table and stays marked invalid; a foreign key outside its
-// table also raises PAC_STATUS_BAD_LINK.  The words found at the end of the
-// chain stay in the lane's registers, already in the order of the A operand
-// (no staging through LDS).
+// table also raises PAC_STATUS_BAD_LINK.  Without MK the words found at the
+// end of the chain stay in the lane's registers, already in the order of the
+// A operand (no staging through LDS).
 struct QChain {
   uint32_t idx[4];
   uint32_t ok[4];
@@ -665,6 +665,8 @@ static bool star_plan(const DevInput &in, StarPlan *pl, int *nt_out) {
   int NT = ((int)G * (D + 1) + 15) / 16;
   if (NT == 5) NT = 6;
   if (NT > 6) return false;
+  // six tiles: full tiles read the first link in 8-byte loads
+  if (NT > 4 && ((uintptr_t)in.links[0] & 7u)) return false;
   p.n_planes = D + 3 + (int)G;  // digits, ones, zeros, G groups, one spare
   const int planes_bytes = p.n_planes * kPlaneStride;
   const int flush_bytes = 16 * NT * 16 * 4;

@@ -46,6 +46,34 @@ static hipError_t launch_fill(const LaunchEnv &env, T *p, int64_t n, T v) {
 
 hipError_t launch_fill_i64(const LaunchEnv &env, int64_t *p, int64_t n, int64_t v) { return launch_fill(env, p, n, v); }
 
+// Several fills in one launch: grid row y sets segment y's n[y] 64-bit words
+// at p[y] to the bit pattern v[y].
+__global__ __launch_bounds__(256) void fill_multi_kernel(FillSegs f) {
+  const int s = blockIdx.y;
+  int64_t *p = f.p[s];
+  const int64_t n = f.n[s], v = f.v[s];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_multi(const LaunchEnv &env, const FillSegs &in) {
+  FillSegs f{};
+  int64_t max_n = 0;
+  for (int i = 0; i < in.count && i < kMaxFillSegs; ++i) {  // empty segments dropped
+    if (in.n[i] <= 0 || !in.p[i]) continue;
+    f.p[f.count] = in.p[i];
+    f.n[f.count] = in.n[i];
+    f.v[f.count] = in.v[i];
+    max_n = in.n[i] > max_n ? in.n[i] : max_n;
+    ++f.count;
+  }
+  if (f.count == 0) return hipSuccess;
+  const int64_t need = (max_n + 255) / 256, cap = (int64_t)env.n_cu * 8 / f.count;
+  const int blocks = (int)(need < cap ? need : (cap > 0 ? cap : 1));
+  hipLaunchKernelGGL(fill_multi_kernel, dim3(blocks, f.count), dim3(256), 0, env.stream, f);
+  return hipGetLastError();
+}
+
 // Occupied slots of a sparse-key table: per-wave ballot counts, summed per
 // workgroup in LDS, one atomic add per workgroup (n_used cleared first).
 __global__ __launch_bounds__(256) void count_used_kernel(const int64_t *slot_keys, int64_t cap, int64_t *n_used) {

@@ -301,16 +301,29 @@ uint32_t choose_algo(const pac::DevInput &d, const pac::DevState &ds) {
 // work can be captured in a graph); the sparse table emptied.
 int init_state(const pac::LaunchEnv &env, const pac::DevInput &d, const pac::DevState &ds) {
   const int64_t G = d.n_groups, m = d.m;
-  hipError_t e = pac::launch_fill_i64(env, ds.count, G * m, 0);
-  if (e == hipSuccess && ds.isum) e = pac::launch_fill_i64(env, ds.isum, G * d.n_icols * m, 0);
-  if (e == hipSuccess && ds.fsum) e = pac::launch_fill_f64(env, ds.fsum, G * d.n_fcols * m, 0.0);
-  if (e == hipSuccess) e = pac::launch_fill_i64(env, ds.nrows, G, 0);
-  if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.slot_keys, G, PAC_EMPTY_KEY);
-  if (e == hipSuccess && d.group_keys) e = pac::launch_fill_i64(env, ds.n_used, 1, 0);
-  if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imin, G * d.n_icols * m, INT64_MAX);
-  if (e == hipSuccess && ds.minmax && d.n_icols > 0) e = pac::launch_fill_i64(env, ds.imax, G * d.n_icols * m, INT64_MIN);
-  if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmin, G * d.n_fcols * m, INFINITY);
-  if (e == hipSuccess && ds.minmax && d.n_fcols > 0) e = pac::launch_fill_f64(env, ds.fmax, G * d.n_fcols * m, -INFINITY);
+  pac::FillSegs f{};
+  auto add = [&](void *p, int64_t n, int64_t bits) {
+    f.p[f.count] = (int64_t *)p;
+    f.n[f.count] = n;
+    f.v[f.count] = bits;
+    ++f.count;
+  };
+  auto dbits = [](double x) {
+    int64_t b;
+    std::memcpy(&b, &x, sizeof b);
+    return b;
+  };
+  add(ds.count, G * m, 0);
+  if (ds.isum) add(ds.isum, G * d.n_icols * m, 0);
+  if (ds.fsum) add(ds.fsum, G * d.n_fcols * m, dbits(0.0));
+  add(ds.nrows, G, 0);
+  if (d.group_keys) add(ds.slot_keys, G, PAC_EMPTY_KEY);
+  if (d.group_keys) add(ds.n_used, 1, 0);
+  if (ds.minmax && d.n_icols > 0) add(ds.imin, G * d.n_icols * m, INT64_MAX);
+  if (ds.minmax && d.n_icols > 0) add(ds.imax, G * d.n_icols * m, INT64_MIN);
+  if (ds.minmax && d.n_fcols > 0) add(ds.fmin, G * d.n_fcols * m, dbits(INFINITY));
+  if (ds.minmax && d.n_fcols > 0) add(ds.fmax, G * d.n_fcols * m, dbits(-INFINITY));
+  const hipError_t e = pac::launch_fill_multi(env, f);  // one launch for every array
   if (e != hipSuccess) return hip_fail(e, "state init");
   return PAC_OK;
 }

@@ -252,6 +252,16 @@ hipError_t launch_hash(const LaunchEnv &env, const int64_t *keys, int64_t n, uin
                        uint64_t *out);
 hipError_t launch_fill_i64(const LaunchEnv &env, int64_t *p, int64_t n, int64_t v);
 hipError_t launch_fill_f64(const LaunchEnv &env, double *p, int64_t n, double v);
+// Up to kMaxFillSegs arrays of 64-bit words, each set to one bit pattern, in
+// one launch (empty or null segments are skipped).
+constexpr int kMaxFillSegs = 12;
+struct FillSegs {
+  int64_t *p[kMaxFillSegs];
+  int64_t n[kMaxFillSegs];
+  int64_t v[kMaxFillSegs];
+  int count;
+};
+hipError_t launch_fill_multi(const LaunchEnv &env, const FillSegs &f);
 // n_used = the number of occupied (non-EMPTY) slots of a sparse-key table.
 hipError_t launch_count_used(const LaunchEnv &env, const int64_t *slot_keys, int64_t cap, int64_t *n_used);
 hipError_t launch_agg_plain(const LaunchEnv &env, const DevInput &in, const DevState &st, void *scratch,
